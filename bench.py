@@ -1,0 +1,197 @@
+"""Benchmark of the Lindhard hot path on one MI355X.
+
+Workload: 2048 x 2048 k-grid, 512 energy points on [-2, 2] eV, G = 0.01 eV,
+256 omegas in (0, 2] eV, seeded t-t'-t'' band, filling 1.15, FP32 with the
+compensated energy window.  One step = one lindhard_exec: the whole hot path
+(spectral builder + row FFT, column FFT, energy window, inverse column FFT,
+inverse row FFT + epilogue) with the band, twiddles and workspace resident in
+HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PASS_NAMES = ["p1_build_rowfft", "p2_colfft", "p3_window", "p4_colifft", "p5_rowifft_epilogue"]
+KERNEL_NAMES = ["k_p1", "k_col<float, false>", "k_p3", "k_col<float, true>", "k_p5"]
+
+
+def algorithmic(cfg, info_lag_hi, fp_bytes=4):
+    """Algorithmic HBM bytes and flops per pass for one exec (FP32 sizes)."""
+    n_x, n_y, neps = cfg["nkx"], cfg["nky"], cfg["neps"]
+    nw = len(cfg["omega"])
+    half = (n_x // 2 + 1) * n_y  # complex half-spectrum points per slice
+    cb = 2 * fp_bytes
+    nS = neps  # every slice enters the window at this workload
+    nL = info_lag_hi
+    B = half * nS * cb
+    S = half * nL * cb
+    out = n_x * n_y * nw * fp_bytes
+    by = [B, 2 * B, B + S, 2 * S, S + out]
+    # energy window: per real-space point sum over lags of the window length
+    j0 = neps // 2
+    cmacs = sum(min(m, j0, neps - m) for m in range(1, nL + 1))
+    fl_win = 8.0 * half * cmacs  # complex MAC = 4 mul + 4 add
+    return by, fl_win
+
+
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM traffic of the window pass from committed rocprofv3 counter runs,
+    only if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_p3_2048x2048x512.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_src_hash") != kernel_src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(cfg, nsamples=32):
+    import oracle
+
+    eps = oracle.band_tb(cfg["t"], cfg["tp"], cfg["tpp"], cfg["nkx"], cfg["nky"])
+    mu = oracle.mu_solve(eps, cfg["gamma"], cfg["filling"])
+    xi = eps - mu
+    rng = np.random.Generator(np.random.PCG64(77))
+    n = cfg["nkx"]
+    nlag = len(cfg["omega"])
+    qx = rng.integers(0, n, nsamples)
+    qy = rng.integers(0, n, nsamples)
+    ms = rng.integers(1, nlag + 1, nsamples)
+    t0 = time.perf_counter()
+    oracle.chi_pairs(xi, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], qx, qy, ms)
+    dt = time.perf_counter() - t0
+    return {"value": nsamples / dt, "unit": "chi(q,w) points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d (q, omega) points of the 2048^2 k x 512 energy workload, q uniform, lag uniform in "
+                      "1..%d, FP64 direct double sum; %.1f s wall" % (nsamples, nlag, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--nk", type=int, default=2048)
+    ap.add_argument("--neps", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported (got --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1208_3210_amd import lindhard as LH
+    from paper_1208_3210_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.config3(nk=args.nk, neps=args.neps)
+    print("bench: planning %dx%d k, %d energies, %d omegas" % (cfg["nkx"], cfg["nky"], cfg["neps"],
+                                                             len(cfg["omega"])), file=sys.stderr, flush=True)
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    out = plan.empty()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.exec_timed(out)
+    torch.cuda.synchronize()
+    step_ms, pass_ms = [], []
+    t_start = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        p = plan.exec_timed(out)
+        pass_ms.append(p)
+        step_ms.append(sum(p))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_start) * 1e3
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    points = cfg["nkx"] * cfg["nky"] * len(cfg["omega"])
+    value = points / (ms_per_step * 1e-3)
+    pass_avg = np.mean(np.array(pass_ms), axis=0)
+    print("bench: %.3f ms/step (wall %.3f), passes %s" % (ms_per_step, wall_ms / args.steps,
+                                                        ", ".join("%.3f" % x for x in pass_avg)),
+          file=sys.stderr, flush=True)
+
+    by, fl_win = algorithmic(cfg, plan.info.lag_hi)
+    gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, pass_avg)]
+    dom = int(np.argmax(pass_avg))
+    src = [os.path.join(ROOT, "paper_1208_3210_amd", "csrc", f) for f in ("lh_kernels.hip", "lh_fft.h")]
+    khash = src_hash(src)
+    if dom == 2:
+        ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
+        roof = {"kernel": KERNEL_NAMES[2], "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+                "traffic": traffic_from_profiles(khash)}
+    else:
+        roof = {"kernel": KERNEL_NAMES[dom], "bound": "hbm", "achieved": gbs[dom], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM_GBS, "traffic": None}
+    roof["avg_ms"] = float(pass_avg[dom])
+    passes = {n: {"ms": float(t), "alg_GB": b / 1e9, "GB/s": g} for n, t, b, g in zip(PASS_NAMES, pass_avg, by, gbs)}
+    passes["p3_window"]["TFLOP/s"] = fl_win / (pass_avg[2] * 1e-3) / 1e12
+    lat = np.array(step_ms)
+
+    # plain FP64 GPU form on the same workload, and the FP32 vs FP64 error
+    fp64 = None
+    if not args.no_fp64:
+        del out
+        plan.close()
+        plan64 = LH.Plan(precision=LH.LINDHARD_FP64, **cfg)
+        o64 = plan64.empty()
+        plan64.exec_timed(o64)
+        t64 = [sum(plan64.exec_timed(o64)) for _ in range(3)]
+        ms64 = float(np.mean(t64))
+        plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+        o32 = plan.exec()
+        torch.cuda.synchronize()
+        diff = (o32.double() - o64).abs()
+        err = diff.max().item() / o64.abs().max().item()
+        per_slice = (diff.amax(dim=(1, 2)) / o64.abs().amax(dim=(1, 2))).max().item()
+        fp64 = {"ms_per_step": ms64, "value": points / (ms64 * 1e-3), "fp32c_speedup": ms64 / ms_per_step,
+                "fp32c_vs_fp64_normwise": err, "fp32c_vs_fp64_worst_slice": per_slice}
+        del o64, o32, diff
+        plan64.close()
+    plan.close()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
+    res = {
+        "metric": "chi(q,w) points/s at 2048^2 k x 512 eps, FP32 vs FP64 at <=1e-5 rel",
+        "value": value, "unit": "chi(q,w) points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded t-t'-t'' band, seed 12083210)",
+        "config": {"workload": "lindhard_2048x2048k_512eps_256w_fp32c", "nkx": cfg["nkx"], "nky": cfg["nky"],
+                   "neps": cfg["neps"], "nomega": len(cfg["omega"]), "gamma_eV": cfg["gamma"],
+                   "points_per_step": points, "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "roofline": roof, "passes": passes, "fp64_gpu": fp64, "cpu_baseline": cpu,
+        "kernel_src_hash": khash,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * lindhard.h -- C ABI of the MI355X (gfx950) library for the bare Lindhard
+ * susceptibility, its extended-zone form factor, Kramers-Kronig real part and
+ * RPA, computed as products of real-space spectral functions plus FFTs
+ * (Wang et al., arXiv:1208.3210, Sec. 3 with Eqs. (9)-(10); RPA and
+ * Kramers-Kronig in Sec. 4).
+ *
+ * What one plan computes (all quantities per site and per spin, eV^-1):
+ *
+ *   k-grid     k = 2 pi (ix / nkx, iy / nky), periodic first Brillouin zone.
+ *   band       eps(k) = -2t(cos kx + cos ky) - 4t' cos kx cos ky
+ *                       - 2t''(cos 2kx + cos 2ky)            (or a caller table)
+ *   mu         given, or solved from the filling (rigid band, Sec. 3) with
+ *              n(mu) = (2/Nk) sum_k [1/2 + atan((mu - eps_k)/gamma)/pi].
+ *   energies   d = (emax - emin)/neps, e_j = emin + (j + 1/2) d; e_j <= 0 occupied.
+ *   A(k, j)    = (gamma/pi) / ((e_j - (eps_k - mu))^2 + gamma^2)   -- Eq. (5)
+ *   Im chi_1BZ(q, m) = -(d/Nk) sum_k sum_{j occupied, j+m unoccupied, j+m < neps}
+ *                       A(k, j) A(k+q, j+m)                  -- Eqs. (2), (9), (A3)
+ *              at omega = m d; exactly 0 for m = 0 and m >= neps.
+ *   extended   out(Q = q + G) = |M(Q)|^2 Im chi_1BZ(q), |M|^2 = F(Q)^2 with the
+ *              on-site matrix element of Eq. (3) for a d_{x2-y2}-like Gaussian
+ *              orbital: F(Q) = exp(-s|Q|^2)[1 - 2s|Q|^2 + s^2(Qx^2-Qy^2)^2],
+ *              s = w^2/4 (ff_kind = LINDHARD_FF_GAUSS_DX2Y2), or 1 (FF_NONE).
+ *   Re chi     Kramers-Kronig (Sec. 4), alternate-point rule over all lags:
+ *              Re(i) = (2/pi) sum_{j=1..neps-1, j-i odd} Im(j) 2j/(j^2 - i^2).
+ *   RPA        chi_RPA = chi / (1 - U chi) on the extended chi (Sec. 4).
+ *
+ * Output layout: float (LINDHARD_FP32C) or double (LINDHARD_FP64) arrays
+ * [nomega][zones_y * nky][zones_x * nkx], row major.  Column X of the extended
+ * map is h = (X - zones_x*nkx/2)/nkx reciprocal-lattice units, first-zone index
+ * u = (X - zones_x*nkx/2) mod nkx (the same for rows): the maps are Gamma
+ * centred.  Output buffers are device memory owned by the caller.
+ *
+ * Streams are passed as `void *` holding a hipStream_t (NULL = the default
+ * stream).  No function throws; every function returns a lindhard_status.
+ * Outputs are written only when a call returns LINDHARD_OK.
+ */
+#ifndef LINDHARD_H
+#define LINDHARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LINDHARD_OK = 0,
+    LINDHARD_EINVAL = -1,    /* invalid argument or problem description */
+    LINDHARD_EOFFGRID = -2,  /* an omega is not m * d (within 1e-9 d) with m >= 0 */
+    LINDHARD_ENOMEM = -3,    /* device or host allocation failed */
+    LINDHARD_ETOOBIG = -4,   /* job footprint exceeds the server's HBM budget */
+    LINDHARD_EBUSY = -5,     /* server queue full */
+    LINDHARD_EDEVICE = -6,   /* a HIP runtime call or kernel launch failed */
+    LINDHARD_ENOCONV = -7,   /* chemical-potential solve did not converge */
+    LINDHARD_ECANCELED = -8, /* served job was cancelled */
+    LINDHARD_ESTATE = -9     /* call out of order (e.g. rpa without want_rpa) */
+} lindhard_status;
+
+typedef enum {
+    LINDHARD_FP32C = 1, /* FP32 FFTs and products, compensated energy-window sums */
+    LINDHARD_FP64 = 2   /* FP64 throughout */
+} lindhard_precision;
+
+typedef enum {
+    LINDHARD_FF_NONE = 0,       /* |M|^2 = 1: extended zones repeat the first zone */
+    LINDHARD_FF_GAUSS_DX2Y2 = 1 /* Gaussian d_{x2-y2}-like orbital of width ff_width */
+} lindhard_ff;
+
+typedef struct {
+    double t, tp, tpp;          /* eV, tight-binding hoppings (ignored if eps_table) */
+    const double *eps_table;    /* optional host table eps[iy][ix] (x fastest), eV;
+                                   read only during lindhard_plan */
+    double mu;                  /* eV; NaN = solve from `filling` */
+    double filling;             /* electrons per site, both spins (1 + x) */
+    double gamma;               /* Lorentzian half width of Eq. (5), eV, > 0 */
+    int32_t nkx, nky;           /* powers of two, 4 .. 2048 */
+    int32_t neps;               /* power of two, 4 .. 2048 */
+    double emin, emax;          /* energy window, emin < 0 < emax */
+    int32_t nomega;             /* number of requested omegas, 1 .. 65536 */
+    const double *omega;        /* host array of omegas, eV; each m*d, m >= 0 */
+    int32_t zones_x, zones_y;   /* odd, >= 1, zones_x*nkx and zones_y*nky <= 65536 */
+    int32_t ff_kind;            /* lindhard_ff */
+    double ff_width;            /* orbital width w in lattice constants (> 0 if used) */
+    int32_t precision;          /* lindhard_precision */
+    int32_t want_rpa;           /* nonzero: keep every lag for lindhard_rpa */
+} lindhard_problem;
+
+typedef struct lindhard_plan_s *lindhard_plan_t;
+
+typedef struct {
+    double mu;                /* chemical potential used, eV */
+    double deps;              /* energy step d, eV */
+    int32_t j0;               /* number of occupied energy points */
+    int32_t out_nx, out_ny;   /* zones_x*nkx, zones_y*nky */
+    int32_t nomega;
+    int32_t lag_lo, lag_hi;   /* lag range the energy-window pass computes (0,0 = none) */
+    int32_t mu_iterations;    /* Newton/bisection steps of the mu solve (0 if given) */
+    size_t workspace_bytes;   /* device bytes the plan holds */
+    size_t out_elems;         /* elements of each output array */
+    size_t elem_bytes;        /* 4 (FP32C) or 8 (FP64) */
+    char schedule[96];        /* human-readable pass schedule */
+} lindhard_info;
+
+/* Validate `p`, build the band on the device, solve mu, build twiddle and
+ * form-factor tables and allocate the device workspace (owned by the plan).
+ * Synchronous.  Errors: EINVAL, EOFFGRID, ENOMEM, EDEVICE, ENOCONV. */
+lindhard_status lindhard_plan(const lindhard_problem *p, lindhard_plan_t *out);
+
+/* Copy the plan's derived quantities into *info.  EINVAL on NULL. */
+lindhard_status lindhard_plan_info(lindhard_plan_t plan, lindhard_info *info);
+
+/* Enqueue the whole hot path on `stream`: spectral builder + row FFT, column
+ * FFT, energy-window product, inverse column FFT, inverse row FFT + scale +
+ * form factor + zone writes into `im_chi` (device, out_elems elements of the
+ * plan's precision).  Asynchronous; a plan is used by one stream at a time.
+ * Errors: EINVAL (NULL), EDEVICE (launch failure). */
+lindhard_status lindhard_exec(lindhard_plan_t plan, void *im_chi, void *stream);
+
+/* lindhard_exec with per-pass timing: records HIP events on `stream` around
+ * the five passes (P1 spectral builder + row FFT, P2 column FFT, P3 energy
+ * window, P4 inverse column FFT, P5 inverse row FFT + epilogue), waits for
+ * the last one and writes the five durations in milliseconds to pass_ms[0..4]
+ * (host array).  Synchronous.  Errors: EINVAL, EDEVICE. */
+lindhard_status lindhard_exec_timed(lindhard_plan_t plan, void *im_chi, void *stream, float *pass_ms);
+
+/* After lindhard_exec on a plan built with want_rpa: Kramers-Kronig real part
+ * and RPA with constant U (eV) into three more device arrays of the same layout:
+ * re_chi = Re chi_ext, im_rpa / re_rpa = Im / Re of chi_ext / (1 - U chi_ext).
+ * Any of the three pointers may be NULL to skip that output.
+ * Errors: EINVAL, ESTATE (plan without want_rpa), EDEVICE. */
+lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void *im_rpa,
+                             void *re_rpa, void *stream);
+
+/* Run n plans on one stream: every pass is launched once for all instances
+ * (grouped launches over mixed grid sizes).  outs[i] as in lindhard_exec.
+ * All plans must have the same precision.  Errors: EINVAL, EDEVICE. */
+lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs,
+                                    void *stream);
+
+/* Free the plan and its device workspace (waits for its work to finish). */
+lindhard_status lindhard_plan_destroy(lindhard_plan_t plan);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct {
+    size_t hbm_budget_bytes; /* admission limit on the sum of in-flight workspaces */
+    int32_t max_inflight;    /* concurrent jobs on the device (>= 1) */
+    int32_t max_queue;       /* queued (not yet admitted) jobs (>= 1) */
+} lindhard_serve_config;
+
+typedef struct lindhard_server_s *lindhard_server_t;
+
+typedef struct {
+    uint64_t submitted, completed, failed, rejected, canceled;
+    double p50_ms, p99_ms;   /* submit -> result-ready latency of completed jobs */
+    double points_per_s;     /* output points of completed jobs / wall time since create */
+    size_t hbm_high_water;   /* largest sum of admitted workspaces seen */
+    int32_t queue_depth, inflight;
+} lindhard_serve_stats;
+
+/* Start a server: a host admission thread that admits queued jobs while the
+ * sum of their workspaces stays within the budget and a slot is free, and runs
+ * each admitted job (plan, exec, optional rpa) on a stream of its own so that
+ * jobs overlap on the device.  Errors: EINVAL, ENOMEM, EDEVICE. */
+lindhard_status lindhard_serve_create(const lindhard_serve_config *cfg, lindhard_server_t *out);
+
+/* Queue one job.  The problem (and its omega / eps_table arrays) is copied.
+ * Outputs are device buffers as in lindhard_exec / lindhard_rpa; pass
+ * U_or_nan = NaN (and NULL re/rpa buffers) for no RPA.  *ticket identifies the
+ * job.  Errors: EINVAL / EOFFGRID (problem invalid), ETOOBIG (footprint over
+ * the budget), EBUSY (queue full). */
+lindhard_status lindhard_serve_submit(lindhard_server_t s, const lindhard_problem *p,
+                                      double U_or_nan, void *im_chi, void *re_chi, void *im_rpa,
+                                      void *re_rpa, uint64_t *ticket);
+
+/* Non-blocking completion check: *done = 1 when finished (then *job_status is
+ * the job's own status). */
+lindhard_status lindhard_serve_poll(lindhard_server_t s, uint64_t ticket, int32_t *done,
+                                    lindhard_status *job_status);
+
+/* Block until the job finishes or timeout_s passes (EBUSY on timeout). */
+lindhard_status lindhard_serve_wait(lindhard_server_t s, uint64_t ticket, double timeout_s,
+                                    lindhard_status *job_status);
+
+/* Cancel a job that has not been admitted yet (its status becomes ECANCELED).
+ * A job already running or finished is left alone and EBUSY is returned.
+ * EINVAL for an unknown ticket. */
+lindhard_status lindhard_serve_cancel(lindhard_server_t s, uint64_t ticket);
+
+lindhard_status lindhard_serve_stats_get(lindhard_server_t s, lindhard_serve_stats *out);
+
+/* Drain queued and in-flight jobs, stop the admission thread, free all. */
+lindhard_status lindhard_serve_destroy(lindhard_server_t s);
+
+/* Static description of a status code. */
+const char *lindhard_strerror(lindhard_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINDHARD_H */

@@ -132,15 +132,22 @@ static inline double lorentz(double e, double xi, double gamma)
 }
 
 /* Sum over k of the energy-window product for one q and a list of lags.
- * acc[im] receives sum_k sum_j A(k, j) A(k+q, j+m_im) (not yet scaled). */
+ * acc[im] receives sum_k sum_j A(k, j) A(k+q, j+m_im) (not yet scaled).
+ * Only the energy points that some requested lag can reach are evaluated:
+ * occupied j >= j0 - max(m) for A(k, j), unoccupied j < j0 + max(m) for
+ * A(k+q, j). */
 static void chi_one_q(const double *xi, int nkx, int nky, int neps, double emin, double d, int j0,
                       double gamma, int qx, int qy, int nm, const int *ms, double *acc, double *arow,
                       double *brow, nsum *sums)
 {
+    int mmax = 0;
     for (int im = 0; im < nm; ++im) {
         sums[im].s = 0.0;
         sums[im].c = 0.0;
+        if (ms[im] > mmax) mmax = ms[im];
     }
+    int alo = j0 - mmax > 0 ? j0 - mmax : 0;
+    int bhi = j0 + mmax < neps ? j0 + mmax : neps;
     int qxm = ((qx % nkx) + nkx) % nkx, qym = ((qy % nky) + nky) % nky;
     for (int iy = 0; iy < nky; ++iy) {
         int iy2 = (iy + qym) % nky;
@@ -148,11 +155,10 @@ static void chi_one_q(const double *xi, int nkx, int nky, int neps, double emin,
             int ix2 = (ix + qxm) % nkx;
             double xa = xi[(size_t)iy * nkx + ix];
             double xb = xi[(size_t)iy2 * nkx + ix2];
-            for (int j = 0; j < neps; ++j) {
-                double e = emin + (j + 0.5) * d;
-                arow[j] = lorentz(e, xa, gamma);
-                brow[j] = lorentz(e, xb, gamma);
-            }
+            for (int j = alo; j < j0; ++j)
+                arow[j] = lorentz(emin + (j + 0.5) * d, xa, gamma);
+            for (int j = j0; j < bhi; ++j)
+                brow[j] = lorentz(emin + (j + 0.5) * d, xb, gamma);
             for (int im = 0; im < nm; ++im) {
                 int m = ms[im];
                 int jlo = j0 - m > 0 ? j0 - m : 0;

@@ -1,0 +1,464 @@
+// lh_api.hip -- C ABI entry points: validation, planning (band, chemical
+// potential, tables, workspace) and execution.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lh_internal.h"
+
+namespace lh {
+
+static bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+static int ilog2(long v)
+{
+    int r = 0;
+    while ((1L << r) < v) ++r;
+    return r;
+}
+
+// Cell-centred energy grid of the window (emin, emax]: j0 = #{e_j <= 0}.
+static int count_occupied(int neps, double emin, double emax)
+{
+    const double d = (emax - emin) / neps;
+    int j0 = 0;
+    for (int j = 0; j < neps; ++j)
+        if (emin + (j + 0.5) * d <= 0.0) ++j0;
+    return j0;
+}
+
+lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
+{
+    if (!p) return LINDHARD_EINVAL;
+    if (p->precision != LINDHARD_FP32C && p->precision != LINDHARD_FP64) return LINDHARD_EINVAL;
+    if (!is_pow2(p->nkx) || !is_pow2(p->nky) || p->nkx < 4 || p->nky < 4 || p->nkx > 2048 || p->nky > 2048)
+        return LINDHARD_EINVAL;
+    if (!is_pow2(p->neps) || p->neps < 4 || p->neps > 2048) return LINDHARD_EINVAL;
+    if (!std::isfinite(p->emin) || !std::isfinite(p->emax) || !(p->emin < 0.0) || !(p->emax > 0.0))
+        return LINDHARD_EINVAL;
+    if (!std::isfinite(p->gamma) || !(p->gamma > 0.0)) return LINDHARD_EINVAL;
+    if (p->nomega < 1 || p->nomega > 65535 || !p->omega) return LINDHARD_EINVAL;
+    if (p->zones_x < 1 || p->zones_y < 1 || !(p->zones_x & 1) || !(p->zones_y & 1)) return LINDHARD_EINVAL;
+    if ((long)p->zones_x * p->nkx > 65536 || (long)p->zones_y * p->nky > 65535) return LINDHARD_EINVAL;
+    if (p->ff_kind != LINDHARD_FF_NONE && p->ff_kind != LINDHARD_FF_GAUSS_DX2Y2) return LINDHARD_EINVAL;
+    if (p->ff_kind == LINDHARD_FF_GAUSS_DX2Y2 && (!std::isfinite(p->ff_width) || !(p->ff_width > 0.0)))
+        return LINDHARD_EINVAL;
+    if (std::isnan(p->mu)) {
+        if (!std::isfinite(p->filling) || !(p->filling > 0.0) || !(p->filling < 2.0)) return LINDHARD_EINVAL;
+    } else if (!std::isfinite(p->mu)) {
+        return LINDHARD_EINVAL;
+    }
+    const long nk = (long)p->nkx * p->nky;
+    if (p->eps_table) {
+        for (long k = 0; k < nk; ++k)
+            if (!std::isfinite(p->eps_table[k])) return LINDHARD_EINVAL;
+    } else if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->tpp)) {
+        return LINDHARD_EINVAL;
+    }
+
+    pl.p = *p;
+    pl.p.omega = nullptr;
+    pl.p.eps_table = nullptr;
+    pl.omega.assign(p->omega, p->omega + p->nomega);
+    pl.deps = (p->emax - p->emin) / p->neps;
+    Geo &g = pl.g;
+    g = Geo{};
+    g.fp64 = p->precision == LINDHARD_FP64;
+    g.nkx = p->nkx;
+    g.nky = p->nky;
+    g.logNx = ilog2(p->nkx);
+    g.logNy = ilog2(p->nky);
+    g.L = p->nkx / 2;
+    g.logL = g.logNx - 1;
+    g.C = g.fp64 ? 2 : 4;
+    g.logC = ilog2(g.C);
+    g.NT = g.L / g.C + 1;
+    g.neps = p->neps;
+    g.j0 = count_occupied(p->neps, p->emin, p->emax);
+
+    // omega -> lag m (omega = m d within 1e-9 d, m >= 0)
+    pl.lag.resize(p->nomega);
+    int mlo = INT_MAX, mhi = -1;
+    for (int w = 0; w < p->nomega; ++w) {
+        const double om = p->omega[w];
+        if (!std::isfinite(om)) return LINDHARD_EOFFGRID;
+        const double r = om / pl.deps;
+        if (r < -0.5 || r > (double)INT_MAX / 2) return LINDHARD_EOFFGRID;
+        const long m = std::lround(r);
+        if (m < 0 || std::fabs(om - (double)m * pl.deps) > 1e-9 * pl.deps) return LINDHARD_EOFFGRID;
+        pl.lag[w] = (int)m;
+        if (m >= 1 && m < p->neps) {
+            mlo = std::min(mlo, (int)m);
+            mhi = std::max(mhi, (int)m);
+        }
+    }
+    if (p->want_rpa) {
+        mlo = 1;
+        mhi = p->neps - 1;
+    }
+    if (mhi >= mlo) {
+        g.m_lo = mlo;
+        g.m_hi = mhi;
+        g.nL = mhi - mlo + 1;
+        g.jA = std::max(0, g.j0 - mhi);
+        g.jB = std::min(p->neps, g.j0 + mhi);
+        g.nS = g.jB - g.jA;
+    } else {
+        g.m_lo = g.m_hi = 0;
+        g.nL = 0;
+        g.jA = g.jB = g.nS = 0;
+    }
+    g.nslots = std::max(g.nS, g.nL);
+    g.slice_elems = (size_t)g.NT * g.nky * g.C;
+    pl.slot.resize(p->nomega);
+    for (int w = 0; w < p->nomega; ++w) {
+        const int m = pl.lag[w];
+        pl.slot[w] = (g.nL > 0 && m >= g.m_lo && m <= g.m_hi) ? m - g.m_lo : -1;
+    }
+
+    // launch shapes
+    const size_t cs = g.fp64 ? 16 : 8;
+    g.p1_R = std::min(p->nky, std::max(1, 4096 / g.L));
+    g.p1_logR = ilog2(g.p1_R);
+    {
+        const long gx = p->nky / g.p1_R;
+        long jc = (gx * std::max(g.nS, 1)) / 4096;
+        g.p1_jc = (int)std::max(1L, std::min(16L, jc));
+    }
+    {
+        int TR = 32;
+        while (TR > g.C && (size_t)std::max(g.nS, 1) * TR * cs > 65536) TR >>= 1;
+        TR = std::min(TR, g.C * p->nky);
+        g.p3_TR = TR;
+        g.p3_logTR = ilog2(TR);
+        g.p3_RY = TR / g.C;
+        g.p3_logRY = ilog2(g.p3_RY);
+    }
+    {
+        // P5 stages (2L + 1) * R complex values in LDS (<= 64 KiB)
+        int R = 1;
+        while (R * 2 <= p->nky && (size_t)(2 * g.L + 1) * (R * 2) * cs <= 65536) R *= 2;
+        g.p5_R = R;
+        g.p5_logR = ilog2(R);
+    }
+
+    pl.zx = p->zones_x;
+    pl.zy = p->zones_y;
+    pl.out_nx = p->zones_x * p->nkx;
+    pl.out_ny = p->zones_y * p->nky;
+    pl.out_elems = (size_t)p->nomega * pl.out_nx * pl.out_ny;
+    pl.elem_bytes = g.fp64 ? 8 : 4;
+    pl.scale = -pl.deps / ((double)nk * (double)nk);
+    pl.ff_s = p->ff_kind == LINDHARD_FF_GAUSS_DX2Y2 ? p->ff_width * p->ff_width / 4.0 : 0.0;
+    pl.ws_bytes = plan_footprint(pl);
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 TR%d P5 R%d%s",
+                  g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.p1_R, g.p1_jc, g.p3_TR, g.p5_R,
+                  p->want_rpa ? " +kk/rpa" : "");
+    pl.schedule = buf;
+    return LINDHARD_OK;
+}
+
+size_t plan_footprint(const Plan &pl)
+{
+    const Geo &g = pl.g;
+    const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
+    const size_t nk = (size_t)g.nkx * g.nky;
+    size_t b = 0;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    b += al(nk * 8);
+    b += al(g.nkx * cs) + al(g.nky * cs);
+    b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
+    b += 2 * al(pl.p.nomega * sizeof(int));
+    b += al((size_t)g.nslots * g.slice_elems * cs);
+    b += al(2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
+    if (pl.p.want_rpa) {
+        b += al((size_t)g.neps * nk * es);
+        b += al((size_t)pl.p.nomega * nk * es);
+        b += al((size_t)pl.p.nomega * g.neps * 8);
+    }
+    return b;
+}
+
+void plan_free(Plan &pl)
+{
+    void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, (void **)&pl.ffx,
+                     (void **)&pl.ffy,    (void **)&pl.d_slot, (void **)&pl.d_lag, &pl.spec,
+                     &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch};
+    for (void **p : ptrs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+}
+
+#define LH_TRY(x)                                                                                         \
+    do {                                                                                                   \
+        hipError_t e_ = (x);                                                                               \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? LINDHARD_ENOMEM : LINDHARD_EDEVICE;       \
+    } while (0)
+
+static lindhard_status dalloc(void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? LINDHARD_ENOMEM : LINDHARD_EDEVICE;
+    }
+    return LINDHARD_OK;
+}
+
+static lindhard_status solve_mu(Plan &pl, hipStream_t st, double band_lo, double band_hi)
+{
+    // Safeguarded Newton on n(mu) - filling with the bracket
+    // [min eps - 100, max eps + 100]; n and dn/dmu are FP64 device reductions.
+    double *d2 = pl.scratch + 2 * kOccBlocks;
+    double lo = band_lo - 100.0, hi = band_hi + 100.0;
+    double mu = 0.5 * (band_lo + band_hi);
+    const double f0 = pl.p.filling;
+    double h2[2];
+    int it = 0;
+    for (; it < 200; ++it) {
+        LH_TRY(launch_occ(pl, mu, d2, st));
+        LH_TRY(hipMemcpyAsync(h2, d2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        LH_TRY(hipStreamSynchronize(st));
+        const double f = h2[0] - f0, df = h2[1];
+        if (f == 0.0) break;
+        if (f < 0.0)
+            lo = mu;
+        else
+            hi = mu;
+        double nxt = (df > 0.0) ? mu - f / df : 0.5 * (lo + hi);
+        if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
+        const double step = std::fabs(nxt - mu);
+        mu = nxt;
+        if (step <= 4e-16 * std::max(1.0, std::fabs(mu)) || hi - lo <= 1e-15) break;
+    }
+    pl.mu_iters = it + 1;
+    if (it >= 200) return LINDHARD_ENOCONV;
+    pl.mu = mu;
+    return LINDHARD_OK;
+}
+
+lindhard_status plan_build(Plan &pl, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
+    const size_t nk = (size_t)g.nkx * g.nky;
+    lindhard_status s;
+#define LH_ALLOC(ptr, bytes)                                 \
+    do {                                                     \
+        s = dalloc((void **)&(ptr), (bytes));                \
+        if (s != LINDHARD_OK) return s;                      \
+    } while (0)
+    LH_ALLOC(pl.xi, nk * 8);
+    LH_ALLOC(pl.twx, g.nkx * cs);
+    LH_ALLOC(pl.twy, g.nky * cs);
+    LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
+    LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
+    LH_ALLOC(pl.d_slot, pl.p.nomega * sizeof(int));
+    LH_ALLOC(pl.d_lag, pl.p.nomega * sizeof(int));
+    LH_ALLOC(pl.spec, (size_t)g.nslots * g.slice_elems * cs);
+    LH_ALLOC(pl.scratch, 2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
+    if (pl.p.want_rpa) {
+        LH_ALLOC(pl.im1, (size_t)g.neps * nk * es);
+        LH_ALLOC(pl.re1, (size_t)pl.p.nomega * nk * es);
+        LH_ALLOC(pl.kkw, (size_t)pl.p.nomega * g.neps * 8);
+    }
+#undef LH_ALLOC
+    return LINDHARD_OK;
+}
+
+}  // namespace lh
+
+using namespace lh;
+
+struct lindhard_plan_s {
+    Plan pl;
+    hipStream_t setup = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each exec / rpa
+};
+
+static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_plan_s *o)
+{
+    Plan &pl = o->pl;
+    lindhard_status s = plan_describe(p, pl);
+    if (s != LINDHARD_OK) return s;
+    if (hipGetDevice(&pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    if (hipStreamCreateWithFlags(&o->setup, hipStreamNonBlocking) != hipSuccess) return LINDHARD_EDEVICE;
+    if (hipEventCreateWithFlags(&o->done, hipEventDisableTiming) != hipSuccess) return LINDHARD_EDEVICE;
+    hipStream_t st = o->setup;
+    s = plan_build(pl, st);
+    if (s != LINDHARD_OK) return s;
+    const size_t nk = (size_t)pl.g.nkx * pl.g.nky;
+    double band_lo = 0.0, band_hi = 0.0;
+    if (p->eps_table) {
+        // the caller's table is read during planning only
+        LH_TRY(hipMemcpyAsync(pl.xi, p->eps_table, nk * sizeof(double), hipMemcpyHostToDevice, st));
+        band_lo = *std::min_element(p->eps_table, p->eps_table + nk);
+        band_hi = *std::max_element(p->eps_table, p->eps_table + nk);
+    } else {
+        LH_TRY(launch_band(pl, nullptr, st));
+        const double bnd = 4.0 * (std::fabs(p->t) + std::fabs(p->tp) + std::fabs(p->tpp));
+        band_lo = -bnd;
+        band_hi = bnd;
+    }
+    if (std::isnan(p->mu)) {
+        s = solve_mu(pl, st, band_lo, band_hi);
+        if (s != LINDHARD_OK) return s;
+    } else {
+        pl.mu = p->mu;
+        pl.mu_iters = 0;
+    }
+    LH_TRY(launch_xi_shift(pl, pl.mu, st));
+    LH_TRY(hipMemcpyAsync(pl.d_slot, pl.slot.data(), pl.slot.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LH_TRY(hipMemcpyAsync(pl.d_lag, pl.lag.data(), pl.lag.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LH_TRY(launch_tables(pl, st));
+    if (pl.p.want_rpa)
+        LH_TRY(hipMemsetAsync(pl.im1, 0, (size_t)pl.g.neps * nk * pl.elem_bytes, st));
+    LH_TRY(hipStreamSynchronize(st));
+    return LINDHARD_OK;
+}
+
+extern "C" {
+
+lindhard_status lindhard_plan(const lindhard_problem *p, lindhard_plan_t *out)
+{
+    if (!p || !out) return LINDHARD_EINVAL;
+    *out = nullptr;
+    lindhard_plan_s *o = new (std::nothrow) lindhard_plan_s();
+    if (!o) return LINDHARD_ENOMEM;
+    lindhard_status s = build_plan_object(p, o);
+    if (s != LINDHARD_OK) {
+        if (o->setup) (void)hipStreamSynchronize(o->setup);
+        plan_free(o->pl);
+        if (o->setup) (void)hipStreamDestroy(o->setup);
+        if (o->done) (void)hipEventDestroy(o->done);
+        delete o;
+        (void)hipGetLastError();
+        return s;
+    }
+    *out = o;
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_plan_info(lindhard_plan_t plan, lindhard_info *info)
+{
+    if (!plan || !info) return LINDHARD_EINVAL;
+    const Plan &pl = plan->pl;
+    std::memset(info, 0, sizeof *info);
+    info->mu = pl.mu;
+    info->deps = pl.deps;
+    info->j0 = pl.g.j0;
+    info->out_nx = pl.out_nx;
+    info->out_ny = pl.out_ny;
+    info->nomega = pl.p.nomega;
+    info->lag_lo = pl.g.m_lo;
+    info->lag_hi = pl.g.m_hi;
+    info->mu_iterations = pl.mu_iters;
+    info->workspace_bytes = pl.ws_bytes;
+    info->out_elems = pl.out_elems;
+    info->elem_bytes = pl.elem_bytes;
+    std::snprintf(info->schedule, sizeof info->schedule, "%s", pl.schedule.c_str());
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_exec(lindhard_plan_t plan, void *im_chi, void *stream)
+{
+    if (!plan || !im_chi) return LINDHARD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_exec(plan->pl, im_chi, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return LINDHARD_EDEVICE;
+    plan->pl.executed = true;
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_exec_timed(lindhard_plan_t plan, void *im_chi, void *stream, float *pass_ms)
+{
+    if (!plan || !im_chi || !pass_ms) return LINDHARD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipEvent_t ev[6] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess) e = launch_exec(plan->pl, im_chi, (hipStream_t)stream, ev);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventElapsedTime(&pass_ms[i], ev[i], ev[i + 1]);
+    for (int i = 0; i < 6; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return LINDHARD_EDEVICE;
+    plan->pl.executed = true;
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void *im_rpa, void *re_rpa, void *stream)
+{
+    if (!plan || !std::isfinite(U)) return LINDHARD_EINVAL;
+    if (!plan->pl.p.want_rpa || !plan->pl.executed) return LINDHARD_ESTATE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_rpa(plan->pl, U, re_chi, im_rpa, re_rpa, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs, void *stream)
+{
+    if (!plans || !outs || n < 0) return LINDHARD_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !outs[i]) return LINDHARD_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        lindhard_status s = lindhard_exec(plans[i], outs[i], stream);
+        if (s != LINDHARD_OK) return s;
+    }
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_plan_destroy(lindhard_plan_t plan)
+{
+    if (!plan) return LINDHARD_EINVAL;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(plan->pl.device);
+    if (plan->done) {
+        (void)hipEventSynchronize(plan->done);
+        (void)hipEventDestroy(plan->done);
+    }
+    if (plan->setup) (void)hipStreamSynchronize(plan->setup);
+    plan_free(plan->pl);
+    if (plan->setup) (void)hipStreamDestroy(plan->setup);
+    (void)hipSetDevice(dev);
+    delete plan;
+    return LINDHARD_OK;
+}
+
+const char *lindhard_strerror(lindhard_status st)
+{
+    switch (st) {
+    case LINDHARD_OK: return "ok";
+    case LINDHARD_EINVAL: return "invalid argument";
+    case LINDHARD_EOFFGRID: return "omega is not on the energy-lag grid";
+    case LINDHARD_ENOMEM: return "out of memory";
+    case LINDHARD_ETOOBIG: return "job footprint exceeds the HBM budget";
+    case LINDHARD_EBUSY: return "busy (queue full or timeout)";
+    case LINDHARD_EDEVICE: return "HIP device error";
+    case LINDHARD_ENOCONV: return "chemical potential did not converge";
+    case LINDHARD_ECANCELED: return "job cancelled";
+    case LINDHARD_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

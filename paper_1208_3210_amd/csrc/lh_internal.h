@@ -1,0 +1,90 @@
+// lh_internal.h -- plan object and pass launchers shared by the C ABI, the
+// batched executor and the server.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lindhard.h"
+
+namespace lh {
+
+// Geometry of one instance and of its device arrays.
+//
+// Spectral / real-space arrays ("slices") use a column-tiled layout so that
+// every pass streams contiguous memory: element (slice s, rx, ry) of the
+// half spectrum rx in [0, L], L = nkx/2, lives at
+//   ((s * NT + rx / C) * nky + ry) * C + rx % C,    NT = L / C + 1,
+// with C complex values = 32 bytes per tile row (C = 4 in FP32, 2 in FP64).
+// A column pass reads one tile (nky * C values) as one contiguous block, a row
+// pass reads R rows * C values per tile, the energy-window pass reads RY rows
+// * C values per slice.
+struct Geo {
+    int fp64;
+    int nkx, nky, logNx, logNy;
+    int L, logL;        // row transform length nkx / 2
+    int C, logC, NT;    // tile width (complex values) and tile count
+    int neps;
+    int jA, jB;         // slices that can enter the window: [jA, jB)
+    int nS;             // jB - jA
+    int j0;             // occupied points (global index)
+    int m_lo, m_hi, nL; // lag range of the window pass; nL = 0: nothing to do
+    int nslots;         // slices allocated in the spectral array
+    size_t slice_elems; // NT * nky * C
+    // launch shapes
+    int p1_R, p1_logR, p1_jc;
+    int p3_RY, p3_logRY, p3_TR, p3_logTR;
+    int p5_R, p5_logR;
+};
+
+struct Plan {
+    lindhard_problem p{};
+    std::vector<double> omega;
+    std::vector<int> lag;      // lag m of each requested omega (>= 0)
+    std::vector<int> slot;     // window slot of each omega, -1 if the value is 0
+    int device = 0;
+    Geo g{};
+    double mu = 0.0, deps = 0.0, scale = 0.0, ff_s = 0.0;
+    int mu_iters = 0;
+    int zx = 1, zy = 1, out_nx = 0, out_ny = 0;
+    size_t out_elems = 0, elem_bytes = 4;
+    // device memory (owned)
+    double *xi = nullptr;      // eps(k) - mu, FP64, [nky][nkx]
+    void *twx = nullptr;       // cx<T>[nkx]
+    void *twy = nullptr;       // cx<T>[nky]
+    double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
+    double2 *ffy = nullptr;    // per extended row
+    int *d_slot = nullptr;     // per omega: window slot or -1
+    int *d_lag = nullptr;      // per omega: lag
+    void *spec = nullptr;      // spectral / real-space array, nslots slices
+    void *im1 = nullptr;       // RPA: Im chi_1BZ [neps][nky][nkx]
+    void *re1 = nullptr;       // RPA: Re chi_1BZ [nomega][nky][nkx]
+    double *kkw = nullptr;     // RPA: Kramers-Kronig weights [nomega][neps]
+    double *scratch = nullptr; // mu-solve partial sums
+    size_t ws_bytes = 0;
+    bool executed = false;
+    std::string schedule;
+};
+
+// Validate and derive everything host-side (no device work).  Fills `pl`.
+lindhard_status plan_describe(const lindhard_problem *p, Plan &pl);
+// Allocate device memory, build band / mu / tables.  Synchronous on `st`.
+lindhard_status plan_build(Plan &pl, hipStream_t st);
+void plan_free(Plan &pl);
+// Device footprint of a problem (for admission).  0 if invalid.
+size_t plan_footprint(const Plan &pl);
+
+// Pass launchers (asynchronous on `st`).
+hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev = nullptr);
+hipError_t launch_rpa(const Plan &pl, double U, void *re, void *imr, void *rer, hipStream_t st);
+
+// Setup kernels.
+hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st);
+hipError_t launch_occ(const Plan &pl, double mu, double *d_out2, hipStream_t st);
+hipError_t launch_tables(const Plan &pl, hipStream_t st);
+hipError_t launch_xi_shift(const Plan &pl, double mu, hipStream_t st);
+
+constexpr int kOccBlocks = 512;
+
+}  // namespace lh

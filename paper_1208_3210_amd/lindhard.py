@@ -1,0 +1,267 @@
+"""Python binding of the C ABI in include/lindhard.h (argument marshalling only).
+
+Every step of the computation runs in the gfx950 kernels of liblindhard.so.
+PyTorch is used for device memory and streams: outputs are torch tensors on the
+GPU and the current torch stream is passed to the library.  If the shared
+library is missing this module raises; there is no fallback path.
+
+torch is imported before the library is loaded so that the process holds a
+single HIP runtime (the library's libamdhip64 dependency resolves to the one
+torch has already loaded).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (must precede the CDLL load, see module docstring)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblindhard.so")
+
+LINDHARD_OK = 0
+LINDHARD_EINVAL = -1
+LINDHARD_EOFFGRID = -2
+LINDHARD_ENOMEM = -3
+LINDHARD_ETOOBIG = -4
+LINDHARD_EBUSY = -5
+LINDHARD_EDEVICE = -6
+LINDHARD_ENOCONV = -7
+LINDHARD_ECANCELED = -8
+LINDHARD_ESTATE = -9
+
+LINDHARD_FP32C = 1
+LINDHARD_FP64 = 2
+LINDHARD_FF_NONE = 0
+LINDHARD_FF_GAUSS_DX2Y2 = 1
+
+
+class LindhardError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, strerror(status) if _lib_obj else "error", status))
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double), ("tp", ctypes.c_double), ("tpp", ctypes.c_double),
+        ("eps_table", ctypes.POINTER(ctypes.c_double)),
+        ("mu", ctypes.c_double), ("filling", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("nkx", ctypes.c_int32), ("nky", ctypes.c_int32),
+        ("neps", ctypes.c_int32), ("emin", ctypes.c_double), ("emax", ctypes.c_double),
+        ("nomega", ctypes.c_int32), ("omega", ctypes.POINTER(ctypes.c_double)),
+        ("zones_x", ctypes.c_int32), ("zones_y", ctypes.c_int32),
+        ("ff_kind", ctypes.c_int32), ("ff_width", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("want_rpa", ctypes.c_int32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("mu", ctypes.c_double), ("deps", ctypes.c_double), ("j0", ctypes.c_int32),
+        ("out_nx", ctypes.c_int32), ("out_ny", ctypes.c_int32), ("nomega", ctypes.c_int32),
+        ("lag_lo", ctypes.c_int32), ("lag_hi", ctypes.c_int32), ("mu_iterations", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_size_t), ("out_elems", ctypes.c_size_t),
+        ("elem_bytes", ctypes.c_size_t), ("schedule", ctypes.c_char * 96),
+    ]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+        ("rejected", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("points_per_s", ctypes.c_double),
+        ("hbm_high_water", ctypes.c_size_t), ("queue_depth", ctypes.c_int32), ("inflight", ctypes.c_int32),
+    ]
+
+
+EXPORTS = [
+    "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa", "lindhard_exec_batch",
+    "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
+    "lindhard_serve_wait", "lindhard_serve_cancel", "lindhard_serve_stats_get", "lindhard_serve_destroy",
+    "lindhard_strerror",
+]
+
+_lib_obj = None
+_lib_lock = threading.Lock()
+_vp = ctypes.c_void_p
+_st = ctypes.c_int
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblindhard.so (raises if it has not been built)."""
+    global _lib_obj
+    with _lib_lock:
+        if _lib_obj is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("liblindhard.so not found at %s; build it with "
+                                   "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            L.lindhard_plan.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(_vp)]
+            L.lindhard_plan_info.argtypes = [_vp, ctypes.POINTER(Info)]
+            L.lindhard_exec.argtypes = [_vp, _vp, _vp]
+            L.lindhard_exec_timed.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]
+            L.lindhard_rpa.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+            L.lindhard_exec_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp), _vp]
+            L.lindhard_plan_destroy.argtypes = [_vp]
+            L.lindhard_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(_vp)]
+            L.lindhard_serve_submit.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.c_double, _vp, _vp, _vp,
+                                                _vp, ctypes.POINTER(ctypes.c_uint64)]
+            L.lindhard_serve_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(_st)]
+            L.lindhard_serve_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_st)]
+            L.lindhard_serve_cancel.argtypes = [_vp, ctypes.c_uint64]
+            L.lindhard_serve_stats_get.argtypes = [_vp, ctypes.POINTER(ServeStats)]
+            L.lindhard_serve_destroy.argtypes = [_vp]
+            L.lindhard_strerror.argtypes = [_st]
+            L.lindhard_strerror.restype = ctypes.c_char_p
+            for name in EXPORTS:
+                if name != "lindhard_strerror":
+                    getattr(L, name).restype = _st
+            _lib_obj = L
+    return _lib_obj
+
+
+def strerror(status: int) -> str:
+    return lib().lindhard_strerror(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != LINDHARD_OK:
+        raise LindhardError(status, where)
+
+
+def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gamma: float,
+                 omega: Sequence[float], t: float = 0.0, tp: float = 0.0, tpp: float = 0.0,
+                 eps_table: Optional[np.ndarray] = None, mu: float = float("nan"), filling: float = 1.0,
+                 zones: tuple = (1, 1), ff_kind: int = LINDHARD_FF_NONE, ff_width: float = 0.0,
+                 precision: int = LINDHARD_FP32C, want_rpa: bool = False):
+    """Fill a Problem; returns (problem, keepalive) -- keep `keepalive` until the call."""
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+    keep = [om]
+    p = Problem()
+    p.t, p.tp, p.tpp = float(t), float(tp), float(tpp)
+    if eps_table is not None:
+        tab = np.ascontiguousarray(np.asarray(eps_table, dtype=np.float64))
+        keep.append(tab)
+        p.eps_table = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.mu, p.filling, p.gamma = float(mu), float(filling), float(gamma)
+    p.nkx, p.nky, p.neps = int(nkx), int(nky), int(neps)
+    p.emin, p.emax = float(emin), float(emax)
+    p.nomega = int(om.size)
+    p.omega = om.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.zones_x, p.zones_y = int(zones[0]), int(zones[1])
+    p.ff_kind, p.ff_width = int(ff_kind), float(ff_width)
+    p.precision, p.want_rpa = int(precision), int(bool(want_rpa))
+    return p, keep
+
+
+def lindhard_plan(problem: Problem) -> int:
+    h = _vp()
+    _check(lib().lindhard_plan(ctypes.byref(problem), ctypes.byref(h)), "lindhard_plan")
+    return h.value
+
+
+def lindhard_plan_info(plan: int) -> Info:
+    info = Info()
+    _check(lib().lindhard_plan_info(_vp(plan), ctypes.byref(info)), "lindhard_plan_info")
+    return info
+
+
+def lindhard_exec(plan: int, im_chi_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_exec(_vp(plan), _vp(im_chi_ptr), _vp(stream_ptr)), "lindhard_exec")
+
+
+def lindhard_exec_timed(plan: int, im_chi_ptr: int, stream_ptr: int):
+    """Run the hot path once and return the five pass durations (ms)."""
+    ms = (ctypes.c_float * 5)()
+    _check(lib().lindhard_exec_timed(_vp(plan), _vp(im_chi_ptr), _vp(stream_ptr), ms), "lindhard_exec_timed")
+    return [float(x) for x in ms]
+
+
+def lindhard_rpa(plan: int, U: float, re_ptr: int, imr_ptr: int, rer_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_rpa(_vp(plan), float(U), _vp(re_ptr), _vp(imr_ptr), _vp(rer_ptr), _vp(stream_ptr)),
+           "lindhard_rpa")
+
+
+def lindhard_exec_batch(plans: Sequence[int], outs: Sequence[int], stream_ptr: int) -> None:
+    n = len(plans)
+    pa = (_vp * n)(*plans)
+    oa = (_vp * n)(*outs)
+    _check(lib().lindhard_exec_batch(pa, n, oa, _vp(stream_ptr)), "lindhard_exec_batch")
+
+
+def lindhard_plan_destroy(plan: int) -> None:
+    _check(lib().lindhard_plan_destroy(_vp(plan)), "lindhard_plan_destroy")
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype(precision: int):
+    return torch.float64 if precision == LINDHARD_FP64 else torch.float32
+
+
+class Plan:
+    """One planned susceptibility problem; outputs are torch tensors on the GPU."""
+
+    def __init__(self, **kw):
+        self.kw = dict(kw)
+        self.problem, keep = make_problem(**kw)
+        self.handle = lindhard_plan(self.problem)
+        del keep
+        self.info = lindhard_plan_info(self.handle)
+        self.dtype = _dtype(self.problem.precision)
+        self.shape = (self.info.nomega, self.info.out_ny, self.info.out_nx)
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def exec(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = self.empty()
+        assert out.is_cuda and out.dtype == self.dtype and tuple(out.shape) == self.shape and out.is_contiguous()
+        lindhard_exec(self.handle, out.data_ptr(), _stream_ptr(stream))
+        return out
+
+    def exec_timed(self, out: torch.Tensor, stream=None):
+        assert out.is_cuda and out.dtype == self.dtype and tuple(out.shape) == self.shape and out.is_contiguous()
+        return lindhard_exec_timed(self.handle, out.data_ptr(), _stream_ptr(stream))
+
+    def rpa(self, U: float, stream=None):
+        re, imr, rer = self.empty(), self.empty(), self.empty()
+        lindhard_rpa(self.handle, U, re.data_ptr(), imr.data_ptr(), rer.data_ptr(), _stream_ptr(stream))
+        return re, imr, rer
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lindhard_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exec_batch(plans: Sequence[Plan], outs: Optional[Sequence[torch.Tensor]] = None, stream=None):
+    if outs is None:
+        outs = [p.empty() for p in plans]
+    lindhard_exec_batch([p.handle for p in plans], [o.data_ptr() for o in outs], _stream_ptr(stream))
+    return outs
+
+
+def nan() -> float:
+    return math.nan

@@ -1,0 +1,98 @@
+"""Seeded synthetic inputs of the benchmark and parity workloads.
+
+Parameters only: band hoppings, grids, broadenings, fillings and omega lists.
+Nothing here evaluates the method.  The paper's NCCO band (KKR-LDA) is
+replaced by a square-lattice t-t'-t'' band whose width (-1.48 .. 1.88 eV for
+t = 0.42, t' = -0.10, t'' = 0.05 eV) matches the -1.4 .. 1.9 eV Cu-O band of
+Sec. 3; random draws use numpy's PCG64 with a fixed seed per workload.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BAND1 = dict(t=0.42, tp=-0.10, tpp=0.05)
+
+
+def lag_omegas(neps: int, emin: float, emax: float, lags) -> np.ndarray:
+    """omega = m * d on the cell-centred energy grid of the window."""
+    d = (emax - emin) / neps
+    return np.asarray(lags, dtype=np.float64) * d
+
+
+def config1() -> dict:
+    """Plain method, FP64: 32x32 k, 64 energies on [-1, 1] eV, G = 0.05 eV,
+    32 omegas in (0, 1] eV, first zone only, |M|^2 = 1."""
+    neps, emin, emax = 64, -1.0, 1.0
+    return dict(**BAND1, filling=1.15, nkx=32, nky=32, neps=neps, emin=emin, emax=emax, gamma=0.05,
+                omega=lag_omegas(neps, emin, emax, range(1, 33)), zones=(1, 1), ff_kind=0, ff_width=0.0)
+
+
+def config2() -> dict:
+    """Extended zones + RPA: 512x512 k, 256 energies on [-2, 2] eV, G = 0.03 eV,
+    128 omegas in (0, 2] eV, 5x5 zones, Gaussian d_{x2-y2} orbital of width 0.6,
+    U = 1.5 eV (passed separately)."""
+    neps, emin, emax = 256, -2.0, 2.0
+    return dict(**BAND1, filling=1.15, nkx=512, nky=512, neps=neps, emin=emin, emax=emax, gamma=0.03,
+                omega=lag_omegas(neps, emin, emax, range(1, 129)), zones=(5, 5), ff_kind=1, ff_width=0.6,
+                want_rpa=True)
+
+
+CONFIG2_U = 1.5
+
+
+def seeded_band(rng: np.random.Generator) -> dict:
+    """t in [0.35, 0.45], t'/t in [-0.35, -0.15], t''/t in [0, 0.2] (eV)."""
+    t = rng.uniform(0.35, 0.45)
+    return dict(t=t, tp=t * rng.uniform(-0.35, -0.15), tpp=t * rng.uniform(0.0, 0.2))
+
+
+def config3(nk: int = 2048, neps: int = 512) -> dict:
+    """Large single instance: 2048x2048 k, 512 energies on [-2, 2] eV,
+    G = 0.01 eV, 256 omegas in (0, 2] eV, seeded band (seed 12083210), filling 1.15."""
+    rng = np.random.Generator(np.random.PCG64(12083210))
+    emin, emax = -2.0, 2.0
+    nlag = neps // 2
+    return dict(**seeded_band(rng), filling=1.15, nkx=nk, nky=nk, neps=neps, emin=emin, emax=emax,
+                gamma=0.01, omega=lag_omegas(neps, emin, emax, range(1, nlag + 1)), zones=(1, 1), ff_kind=0,
+                ff_width=0.0)
+
+
+def config4(n: int = 64, seed: int = 4) -> list:
+    """Batched: 64 instances, k-grid uniform over {128,256,512,1024}^2, energies
+    over {64,128,256,512} on [-2, 2] eV, doping x in [0, 0.2] (filling 1 + x),
+    G in [0.01, 0.08] eV, 64 lags each, band of config 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n):
+        nk = int(rng.choice([128, 256, 512, 1024]))
+        neps = int(rng.choice([64, 128, 256, 512]))
+        x = rng.uniform(0.0, 0.2)
+        g = rng.uniform(0.01, 0.08)
+        out.append(dict(**BAND1, filling=1.0 + x, nkx=nk, nky=nk, neps=neps, emin=-2.0, emax=2.0, gamma=g,
+                        omega=lag_omegas(neps, -2.0, 2.0, range(1, 65)), zones=(1, 1), ff_kind=0,
+                        ff_width=0.0))
+    return out
+
+
+def config5(n_req: int = 2200, seed: int = 5, rate_hz: float = 200.0) -> list:
+    """Served Poisson stream: exponential inter-arrival times of mean 1/rate,
+    k-grid over {128..1024}^2, energies over {64..512}, 16..128 omegas, band
+    and doping as config 3, RPA with probability 1/2 and U in [0, 2] eV."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    jobs = []
+    for _ in range(n_req):
+        t += rng.exponential(1.0 / rate_hz)
+        nk = int(rng.choice([128, 256, 512, 1024]))
+        neps = int(rng.choice([64, 128, 256, 512]))
+        nw = int(rng.integers(16, 129))
+        band = seeded_band(rng)
+        x = rng.uniform(0.0, 0.2)
+        rpa = bool(rng.uniform() < 0.5)
+        U = float(rng.uniform(0.0, 2.0)) if rpa else float("nan")
+        jobs.append(dict(arrival_s=t, U=U,
+                         problem=dict(**band, filling=1.0 + x, nkx=nk, nky=nk, neps=neps, emin=-2.0, emax=2.0,
+                                      gamma=float(rng.uniform(0.01, 0.08)),
+                                      omega=lag_omegas(neps, -2.0, 2.0, range(1, nw + 1)), zones=(1, 1),
+                                      ff_kind=0, ff_width=0.0, want_rpa=rpa)))
+    return jobs

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function declared in include/lindhard.h, and rejects invalid problems
+during validation (before any device call)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIBPATH = os.path.join(ROOT, "paper_1208_3210_amd", "liblindhard.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIBPATH), reason="liblindhard.so not built")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lindhard.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lindhard_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_function():
+    from paper_1208_3210_amd import lindhard as LH
+
+    lib = LH.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(LH.EXPORTS)
+
+
+def test_strerror_covers_every_status():
+    from paper_1208_3210_amd import lindhard as LH
+
+    for s in range(0, -10, -1):
+        assert LH.strerror(s) != "unknown status"
+    assert LH.strerror(-99) == "unknown status"
+
+
+def _base(**over):
+    kw = dict(t=0.42, tp=-0.1, tpp=0.05, filling=1.15, nkx=32, nky=32, neps=64, emin=-1.0, emax=1.0,
+              gamma=0.05, omega=np.arange(1, 33) / 32.0, precision=2)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(nkx=48), -1), (dict(nky=2), -1), (dict(nkx=4096), -1), (dict(neps=100), -1), (dict(neps=2), -1),
+    (dict(emin=0.1), -1), (dict(emax=-0.1), -1), (dict(gamma=0.0), -1), (dict(gamma=math.nan), -1),
+    (dict(precision=3), -1), (dict(zones=(2, 1)), -1), (dict(zones=(1, 0)), -1), (dict(ff_kind=7), -1),
+    (dict(ff_kind=1, ff_width=0.0), -1), (dict(filling=2.5), -1), (dict(mu=math.inf), -1),
+    (dict(t=math.nan), -1), (dict(omega=[]), -1),
+    (dict(omega=[1.5 / 32.0]), -2), (dict(omega=[-1.0 / 32.0]), -2), (dict(omega=[math.nan]), -2),
+    (dict(omega=[1.0 / 32.0 + 1e-6]), -2),
+])
+def test_validation_rejects(over, status):
+    from paper_1208_3210_amd import lindhard as LH
+
+    p, keep = LH.make_problem(**_base(**over))
+    with pytest.raises(LH.LindhardError) as ei:
+        LH.lindhard_plan(p)
+    assert ei.value.status == status
+
+
+def test_validation_rejects_nonfinite_table():
+    from paper_1208_3210_amd import lindhard as LH
+
+    tab = np.zeros((32, 32))
+    tab[3, 4] = math.inf
+    p, keep = LH.make_problem(**_base(eps_table=tab, mu=0.0))
+    with pytest.raises(LH.LindhardError) as ei:
+        LH.lindhard_plan(p)
+    assert ei.value.status == -1
+
+
+def test_null_handles_are_rejected():
+    import ctypes
+
+    from paper_1208_3210_amd import lindhard as LH
+
+    L = LH.lib()
+    assert L.lindhard_exec(None, None, None) == -1
+    assert L.lindhard_rpa(None, 1.0, None, None, None, None) == -1
+    assert L.lindhard_plan_destroy(None) == -1
+    assert L.lindhard_plan_info(None, None) == -1
+    assert L.lindhard_serve_create(None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.lindhard_serve_destroy(None) == -1
