@@ -95,7 +95,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nk", type=int, default=2048)
     ap.add_argument("--neps", type=int, default=512)
+    ap.add_argument("--window", choices=["auto", "direct", "fft"], default="auto",
+                    help="energy-window variant (auto: the plan's own choice)")
     args = ap.parse_args()
+    if args.window != "auto":
+        os.environ["LINDHARD_WINDOW"] = args.window
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported (got --gpus %d)"
               % args.gpus, file=sys.stderr)
@@ -140,9 +144,14 @@ def main():
     by, fl_win = algorithmic(cfg, plan.info.lag_hi)
     gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, pass_avg)]
     dom = int(np.argmax(pass_avg))
-    src = [os.path.join(ROOT, "paper_1208_3210_amd", "csrc", f) for f in ("lh_kernels.hip", "lh_fft.h")]
+    src = [os.path.join(ROOT, "paper_1208_3210_amd", "csrc", f) for f in ("lh_kernels.hip", "lh_fft.h",
+                                                                           "lh_regfft.h")]
     khash = src_hash(src)
-    if dom == 2:
+    schedule = plan.info.schedule.decode()
+    fft_window = " P3 fft " in schedule
+    if fft_window:
+        KERNEL_NAMES[2] = "k_p3f"
+    if dom == 2 and not fft_window:
         ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
         roof = {"kernel": KERNEL_NAMES[2], "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
@@ -188,7 +197,7 @@ def main():
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof, "passes": passes, "fp64_gpu": fp64, "cpu_baseline": cpu,
-        "kernel_src_hash": khash,
+        "kernel_src_hash": khash, "schedule": schedule,
     }
     print(json.dumps(res), flush=True)
 

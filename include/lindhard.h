@@ -133,9 +133,12 @@ lindhard_status lindhard_exec_timed(lindhard_plan_t plan, void *im_chi, void *st
 lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void *im_rpa,
                              void *re_rpa, void *stream);
 
-/* Run n plans on one stream: every pass is launched once for all instances
- * (grouped launches over mixed grid sizes).  outs[i] as in lindhard_exec.
- * All plans must have the same precision.  Errors: EINVAL, EDEVICE. */
+/* Run n independent plans as one batch ordered on `stream`: the instances
+ * are forked onto a pool of worker streams (largest first, round-robin) so
+ * that instances of mixed grid sizes overlap on the device, and joined back
+ * into `stream` before any later work on it.  outs[i] as in lindhard_exec.
+ * All plans must live on the same device; one batch runs at a time per
+ * process.  Errors: EINVAL, EDEVICE. */
 lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs,
                                     void *stream);
 

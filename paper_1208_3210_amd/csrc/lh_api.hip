@@ -4,8 +4,11 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "lh_internal.h"
 
@@ -120,8 +123,12 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
 
     // launch shapes
     const size_t cs = g.fp64 ? 16 : 8;
-    g.p1_R = std::min(p->nky, std::max(1, 4096 / g.L));
-    g.p1_logR = ilog2(g.p1_R);
+    {
+        // P1: G = L / E threads per row (E = min(16, L)), up to 256 threads
+        const int E = std::min(16, g.L), G = g.L / E;
+        g.p1_R = std::min(p->nky, std::max(1, 256 / G));
+        g.p1_logR = ilog2(g.p1_R);
+    }
     {
         const long gx = p->nky / g.p1_R;
         long jc = (gx * std::max(g.nS, 1)) / 4096;
@@ -137,11 +144,86 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.p3_logRY = ilog2(g.p3_RY);
     }
     {
-        // P5 stages (2L + 1) * R complex values in LDS (<= 64 KiB)
+        // energy-window FFT variant: length 2^logNE >= nS, TR points per block
+        g.logNE = std::max(1, ilog2(std::max(g.nS, 2)));
+        const int NE = 1 << g.logNE;
+        const int E = std::min(16, NE), G = NE / E;
+        int TR = 32;
+        while (TR > g.C && ((size_t)NE * TR * cs > 65536 || TR * G > 512)) TR >>= 1;
+        TR = std::min(TR, g.C * p->nky);
+        g.p3f_TR = TR;
+        g.p3f_logTR = ilog2(TR);
+        // direct form: complex MACs per real-space point; FFT form: ~3 transforms
+        double direct = 0.0;
+        for (int m = g.m_lo; m <= g.m_hi && g.nL > 0; ++m) {
+            const int jl = std::max(0, g.j0 - m), jh = std::min(g.j0, p->neps - m);
+            direct += std::max(0, jh - jl);
+        }
+        const double fftw = 3.0 * NE * (g.logNE + 1);
+        g.p3_variant = direct > fftw ? 1 : 0;
+        if (const char *ev = std::getenv("LINDHARD_WINDOW")) {
+            if (!std::strcmp(ev, "direct")) g.p3_variant = 0;
+            if (!std::strcmp(ev, "fft")) g.p3_variant = 1;
+        }
+    }
+    {
+        // P5: R rows of (L + 1) complex values in LDS (<= 64 KiB), <= 256 threads
+        const int E = std::min(16, g.L), G = g.L / E;
         int R = 1;
-        while (R * 2 <= p->nky && (size_t)(2 * g.L + 1) * (R * 2) * cs <= 65536) R *= 2;
+        while (R * 2 <= p->nky && R * 2 * G <= 256 && (size_t)(g.L + 1) * (R * 2) * cs <= 65536) R *= 2;
         g.p5_R = R;
         g.p5_logR = ilog2(R);
+    }
+    // mirror symmetry of the band -> real even transforms on the quarter plane
+    {
+        bool sym = true;
+        if (p->eps_table) {
+            const int nx = p->nkx, ny = p->nky;
+            for (int iy = 0; iy < ny && sym; ++iy)
+                for (int ix = 0; ix < nx; ++ix) {
+                    const double e = p->eps_table[(size_t)iy * nx + ix];
+                    if (e != p->eps_table[(size_t)iy * nx + ((nx - ix) & (nx - 1))] ||
+                        e != p->eps_table[(size_t)((ny - iy) & (ny - 1)) * nx + ix]) {
+                        sym = false;
+                        break;
+                    }
+                }
+        }
+        if (const char *ev = std::getenv("LINDHARD_SYMMETRY"))
+            if (!std::strcmp(ev, "off")) sym = false;
+        g.even = sym ? 1 : 0;
+        const size_t es = g.fp64 ? 8 : 4;
+        g.Ce = (int)(32 / es);
+        g.logCe = ilog2(g.Ce);
+        g.NTe = (g.L + 1 + g.Ce - 1) / g.Ce;
+        g.Hy = p->nky / 2 + 1;
+        g.slice_e = (size_t)g.NTe * g.Hy * g.Ce;
+        const int Ex = std::min(16, p->nkx), Gx = p->nkx / Ex;
+        const int np = (g.Hy + 1) / 2;
+        int R = std::max(1, 256 / Gx);
+        while (R > 1 && (size_t)R * p->nkx * cs > 65536) R >>= 1;
+        R = std::min(R, 1 << ilog2(np));
+        if ((1 << ilog2(np)) > np) R = std::min(R, 1 << (ilog2(np) - 1));
+        g.e1_R = std::max(1, R);
+        g.e5_R = g.e1_R;
+        {
+            const long blocks = (np + g.e1_R - 1) / g.e1_R;
+            long jc = (blocks * std::max(g.nS, 1)) / 4096;
+            g.e1_jc = (int)std::max(1L, std::min(16L, jc));
+        }
+        // even window: TR points per block, arrays P' [PL] and H' [HP + HL]
+        const int nB = (g.nL + 15) / 16;
+        const int HL = g.m_lo + 16 * nB - 1;
+        int TR = 64;
+        for (; TR > 1; TR >>= 1) {
+            const int SU = 64 / TR;
+            const int PL = std::min(HL, g.j0 - g.jA) + SU + 16;
+            const int HP = 32 + SU;
+            if ((size_t)(PL + HP + HL) * TR * es <= 65536) break;
+        }
+        g.e3_TR = TR;
+        g.e3_logTR = ilog2(TR);
+        g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 64 / TR + 16);
     }
 
     pl.zx = p->zones_x;
@@ -154,9 +236,15 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.ff_s = p->ff_kind == LINDHARD_FF_GAUSS_DX2Y2 ? p->ff_width * p->ff_width / 4.0 : 0.0;
     pl.ws_bytes = plan_footprint(pl);
     char buf[96];
-    std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 TR%d P5 R%d%s",
-                  g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.p1_R, g.p1_jc, g.p3_TR, g.p5_R,
-                  p->want_rpa ? " +kk/rpa" : "");
+    if (g.even)
+        std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 direct TR%d P5 R%d%s",
+                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc, g.e3_TR, g.e5_R,
+                      p->want_rpa ? " +kk/rpa" : "");
+    else
+        std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d P5 R%d%s",
+                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.p1_R, g.p1_jc,
+                      g.p3_variant ? "fft" : "direct", g.p3_variant ? g.p3f_TR : g.p3_TR, g.p5_R,
+                      p->want_rpa ? " +kk/rpa" : "");
     pl.schedule = buf;
     return LINDHARD_OK;
 }
@@ -169,10 +257,10 @@ size_t plan_footprint(const Plan &pl)
     size_t b = 0;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     b += al(nk * 8);
-    b += al(g.nkx * cs) + al(g.nky * cs);
+    b += al(g.nkx * cs) + al(g.nky * cs) + al(((size_t)1 << g.logNE) * cs);
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += 2 * al(pl.p.nomega * sizeof(int));
-    b += al((size_t)g.nslots * g.slice_elems * cs);
+    b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
     b += al(2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
     if (pl.p.want_rpa) {
         b += al((size_t)g.neps * nk * es);
@@ -184,7 +272,7 @@ size_t plan_footprint(const Plan &pl)
 
 void plan_free(Plan &pl)
 {
-    void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, (void **)&pl.ffx,
+    void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_slot, (void **)&pl.d_lag, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch};
     for (void **p : ptrs) {
@@ -257,11 +345,12 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     LH_ALLOC(pl.xi, nk * 8);
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
+    LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
     LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
     LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
     LH_ALLOC(pl.d_slot, pl.p.nomega * sizeof(int));
     LH_ALLOC(pl.d_lag, pl.p.nomega * sizeof(int));
-    LH_ALLOC(pl.spec, (size_t)g.nslots * g.slice_elems * cs);
+    LH_ALLOC(pl.spec, g.even ? (size_t)g.nslots * g.slice_e * es : (size_t)g.nslots * g.slice_elems * cs);
     LH_ALLOC(pl.scratch, 2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
     if (pl.p.want_rpa) {
         LH_ALLOC(pl.im1, (size_t)g.neps * nk * es);
@@ -414,16 +503,75 @@ lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void 
     return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
 }
 
+// Batched execution: the instances are spread over a small pool of worker
+// streams (fork from `stream`, join back into it), so independent instances
+// of mixed sizes overlap on the device.
+namespace {
+constexpr int kBatchStreams = 8;
+struct BatchPool {
+    int device = -1;
+    hipStream_t st[kBatchStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchStreams] = {};
+};
+std::mutex g_pool_mu;
+std::vector<BatchPool *> g_pools;
+
+BatchPool *batch_pool(int device)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (BatchPool *bp : g_pools)
+        if (bp->device == device) return bp;
+    BatchPool *bp = new (std::nothrow) BatchPool();
+    if (!bp) return nullptr;
+    bp->device = device;
+    bool ok = hipEventCreateWithFlags(&bp->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kBatchStreams && ok; ++i) {
+        ok = hipStreamCreateWithFlags(&bp->st[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&bp->join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) return nullptr;
+    g_pools.push_back(bp);
+    return bp;
+}
+std::mutex g_batch_mu;  // one batch at a time per process (the pool is shared)
+}  // namespace
+
 lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs, void *stream)
 {
     if (!plans || !outs || n < 0) return LINDHARD_EINVAL;
     for (int i = 0; i < n; ++i)
-        if (!plans[i] || !outs[i]) return LINDHARD_EINVAL;
-    for (int i = 0; i < n; ++i) {
-        lindhard_status s = lindhard_exec(plans[i], outs[i], stream);
-        if (s != LINDHARD_OK) return s;
+        if (!plans[i] || !outs[i] || plans[i]->pl.device != plans[0]->pl.device) return LINDHARD_EINVAL;
+    if (n == 0) return LINDHARD_OK;
+    if (n == 1) return lindhard_exec(plans[0], outs[0], stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    const int pdev = plans[0]->pl.device;
+    if (dev != pdev && hipSetDevice(pdev) != hipSuccess) return LINDHARD_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchPool *bp = batch_pool(pdev);
+    hipStream_t caller = (hipStream_t)stream;
+    hipError_t e = bp ? hipEventRecord(bp->fork, caller) : hipErrorOutOfMemory;
+    const int ns = std::min(n, kBatchStreams);
+    for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(bp->st[i], bp->fork, 0);
+    // largest instances first, round-robin over the worker streams
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return plans[a]->pl.out_elems > plans[b]->pl.out_elems; });
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        const int i = order[k];
+        hipStream_t s = bp->st[k % ns];
+        e = launch_exec(plans[i]->pl, outs[i], s);
+        if (e == hipSuccess) e = hipEventRecord(plans[i]->done, s);
+        if (e == hipSuccess) plans[i]->pl.executed = true;
     }
-    return LINDHARD_OK;
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        e = hipEventRecord(bp->join[i], bp->st[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(caller, bp->join[i], 0);
+    }
+    if (dev != pdev) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
 }
 
 lindhard_status lindhard_plan_destroy(lindhard_plan_t plan)

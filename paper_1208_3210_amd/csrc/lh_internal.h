@@ -36,6 +36,22 @@ struct Geo {
     int p1_R, p1_logR, p1_jc;
     int p3_RY, p3_logRY, p3_TR, p3_logTR;
     int p5_R, p5_logR;
+    // mirror-symmetric band (eps(kx,ky) = eps(-kx,ky) = eps(kx,-ky)): every
+    // real-space function is real and even, so the slices hold real values on
+    // the quarter rx in [0, nkx/2], ry in [0, nky/2]:
+    //   element (s, rx, ry) at ((s * NTe + rx / Ce) * Hy + ry) * Ce + rx % Ce,
+    // Ce = 32 bytes of reals, NTe = ceil((nkx/2 + 1) / Ce), Hy = nky/2 + 1.
+    int even;
+    int Ce, logCe, NTe, Hy;
+    size_t slice_e;
+    int e1_R, e1_jc;          // row pairs per block, slices per block
+    int e3_TR, e3_logTR;      // real-space points per block, even window
+    int e3_PL;                // padded length of each reversed / shifted window array
+    int e5_R;                 // row pairs per block, even inverse row pass
+    // energy-window variant: 0 direct (compensated in FP32), 1 FFT along energy
+    int p3_variant;
+    int logNE;                // FFT length along energy for variant 1
+    int p3f_TR, p3f_logTR;    // real-space points per block for variant 1
 };
 
 struct Plan {
@@ -53,6 +69,7 @@ struct Plan {
     double *xi = nullptr;      // eps(k) - mu, FP64, [nky][nkx]
     void *twx = nullptr;       // cx<T>[nkx]
     void *twy = nullptr;       // cx<T>[nky]
+    void *twe = nullptr;       // cx<T>[2^logNE] (energy-axis FFT)
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
     double2 *ffy = nullptr;    // per extended row
     int *d_slot = nullptr;     // per omega: window slot or -1

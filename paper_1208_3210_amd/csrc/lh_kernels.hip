@@ -14,6 +14,7 @@
 // Kramers-Kronig and chi / (1 - U chi) epilogues.
 #include "lh_fft.h"
 #include "lh_internal.h"
+#include "lh_regfft.h"
 
 namespace lh {
 
@@ -27,8 +28,9 @@ __global__ void __launch_bounds__(kThreads) k_band_tb(double *__restrict__ eps, 
     const long nk = (long)nkx * nky;
     const long k = (long)blockIdx.x * kThreads + threadIdx.x;
     if (k >= nk) return;
-    const int ix = (int)(k & (nkx - 1));
-    const int iy = (int)(k >> logNx);
+    // folded indices make eps(kx, ky) = eps(-kx, ky) = eps(kx, -ky) bit for bit
+    const int ix = min((int)(k & (nkx - 1)), nkx - (int)(k & (nkx - 1)));
+    const int iy = min((int)(k >> logNx), nky - (int)(k >> logNx));
     const double cx = cospi(2.0 * ix / nkx), cy = cospi(2.0 * iy / nky);
     const double c2x = cospi(4.0 * ix / nkx), c2y = cospi(4.0 * iy / nky);
     eps[k] = -2.0 * t * (cx + cy) - 4.0 * tp * cx * cy - 2.0 * tpp * (c2x + c2y);
@@ -144,34 +146,36 @@ __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2
 
 // ---------------------------------------------------------------- P1
 // One block: R rows (ky) of the spectral function for jc consecutive energy
-// slices.  Row kx of length nkx is packed as z[n] = A(2n) + i A(2n+1), FFT of
-// length L = nkx/2, then split into X[k], k = 0..L (real-to-complex).
-// e_j - xi_k is formed in FP64; the Lorentzian and the transform run in T.
-template <typename T>
+// slices; G = L/E threads per row.  Row kx of length nkx is packed as
+// z[n] = A(2n) + i A(2n+1) and transformed with the register FFT of length
+// L = nkx/2, then split into X[k], k = 0..L (real-to-complex) and written to
+// the column-tiled spectral array.  e_j - xi_k is formed in FP64; the
+// Lorentzian and the transform run in T.
+template <typename T, int LOGL>
 __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx,
                                                 cx<T> *__restrict__ spec)
 {
+    using F = RegFFT<T, LOGL, false>;
+    constexpr int L = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-    const int R = g.p1_R, logR = g.p1_logR, L = g.L, logL = g.logL;
-    const int items = R << logL;
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int R = g.p1_R, logR = g.p1_logR;
     const int tid = threadIdx.x;
+    const int row = tid / G, gg = tid % G;
     const int ky0 = blockIdx.x * R;
     const int jbeg = g.jA + blockIdx.y * g.p1_jc;
     const int jend = min(g.jB, jbeg + g.p1_jc);
+    cx<T> *buf = lds + row * L;
 
-    double xa[16], xb[16];
+    double xa[E], xb[E];
+    {
+        const double2 *xr = reinterpret_cast<const double2 *>(xi + (size_t)(ky0 + row) * g.nkx);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int it = tid + q * kThreads;
-        xa[q] = 0.0;
-        xb[q] = 0.0;
-        if (it < items) {
-            const int row = it & (R - 1), n = it >> logR;
-            const double *xr = xi + (size_t)(ky0 + row) * g.nkx;
-            xa[q] = xr[2 * n];
-            xb[q] = xr[2 * n + 1];
+        for (int s = 0; s < E; ++s) {
+            const double2 x2 = xr[gg + s * G];
+            xa[s] = x2.x;
+            xb[s] = x2.y;
         }
     }
     const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
@@ -180,56 +184,66 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
 
     for (int j = jbeg; j < jend; ++j) {
         const double ej = emin + (j + 0.5) * deps;
+        cx<T> v[E];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int it = tid + q * kThreads;
-            if (it < items) {
-                const T d0 = (T)(ej - xa[q]), d1 = (T)(ej - xb[q]);
-                buf[it] = mk<T>(gp / (d0 * d0 + g2), gp / (d1 * d1 + g2));
-            }
+        for (int s = 0; s < E; ++s) {
+            const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
+            v[s] = mk<T>(gp / (d0 * d0 + g2), gp / (d1 * d1 + g2));
         }
+        F::run(v, buf, twx, 1, gg, row);
+#pragma unroll
+        for (int s = 0; s < E; ++s) buf[swz(gg + s * G)] = v[s];
         __syncthreads();
-        fft_dif_lds<T, false>(buf, logL, logR, twx, g.logNx, tid, kThreads);
         cx<T> *dst = spec + (size_t)(j - g.jA) * g.slice_elems;
-        for (int it = tid; it < nout; it += kThreads) {
+        for (int it = tid; it < nout; it += R * G) {
             const int c = it & (C - 1);
-            const int row = (it >> logC) & (R - 1);
+            const int r = (it >> logC) & (R - 1);
             const int tile = it >> (logC + logR);
             const int k = tile * C + c;
             cx<T> X = mk<T>((T)0, (T)0);
             if (k <= L) {
-                const cx<T> Zk = buf[dif_pos(k & (L - 1), logL) * R + row];
-                const cx<T> ZL = cconj(buf[dif_pos((L - k) & (L - 1), logL) * R + row]);
-                const cx<T> E = cscale(cadd(Zk, ZL), (T)0.5);
+                const cx<T> Zk = lds[r * L + swz(k & (L - 1))];
+                const cx<T> ZL = cconj(lds[r * L + swz((L - k) & (L - 1))]);
+                const cx<T> Ev = cscale(cadd(Zk, ZL), (T)0.5);
                 const cx<T> D = cscale(csub(Zk, ZL), (T)0.5);
                 const cx<T> w = twx[k];
-                X = cadd(E, cmul(mk<T>(w.y, -w.x), D));
+                X = cadd(Ev, cmul(mk<T>(w.y, -w.x), D));
             }
-            dst[((size_t)tile * g.nky + ky0 + row) * C + c] = X;
+            dst[((size_t)tile * g.nky + ky0 + r) * C + c] = X;
         }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- P2 / P4
-// One block: one column tile (C columns, all nky rows) of one slice, which is
-// one contiguous block of memory; transformed in place.
-template <typename T, bool INV>
-__global__ void __launch_bounds__(kThreads) k_col(cx<T> *__restrict__ spec, Geo g,
-                                                 const cx<T> *__restrict__ twy)
+// Column pass: each line is one column of a tile (nky values, C columns per
+// tile row).  Threads are ordered line-fastest so that one load instruction of
+// a wave covers whole 32-byte tile rows; data go straight from HBM into the
+// register FFT and back.  TPB tiles per block keep small transforms at 256
+// threads.  Transformed in place.
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
 {
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int N = F::N, E = F::E, G = F::G;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
+    constexpr int NL = TPB * C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
     const int tid = threadIdx.x;
-    const int n = g.nky << g.logC;
-    cx<T> *src = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)blockIdx.x * n;
-    for (int it = tid; it < n; it += kThreads) buf[it] = src[it];
-    __syncthreads();
-    fft_dif_lds<T, INV>(buf, g.logNy, g.logC, twy, g.logNy, tid, kThreads);
-    const int C = g.C, logC = g.logC;
-    for (int it = tid; it < n; it += kThreads) {
-        const int ry = it >> logC, c = it & (C - 1);
-        src[it] = buf[(dif_pos(ry, g.logNy) << logC) + c];
+    const int line = tid % NL, gg = tid / NL;
+    const int tb = line / C, c = line % C;
+    const int tile = blockIdx.x * TPB + tb;
+    const bool active = tile < g.NT;
+    cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)(active ? tile : 0) * N * C;
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) v[s] = active ? base[(gg + s * G) * C + c] : mk<T>((T)0, (T)0);
+    F::run(v, lds + line * N, twy, 0, gg, line);
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) base[(gg + s * G) * C + c] = v[s];
     }
 }
 
@@ -359,25 +373,86 @@ __global__ void __launch_bounds__(kThreads) k_p3(cx<T> *__restrict__ spec, Geo g
     }
 }
 
+// Energy-window product by FFT along the energy axis.  For one real-space
+// point let P_j = B(r, j) for occupied j and H_j = B(r, j) for unoccupied j
+// (zero elsewhere).  Because every occupied index lies below every unoccupied
+// one, the circular correlation of length N >= (number of slices) equals the
+// linear one for 0 <= m < N, so
+//   S(r, m) = sum_j conj(P_j) H_{j+m} = IFFT_N( conj(FFT_N P) * FFT_N H )(m) / N.
+// One block: TR real-space points (RY rows of one column tile), G threads per
+// point; the slices are staged through LDS, which is then reused as the FFT
+// line buffers.  Written in place over the slices, as the direct form.
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twe)
+{
+    using FF = RegFFT<T, LOGN, false>;
+    using FI = RegFFT<T, LOGN, true>;
+    constexpr int N = FF::N, E = FF::E, G = FF::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [N][TR], then [TR][N]
+    const int TR = g.p3f_TR, logTR = g.p3f_logTR;
+    const int tid = threadIdx.x;
+    const int rp = tid & (TR - 1), gg = tid >> logTR;
+    const size_t off = ((size_t)blockIdx.x * g.nky + (size_t)blockIdx.y * (TR >> g.logC)) << g.logC;
+    const int ne = g.nS;
+    const int j0 = g.j0 - g.jA;
+    const int nthr = TR * G;
+    for (int it = tid; it < (ne << logTR); it += nthr) {
+        const int sl = it >> logTR, p = it & (TR - 1);
+        lds[it] = spec[(size_t)sl * g.slice_elems + off + p];
+    }
+    __syncthreads();
+    const cx<T> zero = mk<T>((T)0, (T)0);
+    cx<T> vp[E], vh[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int j = gg + s * G;
+        const cx<T> b = j < ne ? lds[(j << logTR) + rp] : zero;
+        vp[s] = j < j0 ? b : zero;
+        vh[s] = j >= j0 ? b : zero;
+    }
+    __syncthreads();
+    cx<T> *buf = lds + rp * N;
+    FF::run(vp, buf, twe, 0, gg, rp);
+    FF::run(vh, buf, twe, 0, gg, rp);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const cx<T> a = vp[s], b = vh[s];
+        vh[s] = mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);  // conj(a) b
+    }
+    FI::run(vh, buf, twe, 0, gg, rp);
+    const T inv = (T)(1.0 / N);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int m = gg + s * G;
+        if (m >= g.m_lo && m <= g.m_hi)
+            spec[(size_t)(m - g.m_lo) * g.slice_elems + off + rp] = cscale(vh[s], inv);
+    }
+}
+
 // ---------------------------------------------------------------- P5
-// One block: R rows (qy) of one output plane.  Complex-to-real inverse over rx
-// from the half spectrum X[0..L]: Z'[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k/nkx}
-// (X[k] - X*[L-k]), inverse FFT of length L gives x[2n] + i x[2n+1] (no 1/N).
+// One block: R rows (qy) of one output plane, G threads per row.
+// Complex-to-real inverse over rx from the half spectrum X[0..L]:
+// Z'[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k/nkx} (X[k] - X*[L-k]); the inverse
+// register FFT of length L gives x[2n] + i x[2n+1] (no 1/N), written as pairs.
 // MODE 0: plane = requested omega; writes the extended, form-factor weighted
 //         map out[plane][Y][X] (zeros for an empty window).
 // MODE 1: plane = window slot; writes the first-zone map out[m][qy][qx].
-template <typename T, int MODE>
+template <typename T, int LOGL, int MODE>
 __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec, Geo g,
                                                 const cx<T> *__restrict__ twx, const int *__restrict__ plane_slot,
                                                 double scale, int zx, int zy, int ff, double ffs,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
                                                 T *__restrict__ out, int out_nx, int out_ny)
 {
+    using F = RegFFT<T, LOGL, true>;
+    constexpr int L = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int R = g.p5_R, logR = g.p5_logR, L = g.L, logL = g.logL;
-    cx<T> *xb = reinterpret_cast<cx<T> *>(smem_raw);  // [(L+1)][R]
-    cx<T> *zb = xb + (size_t)(L + 1) * R;              // [L][R]
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][L + 1]
+    const int R = g.p5_R, logR = g.p5_logR;
+    const int nthr = R * G;
     const int tid = threadIdx.x;
+    const int row = tid / G, gg = tid % G;
     const int plane = blockIdx.y;
     const int qy0 = blockIdx.x * R;
     const int slot = MODE == 0 ? plane_slot[plane] : plane;
@@ -385,10 +460,10 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 
     if (MODE == 0 && slot < 0) {
         for (int rz = 0; rz < R * zy; ++rz) {
-            const int row = rz % R, zi = rz / R;
-            const int Y = zi * nky + ((qy0 + row + zy * nky / 2) & (nky - 1));
+            const int r = rz % R, zi = rz / R;
+            const int Y = zi * nky + ((qy0 + r + zy * nky / 2) & (nky - 1));
             T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
-            for (int X = tid; X < out_nx; X += kThreads) orow[X] = (T)0;
+            for (int X = tid; X < out_nx; X += nthr) orow[X] = (T)0;
         }
         return;
     }
@@ -396,49 +471,354 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int C = g.C, logC = g.logC;
     const cx<T> *src = spec + (size_t)slot * g.slice_elems;
     const int nin = g.NT * (R << logC);
-    for (int it = tid; it < nin; it += kThreads) {
+    for (int it = tid; it < nin; it += nthr) {
         const int c = it & (C - 1);
-        const int row = (it >> logC) & (R - 1);
+        const int r = (it >> logC) & (R - 1);
         const int tile = it >> (logC + logR);
         const int k = tile * C + c;
-        if (k <= L) xb[k * R + row] = src[((size_t)tile * nky + qy0 + row) * C + c];
+        if (k <= L) lds[r * (L + 1) + k] = src[((size_t)tile * nky + qy0 + r) * C + c];
     }
     __syncthreads();
-    for (int it = tid; it < (L << logR); it += kThreads) {
-        const int row = it & (R - 1), k = it >> logR;
-        const cx<T> Xk = xb[k * R + row];
-        const cx<T> XL = cconj(xb[(L - k) * R + row]);
+    cx<T> *xb = lds + row * (L + 1);
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int k = gg + s * G;
+        const cx<T> Xk = xb[k];
+        const cx<T> XL = cconj(xb[L - k]);
         const cx<T> A = cadd(Xk, XL);
         const cx<T> D = csub(Xk, XL);
-        const cx<T> w = cconj(twx[k]);  // e^{+2 pi i k / nkx}
-        const cx<T> wD = cmul(w, D);
-        zb[it] = cadd(A, mk<T>(-wD.y, wD.x));  // A + i w D
+        const cx<T> wD = cmul(cconj(twx[k]), D);  // e^{+2 pi i k / nkx} D
+        v[s] = cadd(A, mk<T>(-wD.y, wD.x));      // A + i w D
     }
     __syncthreads();
-    fft_dif_lds<T, true>(zb, logL, logR, twx, g.logNx, tid, kThreads);
+    F::run(v, xb, twx, 1, gg, row);
 
     const T sc = (T)scale;
+    const int qy = qy0 + row;
     if (MODE == 0) {
-        for (int rz = 0; rz < R * zy; ++rz) {
-            const int row = rz % R, zi = rz / R;
-            const int Y = zi * nky + ((qy0 + row + zy * nky / 2) & (nky - 1));
+        for (int zi = 0; zi < zy; ++zi) {
+            const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
             T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
             const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
-            for (int X = tid; X < out_nx; X += kThreads) {
-                const int u = (X - (zx * nkx) / 2) & (nkx - 1);
-                const cx<T> v = zb[dif_pos(u >> 1, logL) * R + row];
-                T val = ((u & 1) ? v.y : v.x) * sc;
-                if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
-                orow[X] = val;
+            for (int zj = 0; zj < zx; ++zj) {
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    const int u = 2 * (gg + s * G);
+                    const int X = zj * nkx + ((u + nkx / 2) & (nkx - 1));
+                    T a = v[s].x * sc, b = v[s].y * sc;
+                    if (ff) {
+                        a = (T)((double)a * form_factor_sq(ffx[X], fy, ffs));
+                        b = (T)((double)b * form_factor_sq(ffx[X + 1], fy, ffs));
+                    }
+                    *reinterpret_cast<cx<T> *>(orow + X) = mk<T>(a, b);
+                }
             }
         }
     } else {
         const int m = g.m_lo + slot;
-        for (int row = 0; row < R; ++row) {
-            T *orow = out + ((size_t)m * nky + qy0 + row) * nkx;
-            for (int u = tid; u < nkx; u += kThreads) {
-                const cx<T> v = zb[dif_pos(u >> 1, logL) * R + row];
-                orow[u] = ((u & 1) ? v.y : v.x) * sc;
+        T *orow = out + ((size_t)m * nky + qy) * nkx;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int u = 2 * (gg + s * G);
+            *reinterpret_cast<cx<T> *>(orow + u) = mk<T>(v[s].x * sc, v[s].y * sc);
+        }
+    }
+}
+
+// ====================================================================== even
+// Mirror-symmetric band: A(kx,ky) = A(-kx,ky) = A(kx,-ky), so every transform
+// maps real even sequences to real even sequences.  Two real even lines are
+// packed as one complex line z = a + i b; its full-length FFT is X_a + i X_b
+// with X_a, X_b real, so the real and imaginary parts separate exactly.  Only
+// rx in [0, nkx/2] and ry in [0, nky/2] are stored (see Geo).
+
+// P1 (even): R row pairs (ky = 2p, 2p+1, ky <= nky/2) for jc slices.
+template <typename T, int LOGNX>
+__global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
+                                                double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec)
+{
+    using F = RegFFT<T, LOGNX, false>;
+    constexpr int N = F::N, E = F::E, G = F::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N]
+    const int R = g.e1_R;
+    const int tid = threadIdx.x;
+    const int line = tid / G, gg = tid % G;
+    const int p0 = blockIdx.x * R;
+    const int kya = min(2 * (p0 + line), g.Hy - 1), kyb = min(2 * (p0 + line) + 1, g.Hy - 1);
+    const int jbeg = g.jA + blockIdx.y * g.e1_jc;
+    const int jend = min(g.jB, jbeg + g.e1_jc);
+    cx<T> *buf = lds + line * N;
+    double xa[E], xb[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        xa[s] = xi[(size_t)kya * N + gg + s * G];
+        xb[s] = xi[(size_t)kyb * N + gg + s * G];
+    }
+    const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
+    const int Ce = g.Ce, logCe = g.logCe, H = N / 2;
+    const int rows = 2 * R;
+    const int nout = g.NTe * rows * Ce;
+    for (int j = jbeg; j < jend; ++j) {
+        const double ej = emin + (j + 0.5) * deps;
+        cx<T> v[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
+            v[s] = mk<T>(gp / (d0 * d0 + g2), gp / (d1 * d1 + g2));
+        }
+        F::run(v, buf, twx, 0, gg, line);
+#pragma unroll
+        for (int s = 0; s < E; ++s) buf[gg + s * G] = v[s];
+        __syncthreads();
+        T *dst = spec + (size_t)(j - g.jA) * g.slice_e;
+        for (int it = tid; it < nout; it += R * G) {
+            const int c = it & (Ce - 1);
+            const int r = (it >> logCe) % rows;
+            const int tile = (it >> logCe) / rows;
+            const int rx = tile * Ce + c;
+            const int ky = 2 * p0 + r;
+            if (ky >= g.Hy) continue;
+            const cx<T> z = lds[(r >> 1) * N + min(rx, H)];
+            const T val = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
+            dst[((size_t)tile * g.Hy + ky) * Ce + c] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// Column pass (even), forward or inverse: each line is a pair of adjacent
+// real columns of a tile (read as one complex value per row); rows above
+// nky/2 are the mirror of the stored ones.  Transformed in place.
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
+{
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int N = F::N, E = F::E, G = F::G;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;  // complex pairs per tile row
+    constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
+    constexpr int NL = TPB * C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int line = tid % NL, gg = tid / NL;
+    const int tb = line / C, c = line % C;
+    const int tile = blockIdx.x * TPB + tb;
+    const bool active = tile < g.NTe;
+    const int Hy = g.Hy;
+    cx<T> *base = reinterpret_cast<cx<T> *>(spec + (size_t)blockIdx.y * g.slice_e +
+                                            (size_t)(active ? tile : 0) * Hy * (2 * C));
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int ky = gg + s * G;
+        const int row = ky <= N / 2 ? ky : N - ky;
+        v[s] = active ? base[row * C + c] : mk<T>((T)0, (T)0);
+    }
+    F::run(v, lds + line * N, twy, 0, gg, line);
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int ry = gg + s * G;
+            if (ry < Hy) base[ry * C + c] = v[s];
+        }
+    }
+}
+
+// Energy window (even, direct): S(r, m) = sum_j B(r, j) B(r, j + m), real.
+// With P'[a] = B(j0 - 1 - a) (occupied, reversed) and H'[x] = B(j0 + x)
+// (unoccupied), S(m) = sum_{a=0}^{m-1} P'[a] H'[m-1-a]: a linear convolution.
+// Both arrays are staged in LDS with zero padding, so the inner loop has no
+// masks.  One block: TR consecutive points of the flattened slice; lanes are
+// TR points x SU sub-ranges of a; each wave takes blocks of 16 lags held in
+// registers with a 16-value sliding window of H'.  COMP: blocks of 16 products
+// summed in T, folded into a two-sum (hi, lo) accumulator, partials merged
+// with two-sum across lanes.
+template <typename T, bool COMP>
+__global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int TR = g.e3_TR, logTR = g.e3_logTR;
+    const int PL = g.e3_PL, HP = 32 + (64 >> logTR), HL = g.m_lo + 16 * ((g.nL + 15) >> 4) - 1;
+    T *Pz = lds;                    // [PL][TR]
+    T *Hz = lds + (size_t)PL * TR;  // [HP + HL][TR], index (HP + x)
+    const int tid = threadIdx.x;
+    const size_t p0 = (size_t)blockIdx.x * TR;
+    const int ne = g.nS, j0 = g.j0 - g.jA;
+    const size_t sl = g.slice_e;
+    for (int it = tid; it < (PL << logTR); it += kThreads) {
+        const int a = it >> logTR, p = it & (TR - 1);
+        const size_t pt = p0 + p;
+        T v = (T)0;
+        if (a < j0 && pt < sl) v = spec[(size_t)(j0 - 1 - a) * sl + pt];
+        Pz[it] = v;
+    }
+    for (int it = tid; it < ((HP + HL) << logTR); it += kThreads) {
+        const int x = (it >> logTR) - HP, p = it & (TR - 1);
+        const size_t pt = p0 + p;
+        T v = (T)0;
+        if (x >= 0 && j0 + x < ne && pt < sl) v = spec[(size_t)(j0 + x) * sl + pt];
+        Hz[it] = v;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int p = lane & (TR - 1);
+    const int su = lane >> logTR;
+    const int SU = 64 >> logTR;
+    const int nB = (g.nL + 15) >> 4;
+    for (int b = wave; b < nB; b += kThreads / 64) {
+        const int mf = g.m_lo + 16 * b;
+        const int Atot = min(mf + 15, j0);
+        T hi[16], lo[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            hi[i] = (T)0;
+            lo[i] = (T)0;
+        }
+        if (Atot > 0) {
+            const int cl = (Atot + SU - 1) / SU;
+            const int nit = (cl + 15) & ~15;
+            const int as = su * cl;
+            // window slot (i - u) & 15 holds H'[base + i - u], base = mf - 1 - a
+            const int base0 = mf - 1 - as;
+            T w[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) w[i] = Hz[((HP + base0 + i) << logTR) + p];
+            for (int u0 = 0; u0 < nit; u0 += 16) {
+                T tmp[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) tmp[i] = (T)0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int a = as + u0 + u;
+                    T pv = Pz[(a << logTR) + p];
+                    if (u0 + u >= cl) pv = (T)0;  // end of this lane's sub-range
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) tmp[i] += pv * w[(i - u) & 15];
+                    w[(15 - u) & 15] = Hz[((HP + base0 - u0 - u - 1) << logTR) + p];
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (COMP)
+                        two_sum(hi[i], lo[i], tmp[i]);
+                    else
+                        hi[i] += tmp[i];
+                }
+            }
+        }
+        for (int o = TR; o < 64; o <<= 1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const T oh = __shfl_xor(hi[i], o, 64);
+                if (COMP) {
+                    const T ol = __shfl_xor(lo[i], o, 64);
+                    two_sum(hi[i], lo[i], oh);
+                    lo[i] += ol;
+                } else {
+                    hi[i] += oh;
+                }
+            }
+        }
+        if (su == 0 && p0 + p < sl) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = mf + i;
+                if (m <= g.m_hi) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = COMP ? hi[i] + lo[i] : hi[i];
+            }
+        }
+    }
+}
+
+// P5 (even): R row pairs (qy = 2p, 2p+1 <= nky/2) of one plane.  Each line is
+// the full even row rebuilt from rx in [0, nkx/2]; its FFT gives the two real
+// rows C(qx, qy) for every qx, written to rows qy and nky - qy of each zone.
+// MODE 0: extended, form-factor weighted output planes; MODE 1: first-zone
+// planes (natural order) for the RPA path.
+template <typename T, int LOGNX, int MODE>
+__global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
+                                                const int *__restrict__ plane_slot, double scale, int zx, int zy,
+                                                int ff, double ffs, const double2 *__restrict__ ffx,
+                                                const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
+                                                int out_ny)
+{
+    using F = RegFFT<T, LOGNX, true>;
+    constexpr int N = F::N, E = F::E, G = F::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N] complex; staging [2R][N/2+1] reals
+    T *stage = reinterpret_cast<T *>(smem_raw);
+    const int R = g.e5_R;
+    const int tid = threadIdx.x, nthr = R * G;
+    const int line = tid / G, gg = tid % G;
+    const int plane = blockIdx.y;
+    const int p0 = blockIdx.x * R;
+    const int slot = MODE == 0 ? plane_slot[plane] : plane;
+    const int nkx = g.nkx, nky = g.nky, Hy = g.Hy, H = N / 2, SW = H + 1;
+    const int rows = 2 * R;
+
+    if (MODE == 0 && slot < 0) {
+        for (int rz = 0; rz < rows * 2 * zy; ++rz) {
+            const int r = rz % rows, mir = (rz / rows) & 1, zi = rz / (2 * rows);
+            const int qy0 = 2 * p0 + r;
+            if (qy0 >= Hy) continue;
+            const int qy = mir ? (nky - qy0) & (nky - 1) : qy0;
+            const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
+            T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
+            for (int X = tid; X < out_nx; X += nthr) orow[X] = (T)0;
+        }
+        return;
+    }
+    const int Ce = g.Ce, logCe = g.logCe;
+    const T *src = spec + (size_t)slot * g.slice_e;
+    const int nin = g.NTe * rows * Ce;
+    for (int it = tid; it < nin; it += nthr) {
+        const int c = it & (Ce - 1);
+        const int r = (it >> logCe) % rows;
+        const int tile = (it >> logCe) / rows;
+        const int rx = tile * Ce + c;
+        const int qy = 2 * p0 + r;
+        if (rx <= H) stage[r * SW + rx] = qy < Hy ? src[((size_t)tile * Hy + qy) * Ce + c] : (T)0;
+    }
+    __syncthreads();
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int rx = gg + s * G;
+        const int rr = rx <= H ? rx : N - rx;
+        v[s] = mk<T>(stage[(2 * line) * SW + rr], stage[(2 * line + 1) * SW + rr]);
+    }
+    __syncthreads();
+    F::run(v, lds + line * N, twx, 0, gg, line);
+
+    const T sc = (T)scale;
+    for (int half = 0; half < 2; ++half) {
+        const int qy0 = 2 * (p0 + line) + half;
+        if (qy0 >= Hy) continue;
+        for (int mir = 0; mir < 2; ++mir) {
+            const int qy = mir ? (nky - qy0) & (nky - 1) : qy0;
+            if (mir && qy == qy0) continue;
+            if (MODE == 0) {
+                for (int zi = 0; zi < zy; ++zi) {
+                    const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
+                    T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
+                    const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
+                    for (int zj = 0; zj < zx; ++zj) {
+#pragma unroll
+                        for (int s = 0; s < E; ++s) {
+                            const int qx = gg + s * G;
+                            const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
+                            T val = (half ? v[s].y : v[s].x) * sc;
+                            if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
+                            orow[X] = val;
+                        }
+                    }
+                }
+            } else {
+                const int m = g.m_lo + slot;
+                T *orow = out + ((size_t)m * nky + qy) * nkx;
+#pragma unroll
+                for (int s = 0; s < E; ++s) orow[gg + s * G] = (half ? v[s].y : v[s].x) * sc;
             }
         }
     }
@@ -563,6 +943,8 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
     const Geo &g = pl.g;
     hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(g.nkx, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twx, g.nkx);
     hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(g.nky, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twy, g.nky);
+    hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(1 << g.logNE, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twe,
+                       1 << g.logNE);
     if (pl.p.ff_kind != LINDHARD_FF_NONE) {
         hipLaunchKernelGGL(k_fftab, dim3(cdiv(pl.out_nx, kThreads)), dim3(kThreads), 0, st, pl.ffx, g.nkx, pl.zx,
                            pl.ff_s);
@@ -582,6 +964,98 @@ hipError_t launch_tables(const Plan &pl, hipStream_t st)
     return pl.g.fp64 ? tables_t<double>(pl, st) : tables_t<float>(pl, st);
 }
 
+// Launch helpers with the transform length as a template parameter.
+template <typename T, int LOGL>
+static void launch_p1(const Plan &pl, cx<T> *spec, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGL, false>;
+    hipLaunchKernelGGL((k_p1<T, LOGL>), dim3(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc)), dim3(g.p1_R * F::G),
+                       (size_t)g.p1_R * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
+                       (const cx<T> *)pl.twx, spec);
+}
+
+template <typename T, int LOGN, bool INV>
+static void launch_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
+    hipLaunchKernelGGL((k_col<T, LOGN, INV>), dim3(cdiv(g.NT, TPB), nslices), dim3(F::G * TPB * C),
+                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twy);
+}
+
+template <typename T, int LOGN>
+static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGN, false>;
+    hipLaunchKernelGGL((k_p3f<T, LOGN>), dim3(g.NT, g.nky / (g.p3f_TR >> g.logC)), dim3(g.p3f_TR * F::G),
+                       (size_t)g.p3f_TR * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twe);
+}
+
+template <typename T, int LOGL, int MODE>
+static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGL, true>;
+    const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+    hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
+                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
+                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
+}
+
+template <typename T, int LOGNX>
+static void launch_e1(const Plan &pl, T *spec, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGNX, false>;
+    const int np = (g.Hy + 1) / 2;
+    hipLaunchKernelGGL((k_e1<T, LOGNX>), dim3(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc)), dim3(g.e1_R * F::G),
+                       (size_t)g.e1_R * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
+                       (const cx<T> *)pl.twx, spec);
+}
+
+template <typename T, int LOGN, bool INV>
+static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
+    hipLaunchKernelGGL((k_ecol<T, LOGN, INV>), dim3(cdiv(g.NTe, TPB), nslices), dim3(F::G * TPB * C),
+                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twy);
+}
+
+template <typename T, int LOGNX, int MODE>
+static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGNX, true>;
+    const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+    const int np = (g.Hy + 1) / 2;
+    hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
+                       (size_t)g.e5_R * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
+                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
+}
+
+#define LH_SWITCH_LOG(v, CALL)                   \
+    switch (v) {                                 \
+    case 1: CALL(1); break;                      \
+    case 2: CALL(2); break;                      \
+    case 3: CALL(3); break;                      \
+    case 4: CALL(4); break;                      \
+    case 5: CALL(5); break;                      \
+    case 6: CALL(6); break;                      \
+    case 7: CALL(7); break;                      \
+    case 8: CALL(8); break;                      \
+    case 9: CALL(9); break;                      \
+    case 10: CALL(10); break;                    \
+    case 11: CALL(11); break;                    \
+    default: return hipErrorInvalidValue;        \
+    }
+
 // ev (optional, 6 events): recorded before P1 and after P1, P2, P3, P4, P5.
 template <typename T>
 static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
@@ -589,28 +1063,83 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     const Geo &g = pl.g;
     const size_t cs = sizeof(cx<T>);
     cx<T> *spec = (cx<T> *)pl.spec;
-    const cx<T> *twx = (const cx<T> *)pl.twx, *twy = (const cx<T> *)pl.twy;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
+    if (g.even) {
+        T *spr = (T *)pl.spec;
+        const size_t es = sizeof(T);
+        if (g.nL > 0) {
+#define LH_E1(LG) launch_e1<T, LG>(pl, spr, st)
+            LH_SWITCH_LOG(g.logNx, LH_E1)
+#undef LH_E1
+            mark(1);
+#define LH_E2(LG) launch_ecol<T, LG, false>(pl, spr, g.nS, st)
+            LH_SWITCH_LOG(g.logNy, LH_E2)
+#undef LH_E2
+            mark(2);
+            const size_t lds3 = (size_t)(g.e3_PL + 32 + (64 >> g.e3_logTR) + g.m_lo + 16 * ((g.nL + 15) >> 4) - 1) *
+                                g.e3_TR * es;
+            if (g.fp64)
+                hipLaunchKernelGGL((k_e3<T, false>), dim3(cdiv(g.slice_e, g.e3_TR)), dim3(kThreads), lds3, st, spr,
+                                   g);
+            else
+                hipLaunchKernelGGL((k_e3<T, true>), dim3(cdiv(g.slice_e, g.e3_TR)), dim3(kThreads), lds3, st, spr,
+                                   g);
+            mark(3);
+#define LH_E4(LG) launch_ecol<T, LG, true>(pl, spr, g.nL, st)
+            LH_SWITCH_LOG(g.logNy, LH_E4)
+#undef LH_E4
+            mark(4);
+        } else {
+            mark(1);
+            mark(2);
+            mark(3);
+            mark(4);
+        }
+        if (pl.p.want_rpa) {
+            if (g.nL > 0) {
+#define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
+                LH_SWITCH_LOG(g.logNx, LH_E5)
+#undef LH_E5
+            }
+            hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(pl.out_nx, kThreads), pl.out_ny, pl.p.nomega), dim3(kThreads),
+                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.zx, pl.zy, ff, pl.ff_s,
+                               pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
+        } else {
+#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
+            LH_SWITCH_LOG(g.logNx, LH_E5)
+#undef LH_E5
+        }
+        mark(5);
+        return hipGetLastError();
+    }
     if (g.nL > 0) {
-        hipLaunchKernelGGL(k_p1<T>, dim3(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc)), dim3(kThreads),
-                           (size_t)g.p1_R * g.L * cs, st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma, twx, spec);
+#define LH_P1(LG) launch_p1<T, LG>(pl, spec, st)
+        LH_SWITCH_LOG(g.logL, LH_P1)
+#undef LH_P1
         mark(1);
-        hipLaunchKernelGGL((k_col<T, false>), dim3(g.NT, g.nS), dim3(kThreads), (size_t)g.nky * g.C * cs, st, spec,
-                           g, twy);
+#define LH_P2(LG) launch_col<T, LG, false>(pl, spec, g.nS, st)
+        LH_SWITCH_LOG(g.logNy, LH_P2)
+#undef LH_P2
         mark(2);
-        if (g.fp64)
+        if (g.p3_variant == 1) {
+#define LH_P3F(LG) launch_p3f<T, LG>(pl, spec, st)
+            LH_SWITCH_LOG(g.logNE, LH_P3F)
+#undef LH_P3F
+        } else if (g.fp64) {
             hipLaunchKernelGGL((k_p3<T, false>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads),
                                (size_t)g.nS * g.p3_TR * cs, st, spec, g);
-        else
+        } else {
             hipLaunchKernelGGL((k_p3<T, true>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads),
                                (size_t)g.nS * g.p3_TR * cs, st, spec, g);
+        }
         mark(3);
-        hipLaunchKernelGGL((k_col<T, true>), dim3(g.NT, g.nL), dim3(kThreads), (size_t)g.nky * g.C * cs, st, spec,
-                           g, twy);
+#define LH_P4(LG) launch_col<T, LG, true>(pl, spec, g.nL, st)
+        LH_SWITCH_LOG(g.logNy, LH_P4)
+#undef LH_P4
         mark(4);
     } else {
         mark(1);
@@ -618,19 +1147,19 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         mark(3);
         mark(4);
     }
-    const size_t p5lds = (size_t)(2 * g.L + 1) * g.p5_R * cs;
     if (pl.p.want_rpa) {
-        if (g.nL > 0)
-            hipLaunchKernelGGL((k_p5<T, 1>), dim3(g.nky / g.p5_R, g.nL), dim3(kThreads), p5lds, st, spec, g, twx,
-                               pl.d_slot, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, (T *)pl.im1, g.nkx,
-                               g.nky);
+        if (g.nL > 0) {
+#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
+            LH_SWITCH_LOG(g.logL, LH_P5)
+#undef LH_P5
+        }
         hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(pl.out_nx, kThreads), pl.out_ny, pl.p.nomega), dim3(kThreads), 0,
                            st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
                            pl.ffy, out, pl.out_nx, pl.out_ny);
     } else {
-        hipLaunchKernelGGL((k_p5<T, 0>), dim3(g.nky / g.p5_R, pl.p.nomega), dim3(kThreads), p5lds, st, spec, g, twx,
-                           pl.d_slot, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, pl.out_nx,
-                           pl.out_ny);
+#define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
+        LH_SWITCH_LOG(g.logL, LH_P5)
+#undef LH_P5
     }
     mark(5);
     return hipGetLastError();

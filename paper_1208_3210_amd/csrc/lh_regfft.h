@@ -1,0 +1,179 @@
+// lh_regfft.h -- register-resident Stockham FFT for one line of length
+// N = 2^LOGN held by G = N/E threads with E = min(16, N) elements each.
+//
+// Passes: radix E, ..., radix E, then one pass of the remaining radix
+// (2..E), each thread doing E / r butterflies of radix r per pass.  Values stay
+// in registers inside a pass; between passes they are exchanged through the
+// line's LDS buffer (N complex values, XOR-swizzled so that the stride-r
+// writes of the first pass and the unit-stride reads are free of bank
+// conflicts; a per-line XOR of the low four index bits spreads lanes that
+// work on different lines of the same wave over different banks).
+// Autosort: no bit reversal anywhere.
+//
+// Convention on entry and on exit: thread g of the line holds
+// v[s] = x[g + s * G], s = 0 .. E-1 (natural order, stride G), so a column pass
+// can load from and store to global memory directly in that pattern.
+// Twiddles come from a table tw[x] = exp(-2 pi i x / (N << twsh)) built in FP64
+// and rounded once; the inverse uses the conjugates (no 1/N).
+#pragma once
+#include "lh_fft.h"
+
+namespace lh {
+
+// cos / sin of 2 pi m / 16, m = 0 .. 15
+__host__ __device__ constexpr double cos16(int m)
+{
+    constexpr double c[16] = {1.0,
+                              0.92387953251128675613,
+                              0.70710678118654752440,
+                              0.38268343236508977173,
+                              0.0,
+                              -0.38268343236508977173,
+                              -0.70710678118654752440,
+                              -0.92387953251128675613,
+                              -1.0,
+                              -0.92387953251128675613,
+                              -0.70710678118654752440,
+                              -0.38268343236508977173,
+                              0.0,
+                              0.38268343236508977173,
+                              0.70710678118654752440,
+                              0.92387953251128675613};
+    return c[m & 15];
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16(m + 12); }
+
+// a * exp(-+2 pi i k / R) with compile-time R, k (forward: minus sign).
+template <typename T, int R, int K, bool INV>
+__device__ __forceinline__ cx<T> rot(cx<T> a)
+{
+    constexpr int m = (K * (16 / R)) & 15;
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (m == 4) {
+        return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+    } else if constexpr (m == 8) {
+        return mk<T>(-a.x, -a.y);
+    } else if constexpr (m == 12) {
+        return INV ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+    } else {
+        constexpr T c = (T)cos16(m), s = (T)sin16(m);
+        return INV ? mk<T>(a.x * c - a.y * s, a.y * c + a.x * s) : mk<T>(a.x * c + a.y * s, a.y * c - a.x * s);
+    }
+}
+
+template <typename T, int R, bool INV, int K = 0>
+__device__ __forceinline__ void rdft_combine(cx<T> *v, const cx<T> *e, const cx<T> *o)
+{
+    if constexpr (K < R / 2) {
+        const cx<T> t = rot<T, R, K, INV>(o[K]);
+        v[K] = cadd(e[K], t);
+        v[K + R / 2] = csub(e[K], t);
+        rdft_combine<T, R, INV, K + 1>(v, e, o);
+    }
+}
+
+// In-register DFT of R = 1, 2, 4, 8, 16 points, natural order in and out.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void rdft(cx<T> *v)
+{
+    if constexpr (R == 2) {
+        const cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R > 2) {
+        cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        rdft<T, R / 2, INV>(e);
+        rdft<T, R / 2, INV>(o);
+        rdft_combine<T, R, INV>(v, e, o);
+    }
+}
+
+__device__ __forceinline__ int swz(int x) { return x ^ ((x >> 4) & 15); }
+
+template <typename T, int LOGN, bool INV>
+struct RegFFT {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int LOGE = LOGN < 4 ? LOGN : 4;
+    static constexpr int E = 1 << LOGE;
+    static constexpr int G = N / E;
+    static constexpr int NPASS = LOGN == 0 ? 0 : (LOGN + LOGE - 1) / LOGE;
+
+    // One pass of radix 2^LOGR with sub-length p = 2^LOGP.
+    template <int LOGR, int LOGP>
+    __device__ static __forceinline__ void pass(cx<T> *v, cx<T> *buf, const cx<T> *__restrict__ tw, int twsh,
+                                                int g, int lx)
+    {
+        constexpr int r = 1 << LOGR;
+        constexpr int p = 1 << LOGP;
+        constexpr int q = E / r;       // butterflies per thread
+        constexpr int stride = N / r;  // input stride
+        constexpr bool first = LOGP == 0;
+        constexpr bool last = LOGP + LOGR == LOGN;
+        cx<T> w[E];
+        if constexpr (first) {
+#pragma unroll
+            for (int u = 0; u < q; ++u)
+#pragma unroll
+                for (int s = 0; s < r; ++s) w[u * r + s] = v[u + s * q];
+        } else {
+#pragma unroll
+            for (int u = 0; u < q; ++u) {
+                const int b = g + u * G;
+#pragma unroll
+                for (int s = 0; s < r; ++s) w[u * r + s] = buf[swz(b + s * stride) ^ lx];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < q; ++u) {
+            const int b = g + u * G;
+            const int k = b & (p - 1);
+            if constexpr (!first) {
+                const int sh = LOGN - LOGP - LOGR + twsh;
+#pragma unroll
+                for (int s = 1; s < r; ++s) w[u * r + s] = cmul(w[u * r + s], twid<T, INV>(tw, (s * k) << sh));
+            }
+            rdft<T, r, INV>(w + u * r);
+            if constexpr (last) {
+#pragma unroll
+                for (int s = 0; s < r; ++s) v[u + s * q] = w[u * r + s];
+            } else {
+                const int o = (b - k) * r + k;
+#pragma unroll
+                for (int s = 0; s < r; ++s) buf[swz(o + s * p) ^ lx] = w[u * r + s];
+            }
+        }
+        if constexpr (!last) __syncthreads();
+    }
+
+    template <int T_>
+    __device__ static __forceinline__ void passes(cx<T> *v, cx<T> *buf, const cx<T> *__restrict__ tw, int twsh,
+                                                  int g, int lx)
+    {
+        if constexpr (T_ < NPASS) {
+            constexpr int LOGP = T_ * LOGE;
+            constexpr int LOGR = (LOGN - LOGP) < LOGE ? (LOGN - LOGP) : LOGE;
+            pass<LOGR, LOGP>(v, buf, tw, twsh, g, lx);
+            passes<T_ + 1>(v, buf, tw, twsh, g, lx);
+        }
+    }
+
+    // Transform one line.  Every thread of the block must call this (it
+    // contains block barriers).  buf: N complex values of LDS for this line;
+    // line: index of the line within the block (only its low bits are used).
+    // Ends with a barrier when there is more than one pass, so buf may be
+    // reused right after.
+    __device__ static __forceinline__ void run(cx<T> *v, cx<T> *buf, const cx<T> *__restrict__ tw, int twsh,
+                                               int g, int line = 0)
+    {
+        passes<0>(v, buf, tw, twsh, g, N >= 16 ? (line & 15) : 0);
+    }
+};
+
+}  // namespace lh

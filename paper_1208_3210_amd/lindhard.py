@@ -265,3 +265,71 @@ def exec_batch(plans: Sequence[Plan], outs: Optional[Sequence[torch.Tensor]] = N
 
 def nan() -> float:
     return math.nan
+
+
+class Server:
+    """Continuous-batching server (lindhard_serve_*); outputs are torch tensors."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_queue: int = 1024):
+        cfg = ServeConfig(int(hbm_budget_bytes), int(max_inflight), int(max_queue))
+        h = _vp()
+        _check(lib().lindhard_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "lindhard_serve_create")
+        self.handle = h.value
+        self._keep = {}
+
+    def submit(self, U: float = float("nan"), **problem):
+        """Queue one job; returns (ticket, outputs dict of torch tensors)."""
+        kw = dict(problem)
+        if math.isfinite(U):
+            kw["want_rpa"] = True
+        p, keep = make_problem(**kw)
+        info_probe = _probe_shape(kw)
+        dtype = _dtype(p.precision)
+        outs = {"im_chi": torch.empty(info_probe, dtype=dtype, device="cuda")}
+        if math.isfinite(U):
+            for k in ("re_chi", "im_rpa", "re_rpa"):
+                outs[k] = torch.empty(info_probe, dtype=dtype, device="cuda")
+        ptr = lambda k: outs[k].data_ptr() if k in outs else None
+        t = ctypes.c_uint64()
+        _check(lib().lindhard_serve_submit(_vp(self.handle), ctypes.byref(p), float(U), _vp(ptr("im_chi")),
+                                           _vp(ptr("re_chi")), _vp(ptr("im_rpa")), _vp(ptr("re_rpa")),
+                                           ctypes.byref(t)), "lindhard_serve_submit")
+        self._keep[t.value] = (outs, keep)
+        return t.value, outs
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int32()
+        st = _st()
+        _check(lib().lindhard_serve_poll(_vp(self.handle), ctypes.c_uint64(ticket), ctypes.byref(done),
+                                         ctypes.byref(st)), "lindhard_serve_poll")
+        return bool(done.value), int(st.value)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> int:
+        st = _st()
+        _check(lib().lindhard_serve_wait(_vp(self.handle), ctypes.c_uint64(ticket), float(timeout_s),
+                                         ctypes.byref(st)), "lindhard_serve_wait")
+        return int(st.value)
+
+    def cancel(self, ticket: int) -> int:
+        return int(lib().lindhard_serve_cancel(_vp(self.handle), ctypes.c_uint64(ticket)))
+
+    def stats(self) -> ServeStats:
+        s = ServeStats()
+        _check(lib().lindhard_serve_stats_get(_vp(self.handle), ctypes.byref(s)), "lindhard_serve_stats_get")
+        return s
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().lindhard_serve_destroy(_vp(self.handle)), "lindhard_serve_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _probe_shape(kw) -> tuple:
+    zx, zy = kw.get("zones", (1, 1))
+    return (len(np.atleast_1d(kw["omega"])), zy * int(kw["nky"]), zx * int(kw["nkx"]))

@@ -19,6 +19,20 @@ pytestmark = pytest.mark.gpu
 
 TOL = {LH.LINDHARD_FP64: 1e-11, LH.LINDHARD_FP32C: 1e-5}
 PRECS = [LH.LINDHARD_FP64, LH.LINDHARD_FP32C]
+WINDOWS = ["auto", "direct", "fft"]
+
+
+@pytest.fixture
+def window(request, monkeypatch):
+    """Pipeline chosen at plan time.  auto: the plan's own choice (the real
+    even path for mirror-symmetric bands); direct / fft: the general complex
+    path with the direct or the energy-FFT window."""
+    monkeypatch.delenv("LINDHARD_WINDOW", raising=False)
+    monkeypatch.delenv("LINDHARD_SYMMETRY", raising=False)
+    if request.param != "auto":
+        monkeypatch.setenv("LINDHARD_SYMMETRY", "off")
+        monkeypatch.setenv("LINDHARD_WINDOW", request.param)
+    return request.param
 
 
 def normwise(got, ref):
@@ -57,14 +71,16 @@ def run_gpu(cfg, prec):
     return plan, out.double().cpu().numpy()
 
 
+@pytest.mark.parametrize("window", WINDOWS, indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
-def test_config1_full_grid(prec):
+def test_config1_full_grid(prec, window):
     cfg = W.config1()
     ref, mu = oracle_extended(cfg)
     plan, got = run_gpu(cfg, prec)
     assert abs(plan.info.mu - mu) < 1e-12
     err = normwise(got, ref)
-    print("config1 prec=%d err=%.3e" % (prec, err))
+    print("config1 prec=%d window=%s err=%.3e schedule=%s" % (prec, window, err, plan.info.schedule.decode()))
+    assert (" even " in plan.info.schedule.decode()) == (window == "auto")
     assert err <= TOL[prec]
     plan.close()
 
@@ -96,15 +112,16 @@ EDGE = [
 ]
 
 
+@pytest.mark.parametrize("window", WINDOWS, indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", range(len(EDGE)))
-def test_edge_cases_full_grid(case, prec):
+def test_edge_cases_full_grid(case, prec, window):
     cfg = dict(EDGE[case])
     ref, mu = oracle_extended(cfg)
     plan, got = run_gpu(cfg, prec)
     assert got.shape == ref.shape
     err = normwise(got, ref)
-    print("edge %d prec=%d err=%.3e" % (case, prec, err))
+    print("edge %d prec=%d window=%s err=%.3e schedule=%s" % (case, prec, window, err, plan.info.schedule.decode()))
     assert err <= TOL[prec]
     # empty windows are exact zeros
     lags = lags_of(cfg)
@@ -114,8 +131,9 @@ def test_edge_cases_full_grid(case, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("window", WINDOWS, indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
-def test_caller_table_without_inversion_symmetry(prec):
+def test_caller_table_without_inversion_symmetry(prec, window):
     """A random eps table (no symmetry): complex real-space functions."""
     rng = np.random.Generator(np.random.PCG64(11))
     tab = rng.uniform(-1.2, 1.5, size=(16, 32))
@@ -124,7 +142,29 @@ def test_caller_table_without_inversion_symmetry(prec):
     ref, _ = oracle_extended(cfg)
     plan, got = run_gpu(cfg, prec)
     err = normwise(got, ref)
-    print("table prec=%d err=%.3e" % (prec, err))
+    print("table prec=%d window=%s err=%.3e schedule=%s" % (prec, window, err, plan.info.schedule.decode()))
+    assert err <= TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_caller_table_with_mirror_symmetry_takes_even_path(prec, monkeypatch):
+    """A random table made mirror symmetric in both axes is detected bit for
+    bit and runs on the real even path; it must still match the oracle."""
+    monkeypatch.delenv("LINDHARD_SYMMETRY", raising=False)
+    rng = np.random.Generator(np.random.PCG64(12))
+    nky, nkx = 32, 64
+    base = rng.uniform(-1.2, 1.5, size=(nky, nkx))
+    iy = np.minimum(np.arange(nky), (nky - np.arange(nky)) % nky)
+    ix = np.minimum(np.arange(nkx), (nkx - np.arange(nkx)) % nkx)
+    tab = base[iy[:, None], ix[None, :]]
+    cfg = dict(eps_table=tab, mu=0.05, nkx=nkx, nky=nky, neps=64, emin=-1.5, emax=1.5, gamma=0.07,
+               omega=np.arange(1, 40, 3) * (3.0 / 64), zones=(3, 1), ff_kind=1, ff_width=0.6)
+    ref, _ = oracle_extended(cfg)
+    plan, got = run_gpu(cfg, prec)
+    assert " even " in plan.info.schedule.decode()
+    err = normwise(got, ref)
+    print("sym table prec=%d err=%.3e" % (prec, err))
     assert err <= TOL[prec]
     plan.close()
 
@@ -151,8 +191,9 @@ def _config2_small():
     return cfg
 
 
+@pytest.mark.parametrize("window", WINDOWS, indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
-def test_rpa_path_full_grid(prec):
+def test_rpa_path_full_grid(prec, window):
     cfg = _config2_small()
     U = W.CONFIG2_U
     xi, mu = oracle_xi(cfg)
@@ -173,7 +214,7 @@ def test_rpa_path_full_grid(prec):
     torch.cuda.synchronize()
     errs = [normwise(x.double().cpu().numpy(), r) for x, r in ((im, im_ext), (re, re_ext), (gimr, imr),
                                                                (grer, rer))]
-    print("rpa prec=%d errs=%s" % (prec, ["%.2e" % e for e in errs]))
+    print("rpa prec=%d window=%s errs=%s" % (prec, window, ["%.2e" % e for e in errs]))
     assert max(errs) <= TOL[prec]
     plan.close()
 
@@ -196,8 +237,9 @@ def test_rpa_zero_U_is_identity_and_needs_want_rpa():
     plan.close()
 
 
+@pytest.mark.parametrize("window", ["auto", "fft"], indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
-def test_config2_full_size_sampled(prec):
+def test_config2_full_size_sampled(prec, window):
     """512^2 k, 256 energies, 5x5 zones, form factor, KK and RPA: every output
     component at sampled q (all zones), oracle over all 255 lags there."""
     cfg = W.config2()
@@ -240,7 +282,7 @@ def test_config2_full_size_sampled(prec):
                 gir.append(imr[:, Y, X].double().cpu().numpy())
                 grr.append(rer[:, Y, X].double().cpu().numpy())
     errs = [normwise(np.array(g), np.array(r)) for g, r in ((gi, ri), (gr, rr), (gir, rir), (grr, rrr))]
-    print("config2 prec=%d errs=%s" % (prec, ["%.2e" % e for e in errs]))
+    print("config2 prec=%d window=%s errs=%s" % (prec, window, ["%.2e" % e for e in errs]))
     assert max(errs) <= TOL[prec]
     plan.close()
 
@@ -263,7 +305,8 @@ def q_sum_identity_rhs(xi, neps, emin, emax, gamma, lags):
     return np.array(out)
 
 
-def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64():
+@pytest.mark.parametrize("window", ["auto", "fft", "direct"], indirect=True)
+def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
     """2048^2 k, 512 energies, 256 lags, G = 0.01 eV: FP32 (the benchmarked
     launch) against the oracle at sampled (q, m), the q-sum identity at every
     lag, C4v symmetry, and FP32 against the FP64 GPU path on the full grid."""
@@ -286,9 +329,9 @@ def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64():
     ms = np.array([s[2] for s in samples])
     ref = oracle.chi_pairs(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], qx, qy, ms)
     got = np.array([out32[m - 1, (b + n // 2) % n, (a + n // 2) % n].item() for a, b, m in samples])
-    scale = np.abs(out32).max().item()
+    scale = out32.abs().max().item()
     err_s = np.abs(got - ref).max() / scale
-    print("config3 sampled fp32 err (vs max|chi|) = %.3e" % err_s)
+    print("config3 [%s] sampled fp32 err (vs max|chi|) = %.3e" % (window, err_s))
     assert err_s <= 1e-5
 
     rhs = q_sum_identity_rhs(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], lags)

@@ -1,0 +1,132 @@
+"""Serving: continuous batching through lindhard_serve_* (C ABI).
+
+Each served result must equal the same problem run alone (bitwise: the
+schedule is deterministic and uses no atomics), a sample must match the
+oracle, admission must respect the HBM budget, and rejected, invalid or
+cancelled jobs must not affect the others."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_3210_amd import lindhard as LH
+from paper_1208_3210_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def small_jobs(n=14, seed=9):
+    """The served workload's recipe at test sizes: k-grids 32..256, energies 32..128."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for i in range(n):
+        nk = int(rng.choice([32, 64, 128, 256]))
+        neps = int(rng.choice([32, 64, 128]))
+        nw = int(rng.integers(4, neps // 2 + 1))
+        band = W.seeded_band(rng)
+        U = float(rng.uniform(0.0, 2.0)) if rng.uniform() < 0.5 else float("nan")
+        prob = dict(**band, filling=1.0 + rng.uniform(0, 0.2), nkx=nk, nky=nk, neps=neps, emin=-2.0, emax=2.0,
+                    gamma=float(rng.uniform(0.02, 0.08)),
+                    omega=W.lag_omegas(neps, -2.0, 2.0, range(1, nw + 1)),
+                    precision=LH.LINDHARD_FP32C if i % 3 else LH.LINDHARD_FP64)
+        jobs.append((U, prob))
+    return jobs
+
+
+def run_alone(U, prob):
+    kw = dict(prob)
+    if math.isfinite(U):
+        kw["want_rpa"] = True
+    plan = LH.Plan(**kw)
+    im = plan.exec()
+    res = {"im_chi": im}
+    if math.isfinite(U):
+        re, imr, rer = plan.rpa(U)
+        res.update(re_chi=re, im_rpa=imr, re_rpa=rer)
+    torch.cuda.synchronize()
+    plan.close()
+    return res
+
+
+def test_served_results_equal_alone_and_match_oracle():
+    jobs = small_jobs()
+    srv = LH.Server(hbm_budget_bytes=8 << 30, max_inflight=4, max_queue=64)
+    tickets = [srv.submit(U, **prob) for U, prob in jobs]
+    for t, _ in tickets:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st = srv.stats()
+    assert st.completed == len(jobs) and st.failed == 0
+    assert 0 < st.p50_ms <= st.p99_ms and st.points_per_s > 0
+    assert st.hbm_high_water <= 8 << 30
+    for (U, prob), (t, outs) in zip(jobs, tickets):
+        alone = run_alone(U, prob)
+        for k, v in alone.items():
+            assert torch.equal(outs[k], v), (t, k)
+    # one served job against the oracle
+    U, prob = jobs[0]
+    outs = tickets[0][1]
+    eps = oracle.band_tb(prob["t"], prob["tp"], prob["tpp"], prob["nkx"], prob["nky"])
+    mu = oracle.mu_solve(eps, prob["gamma"], prob["filling"])
+    d = (prob["emax"] - prob["emin"]) / prob["neps"]
+    lags = np.rint(np.asarray(prob["omega"]) / d).astype(int)
+    full = oracle.chi_full(eps - mu, prob["neps"], prob["emin"], prob["emax"], prob["gamma"], lags)
+    ref = oracle.extend(full, 1, 1, 0, 0.0)
+    got = outs["im_chi"].double().cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    tol = 1e-11 if prob["precision"] == LH.LINDHARD_FP64 else 1e-5
+    print("served vs oracle err %.3e" % err)
+    assert err <= tol
+    srv.close()
+
+
+def test_admission_budget_rejection_cancel_and_isolation():
+    U, prob = small_jobs(1, seed=3)[0]
+    prob = dict(prob, nkx=256, nky=256, neps=128, omega=W.lag_omegas(128, -2.0, 2.0, range(1, 33)))
+    probe = LH.Plan(**prob)
+    fp = probe.info.workspace_bytes
+    probe.close()
+    # budget for one job at a time: admission serialises them
+    srv = LH.Server(hbm_budget_bytes=int(fp * 1.5), max_inflight=4, max_queue=16)
+    good = [srv.submit(float("nan"), **prob) for _ in range(4)]
+    # a job larger than the budget is refused at submission
+    big = dict(prob, nkx=1024, nky=1024)
+    with pytest.raises(LH.LindhardError) as ei:
+        srv.submit(float("nan"), **big)
+    assert ei.value.status == LH.LINDHARD_ETOOBIG
+    # an invalid job (omega off the lag grid) is refused and poisons nothing
+    with pytest.raises(LH.LindhardError) as ei:
+        srv.submit(float("nan"), **dict(prob, omega=[0.0123]))
+    assert ei.value.status == LH.LINDHARD_EOFFGRID
+    last, _ = srv.submit(float("nan"), **prob)
+    rc = srv.cancel(last)
+    assert rc in (LH.LINDHARD_OK, LH.LINDHARD_EBUSY)
+    for t, _ in good:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st_last = srv.wait(last, 120.0)
+    assert st_last == (LH.LINDHARD_ECANCELED if rc == LH.LINDHARD_OK else LH.LINDHARD_OK)
+    st = srv.stats()
+    assert st.hbm_high_water <= int(fp * 1.5)
+    assert st.rejected == 2
+    ref = run_alone(float("nan"), prob)["im_chi"]
+    for _, outs in good:
+        assert torch.equal(outs["im_chi"], ref)
+    srv.close()
+
+
+def test_exec_batch_equals_individual_runs():
+    """Mixed-size instances run as one batch give the same bits as one by one."""
+    jobs = small_jobs(8, seed=21)
+    plans = [LH.Plan(**prob) for U, prob in jobs]
+    dtypes = {p.dtype for p in plans}
+    for dt in dtypes:
+        group = [p for p in plans if p.dtype == dt]
+        outs = LH.exec_batch(group)
+        torch.cuda.synchronize()
+        for p, o in zip(group, outs):
+            alone = p.exec()
+            torch.cuda.synchronize()
+            assert torch.equal(o, alone)
+    for p in plans:
+        p.close()
