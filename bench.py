@@ -28,22 +28,29 @@ PASS_NAMES = ["p1_build_rowfft", "p2_colfft", "p3_window", "p4_colifft", "p5_row
 KERNEL_NAMES = ["k_p1", "k_col<float, false>", "k_p3", "k_col<float, true>", "k_p5"]
 
 
-def algorithmic(cfg, info_lag_hi, fp_bytes=4):
-    """Algorithmic HBM bytes and flops per pass for one exec (FP32 sizes)."""
+def algorithmic(cfg, lag_hi, even, fp_bytes=4):
+    """Algorithmic HBM bytes per pass and flops of the energy window for one
+    exec.  General path: complex half plane (nkx/2+1) x nky per slice.  Even
+    path (mirror-symmetric band): real quarter plane (nkx/2+1) x (nky/2+1)."""
     n_x, n_y, neps = cfg["nkx"], cfg["nky"], cfg["neps"]
     nw = len(cfg["omega"])
-    half = (n_x // 2 + 1) * n_y  # complex half-spectrum points per slice
-    cb = 2 * fp_bytes
+    if even:
+        pts = (n_x // 2 + 1) * (n_y // 2 + 1)
+        vb = fp_bytes
+        flops_per_mac = 2.0
+    else:
+        pts = (n_x // 2 + 1) * n_y
+        vb = 2 * fp_bytes
+        flops_per_mac = 8.0
     nS = neps  # every slice enters the window at this workload
-    nL = info_lag_hi
-    B = half * nS * cb
-    S = half * nL * cb
+    nL = lag_hi
+    B = pts * nS * vb
+    S = pts * nL * vb
     out = n_x * n_y * nw * fp_bytes
     by = [B, 2 * B, B + S, 2 * S, S + out]
-    # energy window: per real-space point sum over lags of the window length
     j0 = neps // 2
-    cmacs = sum(min(m, j0, neps - m) for m in range(1, nL + 1))
-    fl_win = 8.0 * half * cmacs  # complex MAC = 4 mul + 4 add
+    macs = sum(min(m, j0, neps - m) for m in range(1, nL + 1))
+    fl_win = flops_per_mac * pts * macs
     return by, fl_win
 
 
@@ -54,16 +61,19 @@ def src_hash(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_src_hash):
-    """HBM traffic of the window pass from committed rocprofv3 counter runs,
-    only if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_p3_2048x2048x512.json")
+def traffic_from_profiles(kernel, kernel_src_hash):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a plain 1 GiB device copy), only if the counters were taken on
+    the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_2048x2048x512_fp32c.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_src_hash") != kernel_src_hash:
         return None
-    return d.get("traffic_bytes_per_launch")
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(cfg, nsamples=32):
@@ -86,6 +96,82 @@ def cpu_baseline(cfg, nsamples=32):
                       "1..%d, FP64 direct double sum; %.1f s wall" % (nsamples, nlag, dt)}
 
 
+def bench_batched(LH, W, torch, steps=3):
+    """64 mixed instances (k-grids 128^2..1024^2, 64..512 energies, 64 lags,
+    doping x in [0, 0.2], G in [0.01, 0.08] eV) run as one batch per step."""
+    cfgs = W.config4()
+    t0 = time.perf_counter()
+    plans = [LH.Plan(precision=LH.LINDHARD_FP32C, **c) for c in cfgs]
+    t_plan = time.perf_counter() - t0
+    outs = [p.empty() for p in plans]
+    LH.exec_batch(plans, outs)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        LH.exec_batch(plans, outs)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    points = sum(c["nkx"] * c["nky"] * len(c["omega"]) for c in cfgs)
+    for p in plans:
+        p.close()
+    del outs
+    return {"instances": len(cfgs), "ms_per_batch": ms, "points_per_batch": points,
+            "points_per_s": points / (ms * 1e-3), "plan_s_total": t_plan}
+
+
+def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
+    """Poisson stream (mean 200 req/s) of mixed jobs through the server;
+    latency = submit -> result ready, reported over the requests after warm-up."""
+    jobs = W.config5(n_req=n_warm + n_req, rate_hz=rate_hz)
+    srv = LH.Server(hbm_budget_bytes=64 << 30, max_inflight=8, max_queue=4096)
+    live = {}
+    lat = []
+    t0 = time.perf_counter()
+    done_points = 0
+
+    def reap(block=False):
+        nonlocal done_points
+        for t in list(live):
+            fin, st = srv.poll(t)
+            if fin:
+                k, t_sub, pts = live.pop(t)
+                if st == LH.LINDHARD_OK and k >= n_warm:
+                    lat.append((time.perf_counter() - t_sub) * 1e3)
+                    done_points += pts
+                srv._keep.pop(t, None)
+    t_first = None
+    for k, job in enumerate(jobs):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= job["arrival_s"]:
+                break
+            reap()
+            time.sleep(min(0.0005, job["arrival_s"] - now))
+        while len(live) > 256:  # back-pressure: queued jobs hold their outputs
+            reap()
+            time.sleep(0.0005)
+        if k == n_warm:
+            t_first = time.perf_counter()
+        ticket, outs = srv.submit(job["U"], precision=LH.LINDHARD_FP32C, **job["problem"])
+        pts = outs["im_chi"].numel()
+        live[ticket] = (k, time.perf_counter(), pts)
+    while live:
+        reap()
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t_first
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    return {"requests": n_req, "warmup_requests": n_warm, "rate_hz": rate_hz,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "points_per_s": done_points / wall, "completed": int(st.completed), "failed": int(st.failed),
+            "hbm_high_water_GB": st.hbm_high_water / 1e9, "max_inflight": 8,
+            "latency_note": "submit -> result ready, host clock, requests after warm-up"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,7 +183,15 @@ def main():
     ap.add_argument("--neps", type=int, default=512)
     ap.add_argument("--window", choices=["auto", "direct", "fft"], default="auto",
                     help="energy-window variant (auto: the plan's own choice)")
+    ap.add_argument("--general", action="store_true",
+                    help="force the general complex path even for a mirror-symmetric band")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched run")
+    ap.add_argument("--no-served", action="store_true", help="skip the served Poisson stream")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.general:
+        os.environ["LINDHARD_SYMMETRY"] = "off"
     if args.window != "auto":
         os.environ["LINDHARD_WINDOW"] = args.window
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -111,6 +205,15 @@ def main():
     from paper_1208_3210_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
     cfg = W.config3(nk=args.nk, neps=args.neps)
     print("bench: planning %dx%d k, %d energies, %d omegas" % (cfg["nkx"], cfg["nky"], cfg["neps"],
                                                              len(cfg["omega"])), file=sys.stderr, flush=True)
@@ -141,27 +244,35 @@ def main():
                                                         ", ".join("%.3f" % x for x in pass_avg)),
           file=sys.stderr, flush=True)
 
-    by, fl_win = algorithmic(cfg, plan.info.lag_hi)
+    schedule = plan.info.schedule.decode()
+    even = " even " in schedule
+    by, fl_win = algorithmic(cfg, plan.info.lag_hi, even)
     gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, pass_avg)]
     dom = int(np.argmax(pass_avg))
     src = [os.path.join(ROOT, "paper_1208_3210_amd", "csrc", f) for f in ("lh_kernels.hip", "lh_fft.h",
                                                                            "lh_regfft.h")]
     khash = src_hash(src)
-    schedule = plan.info.schedule.decode()
     fft_window = " P3 fft " in schedule
-    if fft_window:
+    if even:
+        KERNEL_NAMES[:] = ["k_e1", "k_ecol<float, false>", "k_e3", "k_ecol<float, true>", "k_e5"]
+    elif fft_window:
         KERNEL_NAMES[2] = "k_p3f"
     if dom == 2 and not fft_window:
         ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
         roof = {"kernel": KERNEL_NAMES[2], "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
-                "traffic": traffic_from_profiles(khash)}
+                "traffic": traffic_from_profiles(KERNEL_NAMES[2], khash)}
     else:
         roof = {"kernel": KERNEL_NAMES[dom], "bound": "hbm", "achieved": gbs[dom], "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM_GBS, "traffic": None}
+                "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM_GBS,
+                "traffic": traffic_from_profiles(KERNEL_NAMES[dom], khash)}
     roof["avg_ms"] = float(pass_avg[dom])
     passes = {n: {"ms": float(t), "alg_GB": b / 1e9, "GB/s": g} for n, t, b, g in zip(PASS_NAMES, pass_avg, by, gbs)}
+    for n, k in zip(PASS_NAMES, KERNEL_NAMES):
+        passes[n]["hbm_traffic_bytes"] = traffic_from_profiles(k, khash)
     passes["p3_window"]["TFLOP/s"] = fl_win / (pass_avg[2] * 1e-3) / 1e12
+    for n, k in zip(PASS_NAMES, KERNEL_NAMES):
+        passes[n]["kernel"] = k
     lat = np.array(step_ms)
 
     # plain FP64 GPU form on the same workload, and the FP32 vs FP64 error
@@ -186,6 +297,13 @@ def main():
         plan64.close()
     plan.close()
 
+    batched = None if args.no_batched else bench_batched(LH, W, torch)
+    if batched:
+        print("bench: batched %.3f ms per 64 instances" % batched["ms_per_batch"], file=sys.stderr, flush=True)
+    served = None if args.no_served else bench_served(LH, W, torch)
+    if served:
+        print("bench: served p50 %.2f ms p99 %.2f ms" % (served["p50_ms"], served["p99_ms"]), file=sys.stderr,
+              flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
     res = {
         "metric": "chi(q,w) points/s at 2048^2 k x 512 eps, FP32 vs FP64 at <=1e-5 rel",
@@ -196,7 +314,8 @@ def main():
                    "neps": cfg["neps"], "nomega": len(cfg["omega"]), "gamma_eV": cfg["gamma"],
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": roof, "passes": passes, "fp64_gpu": fp64, "cpu_baseline": cpu,
+        "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
+        "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }
     print(json.dumps(res), flush=True)

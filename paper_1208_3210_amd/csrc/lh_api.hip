@@ -6,7 +6,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -30,6 +32,23 @@ static int count_occupied(int neps, double emin, double emax)
     for (int j = 0; j < neps; ++j)
         if (emin + (j + 0.5) * d <= 0.0) ++j0;
     return j0;
+}
+
+static void describe_schedule(Plan &pl)
+{
+    const Geo &g = pl.g;
+    char buf[96];
+    const char *tn = g.tuned == 1 ? " tuned" : g.tuned == 2 ? " cached" : "";
+    if (g.even)
+        std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 direct TR%d%s P5 R%d%s",
+                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc, g.e3_TR, tn, g.e5_R,
+                      pl.p.want_rpa ? " +kk/rpa" : "");
+    else
+        std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d%s P5 R%d%s",
+                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.p1_R, g.p1_jc,
+                      g.p3_variant ? "fft" : "direct", g.p3_variant ? g.p3f_TR : g.p3_TR, tn, g.p5_R,
+                      pl.p.want_rpa ? " +kk/rpa" : "");
+    pl.schedule = buf;
 }
 
 lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
@@ -201,7 +220,8 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         const int Ex = std::min(16, p->nkx), Gx = p->nkx / Ex;
         const int np = (g.Hy + 1) / 2;
         int R = std::max(1, 256 / Gx);
-        while (R > 1 && (size_t)R * p->nkx * cs > 65536) R >>= 1;
+        // LDS: R line buffers of nkx complex (+ the FP32 twiddle table)
+        while (R > 1 && (size_t)(R + (g.fp64 ? 0 : 1)) * p->nkx * cs > 65536) R >>= 1;
         R = std::min(R, 1 << ilog2(np));
         if ((1 << ilog2(np)) > np) R = std::min(R, 1 << (ilog2(np) - 1));
         g.e1_R = std::max(1, R);
@@ -217,13 +237,13 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         int TR = 64;
         for (; TR > 1; TR >>= 1) {
             const int SU = 64 / TR;
-            const int PL = std::min(HL, g.j0 - g.jA) + SU + 16;
-            const int HP = 32 + SU;
+            const int PL = std::min(HL, g.j0 - g.jA) + 16 * SU + 16;
+            const int HP = 16 * SU + 32;
             if ((size_t)(PL + HP + HL) * TR * es <= 65536) break;
         }
         g.e3_TR = TR;
         g.e3_logTR = ilog2(TR);
-        g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 64 / TR + 16);
+        g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 16 * (64 / TR) + 16);
     }
 
     pl.zx = p->zones_x;
@@ -235,17 +255,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.scale = -pl.deps / ((double)nk * (double)nk);
     pl.ff_s = p->ff_kind == LINDHARD_FF_GAUSS_DX2Y2 ? p->ff_width * p->ff_width / 4.0 : 0.0;
     pl.ws_bytes = plan_footprint(pl);
-    char buf[96];
-    if (g.even)
-        std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 direct TR%d P5 R%d%s",
-                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc, g.e3_TR, g.e5_R,
-                      p->want_rpa ? " +kk/rpa" : "");
-    else
-        std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d P5 R%d%s",
-                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.p1_R, g.p1_jc,
-                      g.p3_variant ? "fft" : "direct", g.p3_variant ? g.p3f_TR : g.p3_TR, g.p5_R,
-                      p->want_rpa ? " +kk/rpa" : "");
-    pl.schedule = buf;
+    describe_schedule(pl);
     return LINDHARD_OK;
 }
 
@@ -270,15 +280,98 @@ size_t plan_footprint(const Plan &pl)
     return b;
 }
 
+// ------------------------------------------------------------ device pool
+// Plans take their device buffers from a per-process pool of exact-size
+// buckets instead of hipMalloc / hipFree: a served job then allocates
+// nothing in the common case, and no hipFree (which waits for the whole
+// device) sits between concurrent jobs.  Buffers return to the pool when the
+// plan is destroyed, after its last work has completed.  Sizes are rounded up
+// (power of two below 1 MiB, 1 MiB multiples above); the pool keeps at most
+// LINDHARD_POOL_LIMIT bytes (default 64 GiB) of idle buffers.
+namespace {
+std::mutex g_dpool_mu;
+std::multimap<std::pair<int, size_t>, void *> g_dpool;
+size_t g_dpool_idle = 0;
+
+size_t pool_round(size_t b)
+{
+    if (b == 0) b = 256;
+    if (b < (1u << 20)) {
+        size_t r = 256;
+        while (r < b) r <<= 1;
+        return r;
+    }
+    return (b + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+}
+
+size_t pool_limit()
+{
+    const char *e = std::getenv("LINDHARD_POOL_LIMIT");
+    return e ? (size_t)std::strtoull(e, nullptr, 10) : ((size_t)64 << 30);
+}
+}  // namespace
+
+static hipError_t pool_alloc(void **p, size_t bytes, int device)
+{
+    const size_t b = pool_round(bytes);
+    {
+        std::lock_guard<std::mutex> lk(g_dpool_mu);
+        auto it = g_dpool.find({device, b});
+        if (it != g_dpool.end()) {
+            *p = it->second;
+            g_dpool.erase(it);
+            g_dpool_idle -= b;
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, b);
+    if (e == hipErrorOutOfMemory) {
+        // give idle buffers back to the device and retry once
+        std::vector<void *> drop;
+        {
+            std::lock_guard<std::mutex> lk(g_dpool_mu);
+            for (auto it = g_dpool.begin(); it != g_dpool.end();) {
+                if (it->first.first == device) {
+                    drop.push_back(it->second);
+                    g_dpool_idle -= it->first.second;
+                    it = g_dpool.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        (void)hipGetLastError();
+        for (void *q : drop) (void)hipFree(q);
+        e = hipMalloc(p, b);
+    }
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+static void pool_free(void *p, size_t bytes, int device)
+{
+    if (!p) return;
+    const size_t b = pool_round(bytes);
+    bool keep = false;
+    {
+        std::lock_guard<std::mutex> lk(g_dpool_mu);
+        if (g_dpool_idle + b <= pool_limit()) {
+            g_dpool.insert({{device, b}, p});
+            g_dpool_idle += b;
+            keep = true;
+        }
+    }
+    if (!keep) (void)hipFree(p);
+}
+
 void plan_free(Plan &pl)
 {
+    for (auto &a : pl.allocs) pool_free(a.first, a.second, pl.device);
+    pl.allocs.clear();
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_slot, (void **)&pl.d_lag, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch};
-    for (void **p : ptrs) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
+    for (void **p : ptrs) *p = nullptr;
 }
 
 #define LH_TRY(x)                                                                                         \
@@ -287,14 +380,173 @@ void plan_free(Plan &pl)
         if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? LINDHARD_ENOMEM : LINDHARD_EDEVICE;       \
     } while (0)
 
-static lindhard_status dalloc(void **p, size_t bytes)
+static lindhard_status dalloc(Plan &pl, void **p, size_t bytes)
 {
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = pool_alloc(p, bytes, pl.device);
     if (e != hipSuccess) {
-        *p = nullptr;
         (void)hipGetLastError();
         return e == hipErrorOutOfMemory ? LINDHARD_ENOMEM : LINDHARD_EDEVICE;
+    }
+    pl.allocs.push_back({*p, bytes});
+    return LINDHARD_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// The energy-window pass has several schedules: the direct and the energy-FFT
+// form on the general path, and the points-per-block width on the even path.
+// The first plan of a shape times each candidate on its own workspace (the
+// timing does not depend on the data) and keeps the fastest; the decision is
+// cached per process, and in the text file LINDHARD_TUNE_CACHE if set.
+// LINDHARD_AUTOTUNE=0 keeps the built-in heuristics; LINDHARD_WINDOW forces
+// the general-path form.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;  // key -> (variant, TR)
+bool g_tune_loaded = false;
+
+bool even_tr_fits(const Geo &g, int TR);
+
+std::string tune_key(const Geo &g)
+{
+    char b[160];
+    // the widest points-per-block that fits LDS fixes the candidate set
+    int maxfit = 0;
+    if (g.even)
+        for (int TR = 64; TR >= 1 && !maxfit; TR >>= 1)
+            if (even_tr_fits(g, TR)) maxfit = TR;
+    // lag ranges are bucketed (32 lags) so that served jobs of one grid share
+    // decisions; a cached width that does not fit the plan is re-timed
+    std::snprintf(b, sizeof b, "w3 %d %d %d %d %d %d %d %d %d", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0, g.m_lo,
+                  (g.m_hi + 31) / 32, maxfit);
+    return b;
+}
+
+void tune_load_file()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("LINDHARD_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char *bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        int v = 0, tr = 0;
+        if (std::sscanf(bar + 1, "%d %d", &v, &tr) == 2) g_tune[line] = {v, tr};
+    }
+    std::fclose(f);
+}
+
+void tune_store_file(const std::string &key, int v, int tr)
+{
+    const char *path = std::getenv("LINDHARD_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s|%d %d\n", key.c_str(), v, tr);
+    std::fclose(f);
+}
+
+int ilog2c(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+void set_even_tr(Geo &g, int TR)
+{
+    const int nB = (g.nL + 15) / 16;
+    const int HL = g.m_lo + 16 * nB - 1;
+    g.e3_TR = TR;
+    g.e3_logTR = ilog2c(TR);
+    g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 16 * (64 / TR) + 16);
+}
+
+bool even_tr_fits(const Geo &g, int TR)
+{
+    const int nB = (g.nL + 15) / 16;
+    const int HL = g.m_lo + 16 * nB - 1;
+    const int SU = 64 / TR;
+    const size_t es = g.fp64 ? 8 : 4;
+    const int PL = std::min(HL, g.j0 - g.jA) + 16 * SU + 16;
+    return (size_t)(PL + 16 * SU + 32 + HL) * TR * es <= 65536;
+}
+}  // namespace
+
+static lindhard_status autotune_window(Plan &pl, hipStream_t st)
+{
+    Geo &g = pl.g;
+    if (g.nL == 0) return LINDHARD_OK;
+    const char *at = std::getenv("LINDHARD_AUTOTUNE");
+    if (at && !std::strcmp(at, "0")) return LINDHARD_OK;
+    const bool forced = !g.even && std::getenv("LINDHARD_WINDOW") != nullptr;
+    if (forced) return LINDHARD_OK;
+    const std::string key = tune_key(g);
+    // One decision per shape for the whole process: the lock is held while a
+    // shape is timed, so concurrent plans of that shape (served jobs) wait and
+    // then take the same schedule, which keeps their results bit-identical.
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_file();
+    {
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && (!g.even || even_tr_fits(g, it->second.second))) {
+            if (g.even)
+                set_even_tr(g, it->second.second);
+            else
+                g.p3_variant = it->second.first;
+            g.tuned = 2;
+            return LINDHARD_OK;
+        }
+    }
+    std::vector<std::pair<int, int>> cands;
+    if (g.even) {
+        for (int TR = 64; TR >= 1 && cands.size() < 3; TR >>= 1)
+            if (even_tr_fits(g, TR)) cands.push_back({0, TR});
+    } else {
+        cands.push_back({0, 0});
+        cands.push_back({1, 0});
+    }
+    if (cands.size() > 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        LH_TRY(hipEventCreate(&e0));
+        LH_TRY(hipEventCreate(&e1));
+        float best = 1e30f;
+        std::pair<int, int> pick = cands[0];
+        const Geo keep = g;
+        for (const auto &c : cands) {
+            if (g.even)
+                set_even_tr(g, c.second);
+            else
+                g.p3_variant = c.first;
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                LH_TRY(hipEventRecord(e0, st));
+                LH_TRY(launch_window(pl, st));
+                LH_TRY(hipEventRecord(e1, st));
+                LH_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                LH_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) tmin = std::min(tmin, ms);
+            }
+            if (tmin < best) {
+                best = tmin;
+                pick = c;
+            }
+            g = keep;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (g.even)
+            set_even_tr(g, pick.second);
+        else
+            g.p3_variant = pick.first;
+        g.tuned = 1;
+        g_tune[key] = pick;
+        tune_store_file(key, pick.first, pick.second);
     }
     return LINDHARD_OK;
 }
@@ -339,7 +591,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     lindhard_status s;
 #define LH_ALLOC(ptr, bytes)                                 \
     do {                                                     \
-        s = dalloc((void **)&(ptr), (bytes));                \
+        s = dalloc(pl, (void **)&(ptr), (bytes));            \
         if (s != LINDHARD_OK) return s;                      \
     } while (0)
     LH_ALLOC(pl.xi, nk * 8);
@@ -371,13 +623,27 @@ struct lindhard_plan_s {
     hipEvent_t done = nullptr;  // recorded after each exec / rpa
 };
 
+// One setup stream per host thread and device, kept for the life of the
+// thread: plans built on a thread reuse it (plan building is synchronous).
+static hipStream_t thread_setup_stream(int device)
+{
+    thread_local std::vector<std::pair<int, hipStream_t>> streams;
+    for (auto &d : streams)
+        if (d.first == device) return d.second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams.push_back({device, st});
+    return st;
+}
+
 static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_plan_s *o)
 {
     Plan &pl = o->pl;
     lindhard_status s = plan_describe(p, pl);
     if (s != LINDHARD_OK) return s;
     if (hipGetDevice(&pl.device) != hipSuccess) return LINDHARD_EDEVICE;
-    if (hipStreamCreateWithFlags(&o->setup, hipStreamNonBlocking) != hipSuccess) return LINDHARD_EDEVICE;
+    o->setup = thread_setup_stream(pl.device);
+    if (!o->setup) return LINDHARD_EDEVICE;
     if (hipEventCreateWithFlags(&o->done, hipEventDisableTiming) != hipSuccess) return LINDHARD_EDEVICE;
     hipStream_t st = o->setup;
     s = plan_build(pl, st);
@@ -409,6 +675,9 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     if (pl.p.want_rpa)
         LH_TRY(hipMemsetAsync(pl.im1, 0, (size_t)pl.g.neps * nk * pl.elem_bytes, st));
     LH_TRY(hipStreamSynchronize(st));
+    s = autotune_window(pl, st);
+    if (s != LINDHARD_OK) return s;
+    describe_schedule(pl);
     return LINDHARD_OK;
 }
 
@@ -424,7 +693,6 @@ lindhard_status lindhard_plan(const lindhard_problem *p, lindhard_plan_t *out)
     if (s != LINDHARD_OK) {
         if (o->setup) (void)hipStreamSynchronize(o->setup);
         plan_free(o->pl);
-        if (o->setup) (void)hipStreamDestroy(o->setup);
         if (o->done) (void)hipEventDestroy(o->done);
         delete o;
         (void)hipGetLastError();
@@ -535,7 +803,48 @@ BatchPool *batch_pool(int device)
     return bp;
 }
 std::mutex g_batch_mu;  // one batch at a time per process (the pool is shared)
+
+// Captured batches: the fork / launches / join sequence of a batch is captured
+// once into a HIP graph and replayed when the same plans and outputs come
+// again (one graph launch instead of five kernels per instance).  A graph is
+// dropped when one of its plans is destroyed.  LINDHARD_BATCH_GRAPH=0 keeps
+// eager launches.
+struct BatchGraph {
+    std::vector<const void *> sig;
+    hipGraphExec_t exec = nullptr;
+};
+std::vector<BatchGraph> g_graphs;
+hipStream_t g_capture_stream = nullptr;
+
+bool batch_graphs_enabled()
+{
+    const char *e = std::getenv("LINDHARD_BATCH_GRAPH");
+    return !(e && !std::strcmp(e, "0"));
+}
 }  // namespace
+
+// Fork the instances over the worker streams and join them back into `origin`.
+static hipError_t batch_launch(BatchPool *bp, const lindhard_plan_t *plans, int n, void *const *outs,
+                               hipStream_t origin)
+{
+    hipError_t e = hipEventRecord(bp->fork, origin);
+    const int ns = std::min(n, kBatchStreams);
+    for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(bp->st[i], bp->fork, 0);
+    // largest instances first, round-robin over the worker streams
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return plans[a]->pl.out_elems > plans[b]->pl.out_elems; });
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        const int i = order[k];
+        e = launch_exec(plans[i]->pl, outs[i], bp->st[k % ns]);
+    }
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        e = hipEventRecord(bp->join[i], bp->st[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin, bp->join[i], 0);
+    }
+    return e;
+}
 
 lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs, void *stream)
 {
@@ -551,32 +860,58 @@ lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, voi
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchPool *bp = batch_pool(pdev);
     hipStream_t caller = (hipStream_t)stream;
-    hipError_t e = bp ? hipEventRecord(bp->fork, caller) : hipErrorOutOfMemory;
-    const int ns = std::min(n, kBatchStreams);
-    for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(bp->st[i], bp->fork, 0);
-    // largest instances first, round-robin over the worker streams
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return plans[a]->pl.out_elems > plans[b]->pl.out_elems; });
-    for (int k = 0; k < n && e == hipSuccess; ++k) {
-        const int i = order[k];
-        hipStream_t s = bp->st[k % ns];
-        e = launch_exec(plans[i]->pl, outs[i], s);
-        if (e == hipSuccess) e = hipEventRecord(plans[i]->done, s);
-        if (e == hipSuccess) plans[i]->pl.executed = true;
+    hipError_t e = bp ? hipSuccess : hipErrorOutOfMemory;
+    std::vector<const void *> sig;
+    sig.reserve(2 * n + 1);
+    sig.push_back((const void *)(intptr_t)pdev);
+    for (int i = 0; i < n; ++i) {
+        sig.push_back(plans[i]);
+        sig.push_back(outs[i]);
     }
-    for (int i = 0; i < ns && e == hipSuccess; ++i) {
-        e = hipEventRecord(bp->join[i], bp->st[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(caller, bp->join[i], 0);
+    hipGraphExec_t gexec = nullptr;
+    if (e == hipSuccess && batch_graphs_enabled()) {
+        for (const BatchGraph &bg : g_graphs)
+            if (bg.sig == sig) gexec = bg.exec;
+        if (!gexec) {
+            if (!g_capture_stream) e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+            hipGraph_t graph = nullptr;
+            if (e == hipSuccess) e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t el = batch_launch(bp, plans, n, outs, g_capture_stream);
+                e = hipStreamEndCapture(g_capture_stream, &graph);
+                if (e == hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess) g_graphs.push_back({sig, gexec});
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(gexec, caller);
+    } else if (e == hipSuccess) {
+        e = batch_launch(bp, plans, n, outs, caller);
+    }
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipEventRecord(plans[i]->done, caller);
+        plans[i]->pl.executed = true;
     }
     if (dev != pdev) (void)hipSetDevice(dev);
+    if (e != hipSuccess) (void)hipGetLastError();
     return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
 }
 
 lindhard_status lindhard_plan_destroy(lindhard_plan_t plan)
 {
     if (!plan) return LINDHARD_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        for (size_t i = 0; i < g_graphs.size();) {
+            if (std::find(g_graphs[i].sig.begin(), g_graphs[i].sig.end(), (const void *)plan) != g_graphs[i].sig.end()) {
+                (void)hipGraphExecDestroy(g_graphs[i].exec);
+                g_graphs.erase(g_graphs.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipSetDevice(plan->pl.device);
@@ -586,7 +921,6 @@ lindhard_status lindhard_plan_destroy(lindhard_plan_t plan)
     }
     if (plan->setup) (void)hipStreamSynchronize(plan->setup);
     plan_free(plan->pl);
-    if (plan->setup) (void)hipStreamDestroy(plan->setup);
     (void)hipSetDevice(dev);
     delete plan;
     return LINDHARD_OK;

@@ -52,6 +52,7 @@ struct Geo {
     int p3_variant;
     int logNE;                // FFT length along energy for variant 1
     int p3f_TR, p3f_logTR;    // real-space points per block for variant 1
+    int tuned;                // 1: window schedule chosen by timing, 2: from the tuning cache
 };
 
 struct Plan {
@@ -80,6 +81,7 @@ struct Plan {
     double *kkw = nullptr;     // RPA: Kramers-Kronig weights [nomega][neps]
     double *scratch = nullptr; // mu-solve partial sums
     size_t ws_bytes = 0;
+    std::vector<std::pair<void *, size_t>> allocs;  // pooled device buffers
     bool executed = false;
     std::string schedule;
 };
@@ -95,6 +97,7 @@ size_t plan_footprint(const Plan &pl);
 // Pass launchers (asynchronous on `st`).
 hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev = nullptr);
 hipError_t launch_rpa(const Plan &pl, double U, void *re, void *imr, void *rer, hipStream_t st);
+hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
 
 // Setup kernels.
 hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st);

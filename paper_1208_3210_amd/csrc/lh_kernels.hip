@@ -135,6 +135,24 @@ __global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const 
     w[idx] = v;
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Map launch index b to a logical tile so that consecutive logical tiles run
+// on the same XCD: tiles sharing cache lines then meet in the same L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks)
+{
+    const unsigned per = nblocks >> 3;          // full rounds of 8
+    if (b >= (per << 3)) return b;              // ragged tail keeps its index
+    return (b & 7) * per + (b >> 3);
+}
+
+// Lorentzian of Eq. (5) from the (already rounded) argument d = e_j - xi_k:
+// (gamma/pi) / (d^2 + gamma^2).  FP32 uses the hardware reciprocal (1 ulp).
+__device__ __forceinline__ float lorentz(float d, float gp, float g2)
+{
+    return gp * __builtin_amdgcn_rcpf(d * d + g2);
+}
+__device__ __forceinline__ double lorentz(double d, double gp, double g2) { return gp / (d * d + g2); }
+
 // |M(Q)|^2 = F(Q)^2 at extended (X, Y), Eq. (3) for the Gaussian d orbital.
 __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2 fy, double s)
 {
@@ -188,7 +206,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
-            v[s] = mk<T>(gp / (d0 * d0 + g2), gp / (d1 * d1 + g2));
+            v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
         F::run(v, buf, twx, 1, gg, row);
 #pragma unroll
@@ -274,9 +292,17 @@ __global__ void __launch_bounds__(kThreads) k_p3(cx<T> *__restrict__ spec, Geo g
     const int tid = threadIdx.x;
     const size_t off = ((size_t)blockIdx.x * g.nky + (size_t)blockIdx.y * g.p3_RY) << g.logC;
     const int ne = g.nS;
-    for (int it = tid; it < (ne << logTR); it += kThreads) {
-        const int s = it >> logTR, rp = it & (TR - 1);
-        buf[it] = spec[(size_t)s * g.slice_elems + off + rp];
+    for (int it0 = tid; it0 < (ne << logTR); it0 += 8 * kThreads) {
+        cx<T> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * kThreads;
+            const int s = it >> logTR, rp = it & (TR - 1);
+            v[k] = spec[it < (ne << logTR) ? (size_t)s * g.slice_elems + off + rp : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (it0 + k * kThreads < (ne << logTR)) buf[it0 + k * kThreads] = v[k];
     }
     __syncthreads();
 
@@ -397,9 +423,17 @@ __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, co
     const int ne = g.nS;
     const int j0 = g.j0 - g.jA;
     const int nthr = TR * G;
-    for (int it = tid; it < (ne << logTR); it += nthr) {
-        const int sl = it >> logTR, p = it & (TR - 1);
-        lds[it] = spec[(size_t)sl * g.slice_elems + off + p];
+    for (int it0 = tid; it0 < (ne << logTR); it0 += 8 * nthr) {
+        cx<T> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * nthr;
+            const int sl = it >> logTR, p = it & (TR - 1);
+            v[k] = spec[it < (ne << logTR) ? (size_t)sl * g.slice_elems + off + p : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (it0 + k * nthr < (ne << logTR)) lds[it0 + k * nthr] = v[k];
     }
     __syncthreads();
     const cx<T> zero = mk<T>((T)0, (T)0);
@@ -471,12 +505,24 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int C = g.C, logC = g.logC;
     const cx<T> *src = spec + (size_t)slot * g.slice_elems;
     const int nin = g.NT * (R << logC);
-    for (int it = tid; it < nin; it += nthr) {
-        const int c = it & (C - 1);
-        const int r = (it >> logC) & (R - 1);
-        const int tile = it >> (logC + logR);
-        const int k = tile * C + c;
-        if (k <= L) lds[r * (L + 1) + k] = src[((size_t)tile * nky + qy0 + r) * C + c];
+    for (int it0 = tid; it0 < nin; it0 += 8 * nthr) {
+        cx<T> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * nthr;
+            const int c = it & (C - 1);
+            const int r = (it >> logC) & (R - 1);
+            const int tile = it >> (logC + logR);
+            v[k] = src[it < nin ? ((size_t)tile * nky + qy0 + r) * C + c : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * nthr;
+            const int c = it & (C - 1);
+            const int r = (it >> logC) & (R - 1);
+            const int kk = (it >> (logC + logR)) * C + c;
+            if (it < nin && kk <= L) lds[r * (L + 1) + kk] = v[k];
+        }
     }
     __syncthreads();
     cx<T> *xb = lds + row * (L + 1);
@@ -550,6 +596,14 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
     const int jbeg = g.jA + blockIdx.y * g.e1_jc;
     const int jend = min(g.jB, jbeg + g.e1_jc);
     cx<T> *buf = lds + line * N;
+    // FP32: the twiddle table lives in LDS after the line buffers
+    const cx<T> *tw = twx;
+    if (sizeof(T) == 4) {
+        cx<T> *twl = lds + R * N;
+        for (int i = tid; i < N; i += R * G) twl[i] = twx[i];
+        tw = twl;
+        __syncthreads();
+    }
     double xa[E], xb[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -558,7 +612,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
     }
     const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
     const int Ce = g.Ce, logCe = g.logCe, H = N / 2;
-    const int rows = 2 * R;
+    const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
     const int nout = g.NTe * rows * Ce;
     for (int j = jbeg; j < jend; ++j) {
         const double ej = emin + (j + 0.5) * deps;
@@ -566,17 +620,17 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
-            v[s] = mk<T>(gp / (d0 * d0 + g2), gp / (d1 * d1 + g2));
+            v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
-        F::run(v, buf, twx, 0, gg, line);
+        F::run(v, buf, tw, 0, gg, line);
 #pragma unroll
         for (int s = 0; s < E; ++s) buf[gg + s * G] = v[s];
         __syncthreads();
         T *dst = spec + (size_t)(j - g.jA) * g.slice_e;
         for (int it = tid; it < nout; it += R * G) {
             const int c = it & (Ce - 1);
-            const int r = (it >> logCe) % rows;
-            const int tile = (it >> logCe) / rows;
+            const int r = (it >> logCe) & (rows - 1);
+            const int tile = (it >> logCe) >> logRows;
             const int rx = tile * Ce + c;
             const int ky = 2 * p0 + r;
             if (ky >= g.Hy) continue;
@@ -629,103 +683,131 @@ __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const
 // Energy window (even, direct): S(r, m) = sum_j B(r, j) B(r, j + m), real.
 // With P'[a] = B(j0 - 1 - a) (occupied, reversed) and H'[x] = B(j0 + x)
 // (unoccupied), S(m) = sum_{a=0}^{m-1} P'[a] H'[m-1-a]: a linear convolution.
-// Both arrays are staged in LDS with zero padding, so the inner loop has no
-// masks.  One block: TR consecutive points of the flattened slice; lanes are
-// TR points x SU sub-ranges of a; each wave takes blocks of 16 lags held in
-// registers with a 16-value sliding window of H'.  COMP: blocks of 16 products
-// summed in T, folded into a two-sum (hi, lo) accumulator, partials merged
-// with two-sum across lanes.
-template <typename T, bool COMP>
+// Both arrays are staged in LDS with zero padding.  One block: TR consecutive
+// points of the flattened slice; lanes are TR points x SU = 64/TR sub-ranges
+// of a (lengths 1 mod 4, so the SU lane groups read different LDS bank
+// quarters; only the last chunk of a sub-range is masked); each wave takes
+// blocks of 16 lags held in registers with a 16-value sliding window of H'
+// (16 FMAs per two LDS reads).  Products are summed in T over 32 steps; the
+// block sums are accumulated in FP64 (compensating the FP32 partial sums) and
+// the lane partials are merged in FP64.  COMP selects nothing else today: the
+// FP64 instantiation sums in FP64 throughout.
+template <typename T, bool COMP, int TR>
 __global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
 {
+    constexpr int SU = 64 / TR;
+    constexpr int HP = 16 * SU + 32;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
-    const int TR = g.e3_TR, logTR = g.e3_logTR;
-    const int PL = g.e3_PL, HP = 32 + (64 >> logTR), HL = g.m_lo + 16 * ((g.nL + 15) >> 4) - 1;
+    const int PL = g.e3_PL, HL = g.m_lo + 16 * ((g.nL + 15) >> 4) - 1;
     T *Pz = lds;                    // [PL][TR]
-    T *Hz = lds + (size_t)PL * TR;  // [HP + HL][TR], index (HP + x)
+    T *Hz = lds + (size_t)PL * TR;  // [HP + HL][TR], row (HP + x)
     const int tid = threadIdx.x;
-    const size_t p0 = (size_t)blockIdx.x * TR;
+    const size_t p0 = (size_t)xcd_tile(blockIdx.x, gridDim.x) * TR;
     const int ne = g.nS, j0 = g.j0 - g.jA;
     const size_t sl = g.slice_e;
-    for (int it = tid; it < (PL << logTR); it += kThreads) {
-        const int a = it >> logTR, p = it & (TR - 1);
-        const size_t pt = p0 + p;
-        T v = (T)0;
-        if (a < j0 && pt < sl) v = spec[(size_t)(j0 - 1 - a) * sl + pt];
-        Pz[it] = v;
-    }
-    for (int it = tid; it < ((HP + HL) << logTR); it += kThreads) {
-        const int x = (it >> logTR) - HP, p = it & (TR - 1);
-        const size_t pt = p0 + p;
-        T v = (T)0;
-        if (x >= 0 && j0 + x < ne && pt < sl) v = spec[(size_t)(j0 + x) * sl + pt];
-        Hz[it] = v;
+    // Stage P' and H' with batches of independent loads (clamped addresses,
+    // select afterwards) so that the loads of one thread overlap.
+    {
+        constexpr int UNR = 8;
+        const int nP = PL * TR, nH = (HP + HL) * TR;
+        for (int it0 = tid; it0 < nP + nH; it0 += UNR * kThreads) {
+            T v[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const int it = it0 + k * kThreads;
+                const bool inP = it < nP;
+                const int row = inP ? it / TR : (it - nP) / TR;
+                const int p = it % TR;
+                const size_t pt = p0 + p;
+                int js;
+                bool ok;
+                if (inP) {
+                    js = j0 - 1 - row;
+                    ok = row < j0;
+                } else {
+                    js = j0 + row - HP;
+                    ok = row >= HP && js < ne;
+                }
+                ok = ok && it < nP + nH && pt < sl;
+                const size_t src = ok ? (size_t)js * sl + pt : 0;
+                const T x = spec[src];
+                v[k] = ok ? x : (T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const int it = it0 + k * kThreads;
+                if (it < nP + nH) lds[it] = v[k];
+            }
+        }
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
-    const int p = lane & (TR - 1);
-    const int su = lane >> logTR;
-    const int SU = 64 >> logTR;
+    const int p = lane % TR;
+    const int su = lane / TR;
     const int nB = (g.nL + 15) >> 4;
     for (int b = wave; b < nB; b += kThreads / 64) {
         const int mf = g.m_lo + 16 * b;
         const int Atot = min(mf + 15, j0);
-        T hi[16], lo[16];
+        double acc[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            hi[i] = (T)0;
-            lo[i] = (T)0;
-        }
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0;
         if (Atot > 0) {
-            const int cl = (Atot + SU - 1) / SU;
-            const int nit = (cl + 15) & ~15;
+            // sub-range length cl = 1 (mod 4) puts the SU lane groups on
+            // different LDS bank quarters; the last chunk is masked
+            int cl = (Atot + SU - 1) / SU;
+            if (SU > 1) cl += (1 - cl) & 3;
+            const int nfull = cl >> 4;
             const int as = su * cl;
-            // window slot (i - u) & 15 holds H'[base + i - u], base = mf - 1 - a
-            const int base0 = mf - 1 - as;
+            // window slot (i - u) & 15 holds H'[mf - 1 - a + i], a = as + step
+            const T *pp = Pz + as * TR + p;
+            const T *hp = Hz + (HP + mf - 1 - as) * TR + p;
             T w[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) w[i] = Hz[((HP + base0 + i) << logTR) + p];
-            for (int u0 = 0; u0 < nit; u0 += 16) {
-                T tmp[16];
+            for (int i = 0; i < 16; ++i) w[i] = hp[i * TR];
+            T tmp[16];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) tmp[i] = (T)0;
+            for (int i = 0; i < 16; ++i) tmp[i] = (T)0;
+            for (int c = 0; c <= nfull; ++c) {
+                const int rem = c < nfull ? 16 : cl - 16 * nfull;  // wave-uniform
+                if (rem == 0) break;
+                hp -= 16 * TR;
+                if (rem == 16) {
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int a = as + u0 + u;
-                    T pv = Pz[(a << logTR) + p];
-                    if (u0 + u >= cl) pv = (T)0;  // end of this lane's sub-range
+                    for (int u = 0; u < 16; ++u) {
+                        const T pv = pp[u * TR];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) tmp[i] += pv * w[(i - u) & 15];
-                    w[(15 - u) & 15] = Hz[((HP + base0 - u0 - u - 1) << logTR) + p];
+                        for (int i = 0; i < 16; ++i) tmp[i] += pv * w[(i - u) & 15];
+                        w[(15 - u) & 15] = hp[(15 - u) * TR];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const T pv = u < rem ? pp[u * TR] : (T)0;
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) tmp[i] += pv * w[(i - u) & 15];
+                        w[(15 - u) & 15] = hp[(15 - u) * TR];
+                    }
                 }
+                pp += 16 * TR;
+                if ((c & 1) || c + 1 >= nfull + (cl > 16 * nfull ? 1 : 0)) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    if (COMP)
-                        two_sum(hi[i], lo[i], tmp[i]);
-                    else
-                        hi[i] += tmp[i];
+                    for (int i = 0; i < 16; ++i) {
+                        acc[i] += (double)tmp[i];
+                        tmp[i] = (T)0;
+                    }
                 }
             }
         }
         for (int o = TR; o < 64; o <<= 1) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const T oh = __shfl_xor(hi[i], o, 64);
-                if (COMP) {
-                    const T ol = __shfl_xor(lo[i], o, 64);
-                    two_sum(hi[i], lo[i], oh);
-                    lo[i] += ol;
-                } else {
-                    hi[i] += oh;
-                }
-            }
+            for (int i = 0; i < 16; ++i) acc[i] += __shfl_xor(acc[i], o, 64);
         }
         if (su == 0 && p0 + p < sl) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int m = mf + i;
-                if (m <= g.m_hi) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = COMP ? hi[i] + lo[i] : hi[i];
+                if (m <= g.m_hi) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = (T)acc[i];
             }
         }
     }
@@ -755,7 +837,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int p0 = blockIdx.x * R;
     const int slot = MODE == 0 ? plane_slot[plane] : plane;
     const int nkx = g.nkx, nky = g.nky, Hy = g.Hy, H = N / 2, SW = H + 1;
-    const int rows = 2 * R;
+    const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
 
     if (MODE == 0 && slot < 0) {
         for (int rz = 0; rz < rows * 2 * zy; ++rz) {
@@ -772,13 +854,33 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int Ce = g.Ce, logCe = g.logCe;
     const T *src = spec + (size_t)slot * g.slice_e;
     const int nin = g.NTe * rows * Ce;
-    for (int it = tid; it < nin; it += nthr) {
-        const int c = it & (Ce - 1);
-        const int r = (it >> logCe) % rows;
-        const int tile = (it >> logCe) / rows;
-        const int rx = tile * Ce + c;
-        const int qy = 2 * p0 + r;
-        if (rx <= H) stage[r * SW + rx] = qy < Hy ? src[((size_t)tile * Hy + qy) * Ce + c] : (T)0;
+    const cx<T> *tw = twx;
+    if (sizeof(T) == 4) {
+        cx<T> *twl = lds + R * N;
+        for (int i = tid; i < N; i += nthr) twl[i] = twx[i];
+        tw = twl;  // made visible by the barrier after the staging loop
+    }
+    for (int it0 = tid; it0 < nin; it0 += 8 * nthr) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * nthr;
+            const int c = it & (Ce - 1);
+            const int r = (it >> logCe) & (rows - 1);
+            const int tile = (it >> logCe) >> logRows;
+            const int qy = 2 * p0 + r;
+            const bool ok = it < nin && qy < Hy;
+            const T x = src[ok ? ((size_t)tile * Hy + qy) * Ce + c : 0];
+            v[k] = ok ? x : (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * nthr;
+            const int c = it & (Ce - 1);
+            const int r = (it >> logCe) & (rows - 1);
+            const int rx = ((it >> logCe) >> logRows) * Ce + c;
+            if (it < nin && rx <= H) stage[r * SW + rx] = v[k];
+        }
     }
     __syncthreads();
     cx<T> v[E];
@@ -789,7 +891,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
         v[s] = mk<T>(stage[(2 * line) * SW + rr], stage[(2 * line + 1) * SW + rr]);
     }
     __syncthreads();
-    F::run(v, lds + line * N, twx, 0, gg, line);
+    F::run(v, lds + line * N, tw, 0, gg, line);
 
     const T sc = (T)scale;
     for (int half = 0; half < 2; ++half) {
@@ -859,9 +961,17 @@ __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int 
     const int QT = 1 << logQT;
     const int tid = threadIdx.x;
     const int q0 = blockIdx.x * QT;
-    for (int it = tid; it < neps * QT; it += kThreads) {
-        const int j = it >> logQT, c = it & (QT - 1);
-        tile[it] = im1[(size_t)j * nk + q0 + c];
+    for (int it0 = tid; it0 < neps * QT; it0 += 8 * kThreads) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int it = it0 + k * kThreads;
+            const int j = it >> logQT, c = it & (QT - 1);
+            v[k] = im1[it < neps * QT ? (size_t)j * nk + q0 + c : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (it0 + k * kThreads < neps * QT) tile[it0 + k * kThreads] = v[k];
     }
     __syncthreads();
     const int c = tid & (QT - 1);
@@ -1013,7 +1123,7 @@ static void launch_e1(const Plan &pl, T *spec, hipStream_t st)
     using F = RegFFT<T, LOGNX, false>;
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e1<T, LOGNX>), dim3(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc)), dim3(g.e1_R * F::G),
-                       (size_t)g.e1_R * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
+                       (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
                        (const cx<T> *)pl.twx, spec);
 }
 
@@ -1036,7 +1146,7 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
-                       (size_t)g.e5_R * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
+                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
                        pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
 }
 
@@ -1055,6 +1165,9 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     case 11: CALL(11); break;                    \
     default: return hipErrorInvalidValue;        \
     }
+
+template <typename T>
+static hipError_t window_t(const Plan &pl, hipStream_t st);
 
 // ev (optional, 6 events): recorded before P1 and after P1, P2, P3, P4, P5.
 template <typename T>
@@ -1080,14 +1193,10 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
             LH_SWITCH_LOG(g.logNy, LH_E2)
 #undef LH_E2
             mark(2);
-            const size_t lds3 = (size_t)(g.e3_PL + 32 + (64 >> g.e3_logTR) + g.m_lo + 16 * ((g.nL + 15) >> 4) - 1) *
-                                g.e3_TR * es;
-            if (g.fp64)
-                hipLaunchKernelGGL((k_e3<T, false>), dim3(cdiv(g.slice_e, g.e3_TR)), dim3(kThreads), lds3, st, spr,
-                                   g);
-            else
-                hipLaunchKernelGGL((k_e3<T, true>), dim3(cdiv(g.slice_e, g.e3_TR)), dim3(kThreads), lds3, st, spr,
-                                   g);
+            {
+                const hipError_t e3 = window_t<T>(pl, st);
+                if (e3 != hipSuccess) return e3;
+            }
             mark(3);
 #define LH_E4(LG) launch_ecol<T, LG, true>(pl, spr, g.nL, st)
             LH_SWITCH_LOG(g.logNy, LH_E4)
@@ -1125,16 +1234,9 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         LH_SWITCH_LOG(g.logNy, LH_P2)
 #undef LH_P2
         mark(2);
-        if (g.p3_variant == 1) {
-#define LH_P3F(LG) launch_p3f<T, LG>(pl, spec, st)
-            LH_SWITCH_LOG(g.logNE, LH_P3F)
-#undef LH_P3F
-        } else if (g.fp64) {
-            hipLaunchKernelGGL((k_p3<T, false>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads),
-                               (size_t)g.nS * g.p3_TR * cs, st, spec, g);
-        } else {
-            hipLaunchKernelGGL((k_p3<T, true>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads),
-                               (size_t)g.nS * g.p3_TR * cs, st, spec, g);
+        {
+            const hipError_t e3 = window_t<T>(pl, st);
+            if (e3 != hipSuccess) return e3;
         }
         mark(3);
 #define LH_P4(LG) launch_col<T, LG, true>(pl, spec, g.nL, st)
@@ -1163,6 +1265,58 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     }
     mark(5);
     return hipGetLastError();
+}
+
+// The energy-window pass alone (autotuner timing).
+template <typename T>
+static hipError_t window_t(const Plan &pl, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    if (g.nL == 0) return hipSuccess;
+    const size_t cs = sizeof(cx<T>);
+    if (g.even) {
+        T *spr = (T *)pl.spec;
+        const size_t es = sizeof(T);
+        const size_t lds3 = (size_t)(g.e3_PL + 16 * (64 >> g.e3_logTR) + 32 + g.m_lo + 16 * ((g.nL + 15) >> 4) - 1) *
+                            g.e3_TR * es;
+        const dim3 g3(cdiv(g.slice_e, g.e3_TR));
+#define LH_E3(TRV)                                                                                    \
+    do {                                                                                              \
+        if (g.fp64)                                                                                   \
+            hipLaunchKernelGGL((k_e3<T, false, TRV>), g3, dim3(kThreads), lds3, st, spr, g);          \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_e3<T, true, TRV>), g3, dim3(kThreads), lds3, st, spr, g);           \
+    } while (0)
+        switch (g.e3_TR) {
+        case 64: LH_E3(64); break;
+        case 32: LH_E3(32); break;
+        case 16: LH_E3(16); break;
+        case 8: LH_E3(8); break;
+        case 4: LH_E3(4); break;
+        case 2: LH_E3(2); break;
+        default: LH_E3(1); break;
+        }
+#undef LH_E3
+        return hipGetLastError();
+    }
+    cx<T> *spec = (cx<T> *)pl.spec;
+    if (g.p3_variant == 1) {
+#define LH_P3F(LG) launch_p3f<T, LG>(pl, spec, st)
+        LH_SWITCH_LOG(g.logNE, LH_P3F)
+#undef LH_P3F
+    } else if (g.fp64) {
+        hipLaunchKernelGGL((k_p3<T, false>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
+                           st, spec, g);
+    } else {
+        hipLaunchKernelGGL((k_p3<T, true>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
+                           st, spec, g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const Plan &pl, hipStream_t st)
+{
+    return pl.g.fp64 ? window_t<double>(pl, st) : window_t<float>(pl, st);
 }
 
 hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev)

@@ -360,3 +360,35 @@ def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
           % (err64, overall, per_slice))
     assert err64 <= 1e-11
     assert overall <= 1e-5
+
+
+def test_autotuner_times_once_per_shape_and_caches(tmp_path, monkeypatch):
+    """The first plan of a shape times the window schedules; the next plan of
+    the same shape reuses the decision (in process and through the cache file),
+    and the tuned plan still matches the oracle."""
+    monkeypatch.delenv("LINDHARD_WINDOW", raising=False)
+    monkeypatch.delenv("LINDHARD_SYMMETRY", raising=False)
+    monkeypatch.delenv("LINDHARD_AUTOTUNE", raising=False)
+    monkeypatch.setenv("LINDHARD_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    cfg = W.config1()
+    cfg.update(nkx=64, nky=32, neps=128, emin=-2.0, emax=2.0, omega=np.arange(1, 41) * (4.0 / 128))
+    ref, _ = oracle_extended(cfg)
+    first = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    second = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    s1, s2 = first.info.schedule.decode(), second.info.schedule.decode()
+    print(s1, "|", s2)
+    assert " cached " in s2 or s2.endswith(" cached")
+    for plan in (first, second):
+        got = plan.exec()
+        torch.cuda.synchronize()
+        assert normwise(got.double().cpu().numpy(), ref) <= 1e-5
+        plan.close()
+    # the general path tunes its own window form
+    monkeypatch.setenv("LINDHARD_SYMMETRY", "off")
+    gen = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    assert " even " not in gen.info.schedule.decode()
+    got = gen.exec()
+    torch.cuda.synchronize()
+    assert normwise(got.double().cpu().numpy(), ref) <= 1e-5
+    gen.close()
+    assert (tmp_path / "tune.txt").exists()
