@@ -76,7 +76,7 @@ def traffic_from_profiles(kernel, kernel_src_hash):
     return None if k is None else k.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(cfg, nsamples=32):
+def cpu_baseline(cfg, nsamples=128):
     import oracle
 
     eps = oracle.band_tb(cfg["t"], cfg["tp"], cfg["tpp"], cfg["nkx"], cfg["nky"])

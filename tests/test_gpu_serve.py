@@ -116,17 +116,30 @@ def test_admission_budget_rejection_cancel_and_isolation():
 
 
 def test_exec_batch_equals_individual_runs():
-    """Mixed-size instances run as one batch give the same bits as one by one."""
+    """Mixed-size instances run as one batch give the same bits as one by one;
+    the batch is captured into a HIP graph on its first call and replayed
+    afterwards, so it is replayed several times with eager work and clears in
+    between, and every replay is checked."""
     jobs = small_jobs(8, seed=21)
     plans = [LH.Plan(**prob) for U, prob in jobs]
     dtypes = {p.dtype for p in plans}
     for dt in dtypes:
         group = [p for p in plans if p.dtype == dt]
-        outs = LH.exec_batch(group)
+        alone = []
+        for p in group:
+            alone.append(p.exec())
         torch.cuda.synchronize()
-        for p, o in zip(group, outs):
-            alone = p.exec()
+        outs = [p.empty() for p in group]
+        for rep in range(4):
+            for o in outs:
+                o.fill_(float("nan"))
+            LH.exec_batch(group, outs)
             torch.cuda.synchronize()
-            assert torch.equal(o, alone)
+            for o, a in zip(outs, alone):
+                assert torch.equal(o, a), rep
+            # eager work on the same plans between replays
+            again = group[rep % len(group)].exec()
+            torch.cuda.synchronize()
+            assert torch.equal(again, alone[rep % len(group)])
     for p in plans:
         p.close()
