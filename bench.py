@@ -181,8 +181,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nk", type=int, default=2048)
     ap.add_argument("--neps", type=int, default=512)
-    ap.add_argument("--window", choices=["auto", "direct", "fft"], default="auto",
-                    help="energy-window variant (auto: the plan's own choice)")
+    ap.add_argument("--window", choices=["auto", "direct", "fft", "even-direct", "even-mfma"], default="auto",
+                    help="energy-window variant (auto: the plan's own choice; direct / fft: general path; "
+                         "even-direct / even-mfma: even path on the vector ALUs / the matrix cores)")
     ap.add_argument("--general", action="store_true",
                     help="force the general complex path even for a mirror-symmetric band")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched run")
@@ -192,8 +193,10 @@ def main():
     args = ap.parse_args()
     if args.general:
         os.environ["LINDHARD_SYMMETRY"] = "off"
-    if args.window != "auto":
+    if args.window in ("direct", "fft"):
         os.environ["LINDHARD_WINDOW"] = args.window
+    elif args.window.startswith("even-"):
+        os.environ["LINDHARD_EVEN_WINDOW"] = args.window[5:]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; multi-GPU runs are not supported (got --gpus %d)"
               % args.gpus, file=sys.stderr)
@@ -253,14 +256,19 @@ def main():
                                                                            "lh_regfft.h")]
     khash = src_hash(src)
     fft_window = " P3 fft " in schedule
+    mfma_window = " P3 mfma " in schedule
     if even:
-        KERNEL_NAMES[:] = ["k_e1", "k_ecol<float, false>", "k_e3", "k_ecol<float, true>", "k_e5"]
+        KERNEL_NAMES[:] = ["k_e1", "k_ecol<float, false>", "k_e3m" if mfma_window else "k_e3",
+                           "k_ecol<float, true>", "k_e5"]
     elif fft_window:
         KERNEL_NAMES[2] = "k_p3f"
     if dom == 2 and not fft_window:
+        # algorithmic flops (2 per multiply-add of the window sums) over the
+        # event-timed duration; the matrix-core form runs on the FP32 MFMA
+        # peak, the direct form on the FP32 vector peak
         ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
-        roof = {"kernel": KERNEL_NAMES[2], "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
+        roof = {"kernel": KERNEL_NAMES[2], "bound": "mfma" if mfma_window else "alu", "achieved": ach,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
                 "traffic": traffic_from_profiles(KERNEL_NAMES[2], khash)}
     else:
         roof = {"kernel": KERNEL_NAMES[dom], "bound": "hbm", "achieved": gbs[dom], "peak": PEAK_HBM_GBS,
@@ -271,6 +279,10 @@ def main():
     for n, k in zip(PASS_NAMES, KERNEL_NAMES):
         passes[n]["hbm_traffic_bytes"] = traffic_from_profiles(k, khash)
     passes["p3_window"]["TFLOP/s"] = fl_win / (pass_avg[2] * 1e-3) / 1e12
+    if mfma_window:
+        # the 16x16 Toeplitz blocks also multiply the zero upper triangle
+        pts = (cfg["nkx"] // 2 + 1) * (cfg["nky"] // 2 + 1)
+        passes["p3_window"]["mfma_issued_TFLOP/s"] = pts * 16 * 2 * 16 ** 3 / (pass_avg[2] * 1e-3) / 1e12
     for n, k in zip(PASS_NAMES, KERNEL_NAMES):
         passes[n]["kernel"] = k
     lat = np.array(step_ms)

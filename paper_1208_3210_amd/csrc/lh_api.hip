@@ -34,14 +34,23 @@ static int count_occupied(int neps, double emin, double emax)
     return j0;
 }
 
+// LDS bytes of the matrix-core even window with TR points per block: the
+// staged points, and the output tile (laid over them with one lag group).
+static size_t even_mfma_lds(const Geo &g, int TR)
+{
+    const size_t tile = (size_t)256 * (TR + 1), stage = (size_t)TR * g.e3m_PS;
+    return (g.e3m_NMG == 1 ? std::max(tile, stage) : tile + stage) * (g.fp64 ? 8 : 4);
+}
+
 static void describe_schedule(Plan &pl)
 {
     const Geo &g = pl.g;
     char buf[96];
     const char *tn = g.tuned == 1 ? " tuned" : g.tuned == 2 ? " cached" : "";
     if (g.even)
-        std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 direct TR%d%s P5 R%d%s",
-                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc, g.e3_TR, tn, g.e5_R,
+        std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d%s P5 R%d%s",
+                      g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc,
+                      g.e3_variant ? "mfma" : "direct", g.e3_variant ? g.e3m_TR : g.e3_TR, tn, g.e5_R,
                       pl.p.want_rpa ? " +kk/rpa" : "");
     else
         std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d%s P5 R%d%s",
@@ -244,6 +253,18 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.e3_TR = TR;
         g.e3_logTR = ilog2(TR);
         g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 16 * (64 / TR) + 16);
+        // matrix-core window: groups of 256 occupied energies and lags
+        const int j0r = g.j0 - g.jA;
+        g.e3m_nA = g.nL > 0 ? std::max(0, std::min(j0r, g.m_hi)) : 0;
+        g.e3m_NAG = std::max(1, (g.e3m_nA + 255) / 256);
+        g.e3m_PA = 256 * g.e3m_NAG;
+        g.e3m_nHe = g.nL > 0 ? std::max(0, std::min(g.nS - j0r, g.m_hi)) : 0;
+        g.e3m_NMG = (g.nL + 255) / 256;
+        g.e3m_PS = (g.e3m_PA + g.e3m_nHe + 64) | 1;
+        g.e3m_TR = 4;
+        g.e3_variant = 0;
+        if (const char *ev = std::getenv("LINDHARD_EVEN_WINDOW"))
+            if (!std::strcmp(ev, "mfma") && even_mfma_lds(g, 4) <= 65536) g.e3_variant = 1;
     }
 
     pl.zx = p->zones_x;
@@ -416,8 +437,13 @@ std::string tune_key(const Geo &g)
             if (even_tr_fits(g, TR)) maxfit = TR;
     // lag ranges are bucketed (32 lags) so that served jobs of one grid share
     // decisions; a cached width that does not fit the plan is re-timed
-    std::snprintf(b, sizeof b, "w3 %d %d %d %d %d %d %d %d %d", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0, g.m_lo,
-                  (g.m_hi + 31) / 32, maxfit);
+    int maxfit_m = 0;
+    if (g.even)
+        for (int TR = 32; TR >= 4 && !maxfit_m; TR >>= 1)
+            if (even_mfma_lds(g, TR) <= 65536) maxfit_m = TR;
+    const char *ev = g.even ? std::getenv("LINDHARD_EVEN_WINDOW") : nullptr;
+    std::snprintf(b, sizeof b, "w4 %d %d %d %d %d %d %d %d %d %d %s", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0,
+                  g.m_lo, (g.m_hi + 31) / 32, maxfit, maxfit_m, ev ? ev : "auto");
     return b;
 }
 
@@ -466,6 +492,22 @@ void set_even_tr(Geo &g, int TR)
     g.e3_PL = std::max(1, std::min(HL, g.j0 - g.jA) + 16 * (64 / TR) + 16);
 }
 
+// An even-window schedule: variant 0 direct (TR points per block), 1 matrix cores.
+void set_even(Geo &g, int variant, int TR)
+{
+    g.e3_variant = variant;
+    if (variant == 1)
+        g.e3m_TR = TR;
+    else
+        set_even_tr(g, TR);
+}
+
+bool even_fits(const Geo &g, int variant, int TR)
+{
+    if (variant == 1) return TR >= 4 && TR <= 32 && even_mfma_lds(g, TR) <= 65536;
+    return even_tr_fits(g, TR);
+}
+
 bool even_tr_fits(const Geo &g, int TR)
 {
     const int nB = (g.nL + 15) / 16;
@@ -493,9 +535,9 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
     tune_load_file();
     {
         auto it = g_tune.find(key);
-        if (it != g_tune.end() && (!g.even || even_tr_fits(g, it->second.second))) {
+        if (it != g_tune.end() && (!g.even || even_fits(g, it->second.first, it->second.second))) {
             if (g.even)
-                set_even_tr(g, it->second.second);
+                set_even(g, it->second.first, it->second.second);
             else
                 g.p3_variant = it->second.first;
             g.tuned = 2;
@@ -504,12 +546,27 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
     }
     std::vector<std::pair<int, int>> cands;
     if (g.even) {
-        for (int TR = 64; TR >= 1 && cands.size() < 3; TR >>= 1)
-            if (even_tr_fits(g, TR)) cands.push_back({0, TR});
+        const char *ev = std::getenv("LINDHARD_EVEN_WINDOW");
+        const bool want_direct = !ev || std::strcmp(ev, "mfma") != 0;
+        const bool want_mfma = !ev || std::strcmp(ev, "direct") != 0;
+        if (want_direct)
+            for (int TR = 64, n = 0; TR >= 1 && n < 3; TR >>= 1)
+                if (even_tr_fits(g, TR)) {
+                    cands.push_back({0, TR});
+                    ++n;
+                }
+        if (want_mfma)
+            for (int TR = 32, n = 0; TR >= 4 && n < 2; TR >>= 1)
+                if (even_fits(g, 1, TR)) {
+                    cands.push_back({1, TR});
+                    ++n;
+                }
+        if (cands.empty()) cands.push_back({0, g.e3_TR});
     } else {
         cands.push_back({0, 0});
         cands.push_back({1, 0});
     }
+    if (cands.size() == 1 && g.even) set_even(g, cands[0].first, cands[0].second);
     if (cands.size() > 1) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         LH_TRY(hipEventCreate(&e0));
@@ -519,7 +576,7 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
         const Geo keep = g;
         for (const auto &c : cands) {
             if (g.even)
-                set_even_tr(g, c.second);
+                set_even(g, c.first, c.second);
             else
                 g.p3_variant = c.first;
             float tmin = 1e30f;
@@ -541,7 +598,7 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (g.even)
-            set_even_tr(g, pick.second);
+            set_even(g, pick.first, pick.second);
         else
             g.p3_variant = pick.first;
         g.tuned = 1;

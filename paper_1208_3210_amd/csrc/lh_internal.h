@@ -48,6 +48,12 @@ struct Geo {
     int e3_TR, e3_logTR;      // real-space points per block, even window
     int e3_PL;                // padded length of each reversed / shifted window array
     int e5_R;                 // row pairs per block, even inverse row pass
+    // even window on the matrix cores (e3_variant 1): TRm points per block,
+    // per point PA reversed occupied values then nHe + 64 unoccupied ones
+    // (32 zeros each side), point stride PS; NAG / NMG groups of 256
+    // occupied energies / lags
+    int e3_variant;
+    int e3m_TR, e3m_PA, e3m_nA, e3m_nHe, e3m_PS, e3m_NAG, e3m_NMG;
     // energy-window variant: 0 direct (compensated in FP32), 1 FFT along energy
     int p3_variant;
     int logNE;                // FFT length along energy for variant 1

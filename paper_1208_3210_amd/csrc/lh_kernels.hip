@@ -813,6 +813,215 @@ __global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
     }
 }
 
+// Energy window (even) on the matrix cores.  The same convolution
+// S(m) = sum_a P'[a] H'[m-1-a] as k_e3, blocked by 16: with m = m0 + 16 c + i
+// (c = 0..15 output column, i = 0..15 row) and a = 16 n + k, the block pair
+// (c, n) only depends on e = c - n through the Toeplitz block
+// T_e[i][k] = H'[m0 - 1 + 16 e + i - k], so for every e one 16x16x16 product
+// T_e * [P'_0 ... P'_15] (four 16x16x4 MFMAs, columns n) gives the terms of
+// column c = n + e: the result is moved e columns to the right with a DPP row
+// shift (zeros shifted in, columns pushed past 15 dropped) and added to the
+// accumulator.  The P' operand is loaded once per point; each MFMA reads one
+// Toeplitz operand from LDS.  FP32: the 16-product MFMA sums are accumulated
+// in FP64; FP64: everything in FP64.
+//
+// Operand layouts (16x16x4): A lane l = (row l%16, k l/16); B lane l =
+// (k l/16, column l%16); D lane l, register r = (row 4(l/16)+r, column l%16)
+// for FP32 and (row 4r+l/16, column l%16) for FP64.
+//
+// One block: TR consecutive points, each staged point-major (stride PS, odd,
+// so that the staging writes of consecutive points fall in different banks):
+// [PA values P'[a], zero for a >= nA][32 zeros][nHe values H'[x]][32 zeros].
+// Lags and occupied energies beyond 256 are handled in groups of 256 (NMG,
+// NAG).  Each wave takes TR/4 points; results go through an LDS tile
+// [256 lags][TR + 1] so that the in-place stores of S are coalesced.
+typedef float lh_f4 __attribute__((ext_vector_type(4)));
+typedef double lh_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaVec;
+template <>
+struct MfmaVec<float> {
+    using V = lh_f4;
+};
+template <>
+struct MfmaVec<double> {
+    using V = lh_d4;
+};
+
+__device__ __forceinline__ lh_f4 mfma16x16x4(float a, float b, lh_f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ lh_d4 mfma16x16x4(double a, double b, lh_d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Value of column c - E of the same 16-lane row (0 where that is outside the row).
+template <int E>
+__device__ __forceinline__ int col_shift_i(int v)
+{
+    constexpr int ctl = E > 0 ? 0x110 + E : 0x100 - E;  // row_shr:E, row_shl:-E
+    return __builtin_amdgcn_update_dpp(0, v, ctl, 0xF, 0xF, true);
+}
+template <int E>
+__device__ __forceinline__ float col_shift(float v)
+{
+    if constexpr (E == 0)
+        return v;
+    else
+        return __int_as_float(col_shift_i<E>(__float_as_int(v)));
+}
+template <int E>
+__device__ __forceinline__ double col_shift(double v)
+{
+    if constexpr (E == 0) {
+        return v;
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = col_shift_i<E>((int)(b & 0xffffffffLL));
+        const int hi = col_shift_i<E>((int)(b >> 32));
+        return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+    }
+}
+
+// Row of the 16x16 result held in register r by lane group k4 = lane / 16.
+template <typename T>
+__device__ __forceinline__ int mfma_row(int r, int k4)
+{
+    return sizeof(T) == 4 ? 4 * k4 + r : 4 * r + k4;
+}
+
+template <typename T, int E>
+__device__ __forceinline__ void e3m_block(const T *hb, const T (&b)[4], double (&acc)[4])
+{
+    typename MfmaVec<T>::V x = {0, 0, 0, 0};
+    x = mfma16x16x4(hb[16 * E], b[0], x);
+    x = mfma16x16x4(hb[16 * E - 4], b[1], x);
+    x = mfma16x16x4(hb[16 * E - 8], b[2], x);
+    x = mfma16x16x4(hb[16 * E - 12], b[3], x);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += (double)col_shift<E>(x[r]);
+}
+
+// Every E in [E0, E1] (the whole range is known to be needed).
+template <typename T, int E, int E1>
+__device__ __forceinline__ void e3m_all(const T *hb, const T (&b)[4], double (&acc)[4])
+{
+    if constexpr (E <= E1) {
+        e3m_block<T, E>(hb, b, acc);
+        e3m_all<T, E + 1, E1>(hb, b, acc);
+    }
+}
+
+// Only the E in [e_lo, e_hi] (wave-uniform bounds).
+template <typename T, int E>
+__device__ __forceinline__ void e3m_some(const T *hb, const T (&b)[4], int e_lo, int e_hi, double (&acc)[4])
+{
+    if constexpr (E <= 15) {
+        if (E >= e_lo && E <= e_hi) e3m_block<T, E>(hb, b, acc);
+        e3m_some<T, E + 1>(hb, b, e_lo, e_hi, acc);
+    }
+}
+
+template <typename T, int TR>
+__global__ void __launch_bounds__(kThreads) k_e3m(T *__restrict__ spec, Geo g)
+{
+    static_assert(TR >= 4 && (TR & (TR - 1)) == 0, "TR: power of two >= 4");
+    constexpr int PPW = TR / 4;  // points per wave
+    constexpr int TS = TR + 1;   // row stride of the output tile
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    const int PA = g.e3m_PA, nA = g.e3m_nA, nHe = g.e3m_nHe, PS = g.e3m_PS;
+    const int NAG = g.e3m_NAG, NMG = g.e3m_NMG;
+    const int rows = PA + nHe + 64;
+    const int tid = threadIdx.x;
+    const size_t p0 = (size_t)xcd_tile(blockIdx.x, gridDim.x) * TR;
+    const int j0 = g.j0 - g.jA;
+    const size_t sl = g.slice_e;
+    {
+        constexpr int UNR = 8;
+        const int n = rows * TR;
+        for (int it0 = tid; it0 < n; it0 += UNR * kThreads) {
+            T v[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const int it = it0 + k * kThreads;
+                const int rr = it / TR, p = it % TR;
+                int js;
+                bool ok;
+                if (rr < PA) {
+                    js = j0 - 1 - rr;
+                    ok = rr < nA;
+                } else {
+                    const int x = rr - PA - 32;
+                    js = j0 + x;
+                    ok = x >= 0 && x < nHe;
+                }
+                ok = ok && it < n && p0 + p < sl;
+                const size_t src = ok ? (size_t)js * sl + p0 + p : 0;
+                const T x = spec[src];
+                v[k] = ok ? x : (T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const int it = it0 + k * kThreads;
+                if (it < n) lds[(it % TR) * PS + it / TR] = v[k];
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c16 = lane & 15, k4 = lane >> 4;
+    const bool overlay = NMG == 1;  // the tile reuses the staging area
+    T *tile = overlay ? lds : lds + (size_t)TR * PS;
+    for (int gm = 0; gm < NMG; ++gm) {
+        T res[PPW][4];
+#pragma unroll
+        for (int pi = 0; pi < PPW; ++pi) {
+            const int P = (wave + 4 * pi) * PS;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int ga = 0; ga < NAG; ++ga) {
+                T b[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b[s] = lds[P + 256 * ga + 16 * c16 + 4 * s + k4];
+                const int D0 = g.m_lo - 1 + 256 * (gm - ga);
+                // e with some H' index D0 + 16 e + [-15, 15] inside [0, nHe)
+                const int e_lo = max(-15, -((D0 + 15) >> 4));
+                const int e_hi = min(15, (nHe + 14 - D0) >> 4);
+                const T *hb = lds + (P + PA + 32 + D0 + c16 - k4);
+                if (e_lo == 0 && e_hi == 15)
+                    e3m_all<T, 0, 15>(hb, b, acc);
+                else
+                    e3m_some<T, -15>(hb, b, e_lo, e_hi, acc);
+            }
+            if (overlay) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) res[pi][r] = (T)acc[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = (T)acc[r];
+            }
+        }
+        __syncthreads();
+        if (overlay) {
+#pragma unroll
+            for (int pi = 0; pi < PPW; ++pi)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = res[pi][r];
+            __syncthreads();
+        }
+        const int mb = g.m_lo + 256 * gm;
+        for (int it = tid; it < 256 * TR; it += kThreads) {
+            const int row = it / TR, p = it % TR;
+            const int m = mb + row;
+            if (m <= g.m_hi && p0 + p < sl) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = tile[row * TS + p];
+        }
+        __syncthreads();
+    }
+}
+
 // P5 (even): R row pairs (qy = 2p, 2p+1 <= nky/2) of one plane.  Each line is
 // the full even row rebuilt from rx in [0, nkx/2]; its FFT gives the two real
 // rows C(qx, qy) for every qx, written to rows qy and nky - qy of each zone.
@@ -1174,7 +1383,6 @@ template <typename T>
 static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 {
     const Geo &g = pl.g;
-    const size_t cs = sizeof(cx<T>);
     cx<T> *spec = (cx<T> *)pl.spec;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     auto mark = [&](int i) {
@@ -1183,7 +1391,6 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     mark(0);
     if (g.even) {
         T *spr = (T *)pl.spec;
-        const size_t es = sizeof(T);
         if (g.nL > 0) {
 #define LH_E1(LG) launch_e1<T, LG>(pl, spr, st)
             LH_SWITCH_LOG(g.logNx, LH_E1)
@@ -1287,6 +1494,18 @@ static hipError_t window_t(const Plan &pl, hipStream_t st)
         else                                                                                          \
             hipLaunchKernelGGL((k_e3<T, true, TRV>), g3, dim3(kThreads), lds3, st, spr, g);           \
     } while (0)
+        if (g.e3_variant == 1) {
+            const size_t tile = (size_t)256 * (g.e3m_TR + 1), stage = (size_t)g.e3m_TR * g.e3m_PS;
+            const size_t ldsm = (g.e3m_NMG == 1 ? std::max(tile, stage) : tile + stage) * es;
+            const dim3 gm(cdiv(g.slice_e, g.e3m_TR));
+            switch (g.e3m_TR) {
+            case 32: hipLaunchKernelGGL((k_e3m<T, 32>), gm, dim3(kThreads), ldsm, st, spr, g); break;
+            case 16: hipLaunchKernelGGL((k_e3m<T, 16>), gm, dim3(kThreads), ldsm, st, spr, g); break;
+            case 8: hipLaunchKernelGGL((k_e3m<T, 8>), gm, dim3(kThreads), ldsm, st, spr, g); break;
+            default: hipLaunchKernelGGL((k_e3m<T, 4>), gm, dim3(kThreads), ldsm, st, spr, g); break;
+            }
+            return hipGetLastError();
+        }
         switch (g.e3_TR) {
         case 64: LH_E3(64); break;
         case 32: LH_E3(32); break;

@@ -19,19 +19,24 @@ pytestmark = pytest.mark.gpu
 
 TOL = {LH.LINDHARD_FP64: 1e-11, LH.LINDHARD_FP32C: 1e-5}
 PRECS = [LH.LINDHARD_FP64, LH.LINDHARD_FP32C]
-WINDOWS = ["auto", "direct", "fft"]
+WINDOWS = ["auto", "direct", "fft", "even-direct", "even-mfma"]
+EVEN_WINDOWS = ("auto", "even-direct", "even-mfma")
 
 
 @pytest.fixture
 def window(request, monkeypatch):
     """Pipeline chosen at plan time.  auto: the plan's own choice (the real
-    even path for mirror-symmetric bands); direct / fft: the general complex
-    path with the direct or the energy-FFT window."""
-    monkeypatch.delenv("LINDHARD_WINDOW", raising=False)
-    monkeypatch.delenv("LINDHARD_SYMMETRY", raising=False)
-    if request.param != "auto":
+    even path for mirror-symmetric bands, window form timed); direct / fft:
+    the general complex path with the direct or the energy-FFT window;
+    even-direct / even-mfma: the even path with the vector-ALU or the
+    matrix-core window (the latter where its LDS tiles fit)."""
+    for v in ("LINDHARD_WINDOW", "LINDHARD_SYMMETRY", "LINDHARD_EVEN_WINDOW"):
+        monkeypatch.delenv(v, raising=False)
+    if request.param in ("direct", "fft"):
         monkeypatch.setenv("LINDHARD_SYMMETRY", "off")
         monkeypatch.setenv("LINDHARD_WINDOW", request.param)
+    elif request.param.startswith("even-"):
+        monkeypatch.setenv("LINDHARD_EVEN_WINDOW", request.param[5:])
     return request.param
 
 
@@ -80,7 +85,12 @@ def test_config1_full_grid(prec, window):
     assert abs(plan.info.mu - mu) < 1e-12
     err = normwise(got, ref)
     print("config1 prec=%d window=%s err=%.3e schedule=%s" % (prec, window, err, plan.info.schedule.decode()))
-    assert (" even " in plan.info.schedule.decode()) == (window == "auto")
+    sched = plan.info.schedule.decode()
+    assert (" even " in sched) == (window in EVEN_WINDOWS)
+    if window == "even-mfma":
+        assert " P3 mfma " in sched
+    if window == "even-direct":
+        assert " P3 direct " in sched
     assert err <= TOL[prec]
     plan.close()
 
@@ -147,11 +157,11 @@ def test_caller_table_without_inversion_symmetry(prec, window):
     plan.close()
 
 
+@pytest.mark.parametrize("window", EVEN_WINDOWS, indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
-def test_caller_table_with_mirror_symmetry_takes_even_path(prec, monkeypatch):
+def test_caller_table_with_mirror_symmetry_takes_even_path(prec, window):
     """A random table made mirror symmetric in both axes is detected bit for
     bit and runs on the real even path; it must still match the oracle."""
-    monkeypatch.delenv("LINDHARD_SYMMETRY", raising=False)
     rng = np.random.Generator(np.random.PCG64(12))
     nky, nkx = 32, 64
     base = rng.uniform(-1.2, 1.5, size=(nky, nkx))
@@ -164,7 +174,7 @@ def test_caller_table_with_mirror_symmetry_takes_even_path(prec, monkeypatch):
     plan, got = run_gpu(cfg, prec)
     assert " even " in plan.info.schedule.decode()
     err = normwise(got, ref)
-    print("sym table prec=%d err=%.3e" % (prec, err))
+    print("sym table prec=%d window=%s err=%.3e schedule=%s" % (prec, window, err, plan.info.schedule.decode()))
     assert err <= TOL[prec]
     plan.close()
 
@@ -237,7 +247,7 @@ def test_rpa_zero_U_is_identity_and_needs_want_rpa():
     plan.close()
 
 
-@pytest.mark.parametrize("window", ["auto", "fft"], indirect=True)
+@pytest.mark.parametrize("window", ["auto", "fft", "even-mfma"], indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
 def test_config2_full_size_sampled(prec, window):
     """512^2 k, 256 energies, 5x5 zones, form factor, KK and RPA: every output
@@ -305,7 +315,7 @@ def q_sum_identity_rhs(xi, neps, emin, emax, gamma, lags):
     return np.array(out)
 
 
-@pytest.mark.parametrize("window", ["auto", "fft", "direct"], indirect=True)
+@pytest.mark.parametrize("window", ["auto", "fft", "direct", "even-direct", "even-mfma"], indirect=True)
 def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
     """2048^2 k, 512 energies, 256 lags, G = 0.01 eV: FP32 (the benchmarked
     launch) against the oracle at sampled (q, m), the q-sum identity at every
@@ -316,6 +326,9 @@ def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
     lags = lags_of(cfg)
     plan32 = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
     assert abs(plan32.info.mu - mu) < 1e-12
+    print("config3 [%s] schedule %s" % (window, plan32.info.schedule.decode()))
+    if window == "even-mfma":
+        assert " P3 mfma " in plan32.info.schedule.decode()
     out32 = plan32.exec()
     torch.cuda.synchronize()
     plan32.close()
