@@ -34,11 +34,21 @@ static int count_occupied(int neps, double emin, double emax)
     return j0;
 }
 
+// Point stride of the matrix-core even window with TR points per block: at
+// least the staged rows, and congruent to 64 / TR modulo 64 so that the
+// staging writes of one wave (TR points x 64 / TR consecutive rows) hit 64
+// different banks.
+static int even_mfma_ps(const Geo &g, int TR)
+{
+    const int base = g.e3m_PA + g.e3m_nHe + 64;
+    return base + (((64 / TR - base) % 64) + 64) % 64;
+}
+
 // LDS bytes of the matrix-core even window with TR points per block: the
 // staged points, and the output tile (laid over them with one lag group).
 static size_t even_mfma_lds(const Geo &g, int TR)
 {
-    const size_t tile = (size_t)256 * (TR + 1), stage = (size_t)TR * g.e3m_PS;
+    const size_t tile = (size_t)256 * (TR + 1), stage = (size_t)TR * even_mfma_ps(g, TR);
     return (g.e3m_NMG == 1 ? std::max(tile, stage) : tile + stage) * (g.fp64 ? 8 : 4);
 }
 
@@ -260,7 +270,11 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.e3m_PA = 256 * g.e3m_NAG;
         g.e3m_nHe = g.nL > 0 ? std::max(0, std::min(g.nS - j0r, g.m_hi)) : 0;
         g.e3m_NMG = (g.nL + 255) / 256;
-        g.e3m_PS = (g.e3m_PA + g.e3m_nHe + 64) | 1;
+        g.e3m_PS = even_mfma_ps(g, 4);
+        {
+            const size_t lim = 0xFFFFFF00u, es3 = g.fp64 ? 8 : 4;
+            g.e3m_buf = (size_t)g.e3m_nA * g.slice_e * es3 < lim && (size_t)g.e3m_nHe * g.slice_e * es3 < lim;
+        }
         g.e3m_TR = 4;
         g.e3_variant = 0;
         if (const char *ev = std::getenv("LINDHARD_EVEN_WINDOW"))
@@ -496,9 +510,10 @@ void set_even_tr(Geo &g, int TR)
 void set_even(Geo &g, int variant, int TR)
 {
     g.e3_variant = variant;
-    if (variant == 1)
+    if (variant == 1) {
         g.e3m_TR = TR;
-    else
+        g.e3m_PS = even_mfma_ps(g, TR);
+    } else
         set_even_tr(g, TR);
 }
 

@@ -54,6 +54,7 @@ struct Geo {
     // occupied energies / lags
     int e3_variant;
     int e3m_TR, e3m_PA, e3m_nA, e3m_nHe, e3m_PS, e3m_NAG, e3m_NMG;
+    int e3m_buf;              // occupied and unoccupied slice ranges each below 4 GiB: buffer loads
     // energy-window variant: 0 direct (compensated in FP32), 1 FFT along energy
     int p3_variant;
     int logNE;                // FFT length along energy for variant 1

@@ -16,6 +16,9 @@
 #include "lh_internal.h"
 #include "lh_regfft.h"
 
+#include <map>
+#include <mutex>
+
 namespace lh {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
             v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
-        F::run(v, buf, twx, 1, gg, row);
+        F::run(v, buf, twx, 1, gg, lds_xor_gfast<L, G>(row));
 #pragma unroll
         for (int s = 0; s < E; ++s) buf[swz(gg + s * G)] = v[s];
         __syncthreads();
@@ -258,7 +261,7 @@ __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, co
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) v[s] = active ? base[(gg + s * G) * C + c] : mk<T>((T)0, (T)0);
-    F::run(v, lds + line * N, twy, 0, gg, line);
+    F::run(v, lds + line * N, twy, 0, gg, lds_xor_interleaved<T, N>(line, NL));
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) base[(gg + s * G) * C + c] = v[s];
@@ -447,14 +450,15 @@ __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, co
     }
     __syncthreads();
     cx<T> *buf = lds + rp * N;
-    FF::run(vp, buf, twe, 0, gg, rp);
-    FF::run(vh, buf, twe, 0, gg, rp);
+    const int lxe = lds_xor_interleaved<T, N>(rp, TR);
+    FF::run(vp, buf, twe, 0, gg, lxe);
+    FF::run(vh, buf, twe, 0, gg, lxe);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const cx<T> a = vp[s], b = vh[s];
         vh[s] = mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);  // conj(a) b
     }
-    FI::run(vh, buf, twe, 0, gg, rp);
+    FI::run(vh, buf, twe, 0, gg, lxe);
     const T inv = (T)(1.0 / N);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -538,7 +542,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         v[s] = cadd(A, mk<T>(-wD.y, wD.x));      // A + i w D
     }
     __syncthreads();
-    F::run(v, xb, twx, 1, gg, row);
+    F::run(v, xb, twx, 1, gg, lds_xor_gfast<L, G>(row));
 
     const T sc = (T)scale;
     const int qy = qy0 + row;
@@ -622,7 +626,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
             v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
-        F::run(v, buf, tw, 0, gg, line);
+        F::run(v, buf, tw, 0, gg, lds_xor_gfast<N, G>(line));
 #pragma unroll
         for (int s = 0; s < E; ++s) buf[gg + s * G] = v[s];
         __syncthreads();
@@ -670,7 +674,7 @@ __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const
         const int row = ky <= N / 2 ? ky : N - ky;
         v[s] = active ? base[row * C + c] : mk<T>((T)0, (T)0);
     }
-    F::run(v, lds + line * N, twy, 0, gg, line);
+    F::run(v, lds + line * N, twy, 0, gg, lds_xor_interleaved<T, N>(line, NL));
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) {
@@ -819,22 +823,24 @@ __global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
 // (c, n) only depends on e = c - n through the Toeplitz block
 // T_e[i][k] = H'[m0 - 1 + 16 e + i - k], so for every e one 16x16x16 product
 // T_e * [P'_0 ... P'_15] (four 16x16x4 MFMAs, columns n) gives the terms of
-// column c = n + e: the result is moved e columns to the right with a DPP row
-// shift (zeros shifted in, columns pushed past 15 dropped) and added to the
+// column c = n + e: the result is moved e columns to the right with DPP row
+// shifts (zeros shifted in, columns pushed past 15 dropped) and added to the
 // accumulator.  The P' operand is loaded once per point; each MFMA reads one
-// Toeplitz operand from LDS.  FP32: the 16-product MFMA sums are accumulated
-// in FP64; FP64: everything in FP64.
+// Toeplitz operand from LDS.  FP32: partial sums of four e (64 products) are
+// accumulated in FP64; FP64: everything in FP64.
 //
 // Operand layouts (16x16x4): A lane l = (row l%16, k l/16); B lane l =
 // (k l/16, column l%16); D lane l, register r = (row 4(l/16)+r, column l%16)
 // for FP32 and (row 4r+l/16, column l%16) for FP64.
 //
-// One block: TR consecutive points, each staged point-major (stride PS, odd,
-// so that the staging writes of consecutive points fall in different banks):
-// [PA values P'[a], zero for a >= nA][32 zeros][nHe values H'[x]][32 zeros].
-// Lags and occupied energies beyond 256 are handled in groups of 256 (NMG,
-// NAG).  Each wave takes TR/4 points; results go through an LDS tile
-// [256 lags][TR + 1] so that the in-place stores of S are coalesced.
+// Tiles of TR consecutive points; each point staged point-major, stride PS
+// (congruent to 64 / TR modulo 64, so that the staging writes of one wave hit
+// 64 different banks): [PA values P'[a], zero for a >= nA][32 zeros]
+// [nHe values H'[x]][32 zeros].  Lags and occupied energies beyond 256 are
+// handled in groups of 256 (NMG, NAG).  Each wave takes TR/4 points; results
+// go through an LDS tile [256 lags][TR + 1] so that the in-place stores of S
+// are coalesced.  Blocks are persistent and load the next tile into
+// registers while the current one is on the matrix cores.
 typedef float lh_f4 __attribute__((ext_vector_type(4)));
 typedef double lh_d4 __attribute__((ext_vector_type(4)));
 
@@ -893,131 +899,307 @@ __device__ __forceinline__ int mfma_row(int r, int k4)
     return sizeof(T) == 4 ? 4 * k4 + r : 4 * r + k4;
 }
 
+// x + T_E [P'_0 .. P'_15]: four 16x16x4 products accumulated on x.
 template <typename T, int E>
-__device__ __forceinline__ void e3m_block(const T *hb, const T (&b)[4], double (&acc)[4])
+__device__ __forceinline__ typename MfmaVec<T>::V e3m_prod(const T *hb, const T (&b)[4], typename MfmaVec<T>::V x)
 {
-    typename MfmaVec<T>::V x = {0, 0, 0, 0};
     x = mfma16x16x4(hb[16 * E], b[0], x);
     x = mfma16x16x4(hb[16 * E - 4], b[1], x);
     x = mfma16x16x4(hb[16 * E - 8], b[2], x);
     x = mfma16x16x4(hb[16 * E - 12], b[3], x);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] += (double)col_shift<E>(x[r]);
+    return x;
 }
 
-// Every E in [E0, E1] (the whole range is known to be needed).
-template <typename T, int E, int E1>
-__device__ __forceinline__ void e3m_all(const T *hb, const T (&b)[4], double (&acc)[4])
+template <int S, typename V>
+__device__ __forceinline__ V vshift(V x)
 {
-    if constexpr (E <= E1) {
-        e3m_block<T, E>(hb, b, acc);
-        e3m_all<T, E + 1, E1>(hb, b, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = col_shift<S>(x[r]);
+    return x;
+}
+
+// Horner chains over a group of up to four e: the products of the group are
+// summed in the precision of the MFMA (64 products per FP32 partial sum) and
+// each group is folded once into the FP64 accumulator.  For e >= 0 the chain
+// runs from the largest e down with one-column right shifts in between and a
+// final right shift by the smallest e; for e < 0 it runs upwards with left
+// shifts.  Every shift of a chain moves the same way, so what leaves the
+// 16-column row has left the lag block for good.
+template <typename T, int E, int E0, bool CHECK>
+__device__ __forceinline__ void e3m_chain_r(const T *hb, const T (&b)[4], int e_lo, int e_hi,
+                                            typename MfmaVec<T>::V &x)
+{
+    if (!CHECK || (E >= e_lo && E <= e_hi)) x = e3m_prod<T, E>(hb, b, x);
+    if constexpr (E > E0) {
+        x = vshift<1>(x);
+        e3m_chain_r<T, E - 1, E0, CHECK>(hb, b, e_lo, e_hi, x);
+    }
+}
+template <typename T, int E, int E1, bool CHECK>
+__device__ __forceinline__ void e3m_chain_l(const T *hb, const T (&b)[4], int e_lo, int e_hi,
+                                            typename MfmaVec<T>::V &x)
+{
+    if (!CHECK || (E >= e_lo && E <= e_hi)) x = e3m_prod<T, E>(hb, b, x);
+    if constexpr (E < E1) {
+        x = vshift<-1>(x);
+        e3m_chain_l<T, E + 1, E1, CHECK>(hb, b, e_lo, e_hi, x);
     }
 }
 
-// Only the E in [e_lo, e_hi] (wave-uniform bounds).
+// Group [E0, E1] (both >= 0, or both < 0).
+template <typename T, int E0, int E1, bool CHECK>
+__device__ __forceinline__ void e3m_group(const T *hb, const T (&b)[4], int e_lo, int e_hi, double (&acc)[4])
+{
+    if (CHECK && (e_hi < E0 || e_lo > E1)) return;  // wave-uniform
+    typename MfmaVec<T>::V x = {0, 0, 0, 0};
+    if constexpr (E0 >= 0) {
+        e3m_chain_r<T, E1, E0, CHECK>(hb, b, e_lo, e_hi, x);
+        x = vshift<E0>(x);
+    } else {
+        e3m_chain_l<T, E0, E1, CHECK>(hb, b, e_lo, e_hi, x);
+        x = vshift<E1>(x);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += (double)x[r];
+}
+
+// Every e in [0, 15] (the whole range is known to be needed).
+template <typename T>
+__device__ __forceinline__ void e3m_all(const T *hb, const T (&b)[4], double (&acc)[4])
+{
+    e3m_group<T, 0, 3, false>(hb, b, 0, 15, acc);
+    e3m_group<T, 4, 7, false>(hb, b, 0, 15, acc);
+    e3m_group<T, 8, 11, false>(hb, b, 0, 15, acc);
+    e3m_group<T, 12, 15, false>(hb, b, 0, 15, acc);
+}
+
+// One e alone, folded at once (the general ranges of e3m_some).
 template <typename T, int E>
+__device__ __forceinline__ void e3m_one(const T *hb, const T (&b)[4], double (&acc)[4])
+{
+    typename MfmaVec<T>::V x = {0, 0, 0, 0};
+    x = vshift<E>(e3m_prod<T, E>(hb, b, x));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += (double)x[r];
+}
+
+// Only the e in [e_lo, e_hi] (wave-uniform bounds within [-15, 15]).
+template <typename T, int E = -15>
 __device__ __forceinline__ void e3m_some(const T *hb, const T (&b)[4], int e_lo, int e_hi, double (&acc)[4])
 {
     if constexpr (E <= 15) {
-        if (E >= e_lo && E <= e_hi) e3m_block<T, E>(hb, b, acc);
+        if (E >= e_lo && E <= e_hi) e3m_one<T, E>(hb, b, acc);
         e3m_some<T, E + 1>(hb, b, e_lo, e_hi, acc);
     }
 }
 
+// Registers per thread that hold the next tile's staging loads.
+constexpr int kE3mPF = 24;
+
+// Staging geometry of one thread: P' rows a < nA, H' rows x < nHe (at row
+// PA + 32 + x), point pst, slice stride sb bytes.
+struct E3mStage {
+    int PA, nA, nHe, pst;
+    unsigned sb;
+};
+struct E3mRsrc {
+    __amdgpu_buffer_rsrc_t P, H;
+};
+
+// Buffer descriptors of one tile (first point p0): P' rows a at slice
+// j0 - 1 - a counted from base slice j0 - nA, H' rows x at slice j0 + x; each
+// range ends with the last element of its slices.
+template <typename T>
+__device__ __forceinline__ E3mRsrc e3m_rsrc(T *spec, size_t sl, int j0, int nA, int nHe, size_t p0)
+{
+    const size_t nP = (size_t)nA * sl, nH = (size_t)nHe * sl;
+    E3mRsrc r;
+    r.P = __builtin_amdgcn_make_buffer_rsrc((void *)(spec + (size_t)(j0 - nA) * sl + p0), 0,
+                                            (int)(nP > p0 ? (nP - p0) * sizeof(T) : 0), 0x00020000);
+    r.H = __builtin_amdgcn_make_buffer_rsrc((void *)(spec + (size_t)j0 * sl + p0), 0,
+                                            (int)(nH > p0 ? (nH - p0) * sizeof(T) : 0), 0x00020000);
+    return r;
+}
+
+// Staged row rr of point st.pst (0 for the zero rows: out-of-range offset).
+template <typename T>
+__device__ __forceinline__ T e3m_bload(const E3mRsrc &rs, const E3mStage &st, int rr)
+{
+    const bool wP = __builtin_amdgcn_readfirstlane(rr) < st.PA;  // wave-uniform
+    const int x = rr - st.PA - 32;
+    const unsigned po = (unsigned)st.pst * (unsigned)sizeof(T);
+    unsigned off;
+    if (wP)
+        off = rr < st.nA ? (unsigned)(st.nA - 1 - rr) * st.sb + po : 0xFFFFFFF0u;
+    else
+        off = (x >= 0 && x < st.nHe) ? (unsigned)x * st.sb + po : 0xFFFFFFF0u;
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(wP ? rs.P : rs.H, (int)off, 0, 0));
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(wP ? rs.P : rs.H, (int)off, 0, 0);
+        return __builtin_bit_cast(double, v);
+    }
+}
+
+// The same row with a plain global load (any size).
+template <typename T>
+__device__ __forceinline__ T e3m_gload(const T *col, bool pv, const E3mStage &st, int j0, int rows, size_t sl,
+                                       int rr)
+{
+    int js;
+    bool ok;
+    if (rr < st.PA) {
+        js = j0 - 1 - rr;
+        ok = rr < st.nA;
+    } else {
+        const int xx = rr - st.PA - 32;
+        js = j0 + xx;
+        ok = xx >= 0 && xx < st.nHe;
+    }
+    ok = ok && rr < rows && pv;
+    const T xv = col[ok ? (size_t)js * sl : 0];
+    return ok ? xv : (T)0;
+}
+
 template <typename T, int TR>
-__global__ void __launch_bounds__(kThreads) k_e3m(T *__restrict__ spec, Geo g)
+__global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g, int ntiles)
 {
     static_assert(TR >= 4 && (TR & (TR - 1)) == 0, "TR: power of two >= 4");
     constexpr int PPW = TR / 4;  // points per wave
     constexpr int TS = TR + 1;   // row stride of the output tile
+    constexpr int NPF = kE3mPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int PA = g.e3m_PA, nA = g.e3m_nA, nHe = g.e3m_nHe, PS = g.e3m_PS;
     const int NAG = g.e3m_NAG, NMG = g.e3m_NMG;
     const int rows = PA + nHe + 64;
     const int tid = threadIdx.x;
-    const size_t p0 = (size_t)xcd_tile(blockIdx.x, gridDim.x) * TR;
     const int j0 = g.j0 - g.jA;
     const size_t sl = g.slice_e;
-    {
+    // Persistent blocks: the blocks of one XCD (launch index mod 8) walk one
+    // contiguous range of tiles, so neighbouring tiles meet in that XCD's L2.
+    const int xcd = blockIdx.x & 7, bi = blockIdx.x >> 3, bx = gridDim.x >> 3;
+    const int per = (ntiles + 7) >> 3;
+    const int t_end = min(ntiles, (xcd + 1) * per);
+    int t = xcd * per + bi;
+    if (t >= t_end) return;
+
+    // Staging: thread tid always loads point pst = tid % TR, rows r0 + k RS
+    // (the 64 / TR rows of one wave at one k never straddle the P' / H'
+    // boundary, whose row indices are multiples of 32).  With buffer loads
+    // (both slice ranges below 4 GiB) rows of zeros get an out-of-range offset
+    // and read 0, and every load of a thread is in flight at once.
+    constexpr int RS = kThreads / TR;
+    const int pst = tid % TR, r0 = tid / TR;
+    const bool buf = g.e3m_buf != 0;
+    const E3mStage st{PA, nA, nHe, pst, (unsigned)(sl * sizeof(T))};
+    auto stage_sync = [&](size_t p0) {
         constexpr int UNR = 8;
-        const int n = rows * TR;
-        for (int it0 = tid; it0 < n; it0 += UNR * kThreads) {
-            T v[UNR];
+        if (buf) {
+            const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, p0);
+            for (int rb = r0; rb < rows; rb += UNR * RS) {
+                T v[UNR];
 #pragma unroll
-            for (int k = 0; k < UNR; ++k) {
-                const int it = it0 + k * kThreads;
-                const int rr = it / TR, p = it % TR;
-                int js;
-                bool ok;
-                if (rr < PA) {
-                    js = j0 - 1 - rr;
-                    ok = rr < nA;
-                } else {
-                    const int x = rr - PA - 32;
-                    js = j0 + x;
-                    ok = x >= 0 && x < nHe;
-                }
-                ok = ok && it < n && p0 + p < sl;
-                const size_t src = ok ? (size_t)js * sl + p0 + p : 0;
-                const T x = spec[src];
-                v[k] = ok ? x : (T)0;
+                for (int k = 0; k < UNR; ++k) v[k] = e3m_bload<T>(rs, st, rb + k * RS);
+#pragma unroll
+                for (int k = 0; k < UNR; ++k)
+                    if (rb + k * RS < rows) lds[pst * PS + rb + k * RS] = v[k];
             }
+        } else {
+            const bool pv = p0 + pst < sl;
+            const T *col = spec + (pv ? p0 + pst : 0);
+            for (int rb = r0; rb < rows; rb += UNR * RS) {
+                T v[UNR];
 #pragma unroll
-            for (int k = 0; k < UNR; ++k) {
-                const int it = it0 + k * kThreads;
-                if (it < n) lds[(it % TR) * PS + it / TR] = v[k];
+                for (int k = 0; k < UNR; ++k) v[k] = e3m_gload<T>(col, pv, st, j0, rows, sl, rb + k * RS);
+#pragma unroll
+                for (int k = 0; k < UNR; ++k)
+                    if (rb + k * RS < rows) lds[pst * PS + rb + k * RS] = v[k];
             }
         }
-    }
-    __syncthreads();
+    };
+    T pf[NPF];
+
     const int lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, k4 = lane >> 4;
-    const bool overlay = NMG == 1;  // the tile reuses the staging area
+    const bool overlay = NMG == 1;  // the output tile reuses the staging area
+    const bool prefetch = buf && overlay && rows <= NPF * RS;
     T *tile = overlay ? lds : lds + (size_t)TR * PS;
-    for (int gm = 0; gm < NMG; ++gm) {
-        T res[PPW][4];
+
+    if (prefetch) {
+        const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, (size_t)t * TR);
 #pragma unroll
-        for (int pi = 0; pi < PPW; ++pi) {
-            const int P = (wave + 4 * pi) * PS;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int ga = 0; ga < NAG; ++ga) {
-                T b[4];
+        for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0 + k * RS);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) b[s] = lds[P + 256 * ga + 16 * c16 + 4 * s + k4];
-                const int D0 = g.m_lo - 1 + 256 * (gm - ga);
-                // e with some H' index D0 + 16 e + [-15, 15] inside [0, nHe)
-                const int e_lo = max(-15, -((D0 + 15) >> 4));
-                const int e_hi = min(15, (nHe + 14 - D0) >> 4);
-                const T *hb = lds + (P + PA + 32 + D0 + c16 - k4);
-                if (e_lo == 0 && e_hi == 15)
-                    e3m_all<T, 0, 15>(hb, b, acc);
-                else
-                    e3m_some<T, -15>(hb, b, e_lo, e_hi, acc);
+        for (int k = 0; k < NPF; ++k)
+            if (r0 + k * RS < rows) lds[pst * PS + r0 + k * RS] = pf[k];
+    } else {
+        stage_sync((size_t)t * TR);
+    }
+    __syncthreads();
+    for (;;) {
+        const size_t p0 = (size_t)t * TR;
+        const int tn = t + bx;
+        const bool more = tn < t_end;
+        if (prefetch && more) {  // in flight during the products
+            const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, (size_t)tn * TR);
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0 + k * RS);
+        }
+        for (int gm = 0; gm < NMG; ++gm) {
+            T res[PPW][4];
+#pragma unroll
+            for (int pi = 0; pi < PPW; ++pi) {
+                const int P = (wave + 4 * pi) * PS;
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int ga = 0; ga < NAG; ++ga) {
+                    T b[4];
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] = lds[P + 256 * ga + 16 * c16 + 4 * s4 + k4];
+                    const int D0 = g.m_lo - 1 + 256 * (gm - ga);
+                    // e with some H' index D0 + 16 e + [-15, 15] inside [0, nHe)
+                    const int e_lo = max(-15, -((D0 + 15) >> 4));
+                    const int e_hi = min(15, (nHe + 14 - D0) >> 4);
+                    const T *hb = lds + (P + PA + 32 + D0 + c16 - k4);
+                    if (e_lo == 0 && e_hi == 15)
+                        e3m_all<T>(hb, b, acc);
+                    else
+                        e3m_some<T>(hb, b, e_lo, e_hi, acc);
+                }
+                if (overlay) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) res[pi][r] = (T)acc[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = (T)acc[r];
+                }
             }
+            __syncthreads();
             if (overlay) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) res[pi][r] = (T)acc[r];
-            } else {
+                for (int pi = 0; pi < PPW; ++pi)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = (T)acc[r];
+                    for (int r = 0; r < 4; ++r)
+                        tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = res[pi][r];
+                __syncthreads();
             }
-        }
-        __syncthreads();
-        if (overlay) {
-#pragma unroll
-            for (int pi = 0; pi < PPW; ++pi)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tile[(16 * c16 + mfma_row<T>(r, k4)) * TS + wave + 4 * pi] = res[pi][r];
+            const int mb = g.m_lo + 256 * gm;
+            for (int it = tid; it < 256 * TR; it += kThreads) {
+                const int row = it / TR, p = it % TR;
+                const int m = mb + row;
+                if (m <= g.m_hi && p0 + p < sl) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = tile[row * TS + p];
+            }
             __syncthreads();
         }
-        const int mb = g.m_lo + 256 * gm;
-        for (int it = tid; it < 256 * TR; it += kThreads) {
-            const int row = it / TR, p = it % TR;
-            const int m = mb + row;
-            if (m <= g.m_hi && p0 + p < sl) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = tile[row * TS + p];
-        }
+        if (!more) break;
+        t = tn;
+        if (prefetch) {
+#pragma unroll
+            for (int k = 0; k < NPF; ++k)
+                if (r0 + k * RS < rows) lds[pst * PS + r0 + k * RS] = pf[k];
+        } else
+            stage_sync((size_t)t * TR);
         __syncthreads();
     }
 }
@@ -1100,7 +1282,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
         v[s] = mk<T>(stage[(2 * line) * SW + rr], stage[(2 * line + 1) * SW + rr]);
     }
     __syncthreads();
-    F::run(v, lds + line * N, tw, 0, gg, line);
+    F::run(v, lds + line * N, tw, 0, gg, lds_xor_gfast<N, G>(line));
 
     const T sc = (T)scale;
     for (int half = 0; half < 2; ++half) {
@@ -1474,6 +1656,40 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     return hipGetLastError();
 }
 
+#define LH_HIP_TRY(x)                     \
+    do {                                  \
+        const hipError_t e_ = (x);        \
+        if (e_ != hipSuccess) return e_;  \
+    } while (0)
+
+// Persistent launch of the matrix-core window: as many blocks as fit on the
+// device at once (a multiple of 8, one share per XCD), each walking tiles.
+template <typename T, int TR>
+static hipError_t launch_e3m(const Plan &pl, T *spr, int ntiles, size_t lds, hipStream_t st)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, int> fit;  // (device, LDS bytes) -> blocks per CU
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = fit.find({pl.device, lds});
+        if (it != fit.end()) {
+            per_cu = it->second;
+        } else {
+            LH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(&k_e3m<T, TR>), kThreads, lds));
+            per_cu = std::max(1, per_cu);
+            fit[{pl.device, lds}] = per_cu;
+        }
+    }
+    int ncu = 0;
+    LH_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl.device));
+    const long want = ((long)ntiles + 7) / 8 * 8;
+    const int blocks = (int)std::max(8L, std::min(want, (long)ncu * per_cu / 8 * 8));
+    hipLaunchKernelGGL((k_e3m<T, TR>), dim3(blocks), dim3(kThreads), lds, st, spr, pl.g, ntiles);
+    return hipGetLastError();
+}
+
 // The energy-window pass alone (autotuner timing).
 template <typename T>
 static hipError_t window_t(const Plan &pl, hipStream_t st)
@@ -1497,14 +1713,13 @@ static hipError_t window_t(const Plan &pl, hipStream_t st)
         if (g.e3_variant == 1) {
             const size_t tile = (size_t)256 * (g.e3m_TR + 1), stage = (size_t)g.e3m_TR * g.e3m_PS;
             const size_t ldsm = (g.e3m_NMG == 1 ? std::max(tile, stage) : tile + stage) * es;
-            const dim3 gm(cdiv(g.slice_e, g.e3m_TR));
+            const int ntiles = (int)cdiv(g.slice_e, g.e3m_TR);
             switch (g.e3m_TR) {
-            case 32: hipLaunchKernelGGL((k_e3m<T, 32>), gm, dim3(kThreads), ldsm, st, spr, g); break;
-            case 16: hipLaunchKernelGGL((k_e3m<T, 16>), gm, dim3(kThreads), ldsm, st, spr, g); break;
-            case 8: hipLaunchKernelGGL((k_e3m<T, 8>), gm, dim3(kThreads), ldsm, st, spr, g); break;
-            default: hipLaunchKernelGGL((k_e3m<T, 4>), gm, dim3(kThreads), ldsm, st, spr, g); break;
+            case 32: return launch_e3m<T, 32>(pl, spr, ntiles, ldsm, st);
+            case 16: return launch_e3m<T, 16>(pl, spr, ntiles, ldsm, st);
+            case 8: return launch_e3m<T, 8>(pl, spr, ntiles, ldsm, st);
+            default: return launch_e3m<T, 4>(pl, spr, ntiles, ldsm, st);
             }
-            return hipGetLastError();
         }
         switch (g.e3_TR) {
         case 64: LH_E3(64); break;

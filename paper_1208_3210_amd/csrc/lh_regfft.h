@@ -6,8 +6,8 @@
 // in registers inside a pass; between passes they are exchanged through the
 // line's LDS buffer (N complex values, XOR-swizzled so that the stride-r
 // writes of the first pass and the unit-stride reads are free of bank
-// conflicts; a per-line XOR of the low four index bits spreads lanes that
-// work on different lines of the same wave over different banks).
+// conflicts; a per-line XOR chosen by the caller for its lane layout spreads
+// lanes that work on different lines of the same wave over different banks).
 // Autosort: no bit reversal anywhere.
 //
 // Convention on entry and on exit: thread g of the line holds
@@ -166,14 +166,37 @@ struct RegFFT {
 
     // Transform one line.  Every thread of the block must call this (it
     // contains block barriers).  buf: N complex values of LDS for this line;
-    // line: index of the line within the block (only its low bits are used).
-    // Ends with a barrier when there is more than one pass, so buf may be
-    // reused right after.
+    // lx: XOR applied to every LDS index of this line (0 <= lx < N; see
+    // lds_xor_interleaved / lds_xor_gfast).  Ends with a barrier when there is
+    // more than one pass, so buf may be reused right after.
     __device__ static __forceinline__ void run(cx<T> *v, cx<T> *buf, const cx<T> *__restrict__ tw, int twsh,
-                                               int g, int line = 0)
+                                               int g, int lx = 0)
     {
-        passes<0>(v, buf, tw, twsh, g, N >= 16 ? (line & 15) : 0);
+        passes<0>(v, buf, tw, twsh, g, lx);
     }
 };
+
+// LDS banks hold 64 dwords: 32 FP32 or 16 FP64 complex values.
+template <typename T>
+constexpr int lds_bank_elems()
+{
+    return sizeof(T) == 4 ? 32 : 16;
+}
+
+// Per-line XOR when NL lines are interleaved lane by lane (lane = g NL + line):
+// the lines of one 32-lane group then occupy disjoint bank ranges.
+template <typename T, int N>
+__device__ __forceinline__ int lds_xor_interleaved(int line, int NL)
+{
+    const int m = lds_bank_elems<T>() / NL;
+    return (line * (m > 0 ? m : 1)) & (N - 1);
+}
+
+// Per-line XOR when each line takes G consecutive lanes (lane = line G + g).
+template <int N, int G>
+__device__ __forceinline__ int lds_xor_gfast(int line)
+{
+    return (line * G) & (N - 1);
+}
 
 }  // namespace lh
