@@ -993,14 +993,19 @@ __device__ __forceinline__ void e3m_some(const T *hb, const T (&b)[4], int e_lo,
     }
 }
 
-// Registers per thread that hold the next tile's staging loads.
-constexpr int kE3mPF = 24;
+// 16-byte staging loads: VEC consecutive points of one row per lane.
+template <typename T>
+struct Vec16 {
+    T v[16 / sizeof(T)];
+};
+typedef unsigned lh_u4 __attribute__((ext_vector_type(4)));
 
 // Staging geometry of one thread: P' rows a < nA, H' rows x < nHe (at row
-// PA + 32 + x), point pst, slice stride sb bytes.
+// PA + 32 + x), byte offset qb of its points within the tile row, slice
+// stride sb bytes.
 struct E3mStage {
-    int PA, nA, nHe, pst;
-    unsigned sb;
+    int PA, nA, nHe;
+    unsigned qb, sb;
 };
 struct E3mRsrc {
     __amdgpu_buffer_rsrc_t P, H;
@@ -1021,29 +1026,40 @@ __device__ __forceinline__ E3mRsrc e3m_rsrc(T *spec, size_t sl, int j0, int nA, 
     return r;
 }
 
-// Staged row rr of point st.pst (0 for the zero rows: out-of-range offset).
+// Staged row rr of this thread's points (0 for the zero rows: out-of-range
+// offset; the P' / H' choice is wave-uniform).
 template <typename T>
-__device__ __forceinline__ T e3m_bload(const E3mRsrc &rs, const E3mStage &st, int rr)
+__device__ __forceinline__ Vec16<T> e3m_bload(const E3mRsrc &rs, const E3mStage &st, int rr)
 {
-    const bool wP = __builtin_amdgcn_readfirstlane(rr) < st.PA;  // wave-uniform
+    const bool wP = __builtin_amdgcn_readfirstlane(rr) < st.PA;
     const int x = rr - st.PA - 32;
-    const unsigned po = (unsigned)st.pst * (unsigned)sizeof(T);
     unsigned off;
     if (wP)
-        off = rr < st.nA ? (unsigned)(st.nA - 1 - rr) * st.sb + po : 0xFFFFFFF0u;
+        off = rr < st.nA ? (unsigned)(st.nA - 1 - rr) * st.sb + st.qb : 0xFFFFFFF0u;
     else
-        off = (x >= 0 && x < st.nHe) ? (unsigned)x * st.sb + po : 0xFFFFFFF0u;
-    if constexpr (sizeof(T) == 4) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(wP ? rs.P : rs.H, (int)off, 0, 0));
-    } else {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(wP ? rs.P : rs.H, (int)off, 0, 0);
-        return __builtin_bit_cast(double, v);
+        off = (x >= 0 && x < st.nHe) ? (unsigned)x * st.sb + st.qb : 0xFFFFFFF0u;
+    const lh_u4 w = __builtin_amdgcn_raw_buffer_load_b128(wP ? rs.P : rs.H, (int)off, 0, 0);
+    return __builtin_bit_cast(Vec16<T>, w);
+}
+
+// Write a staged row of this thread's points into the point-major LDS layout.
+template <typename T>
+__device__ __forceinline__ void e3m_put(T *lds, int PS, int pq, int rows, int rr, const Vec16<T> &v)
+{
+    if (rr < rows) {
+#pragma unroll
+        for (int i = 0; i < (int)(16 / sizeof(T)); ++i) lds[(pq + i) * PS + rr] = v.v[i];
     }
 }
 
-// The same row with a plain global load (any size).
+// Scalar staging (plain global loads, any size): point pst, slice stride sl.
+struct E3mStageS {
+    int PA, nA, nHe, pst;
+};
+
+// One staged row with a plain global load (any size).
 template <typename T>
-__device__ __forceinline__ T e3m_gload(const T *col, bool pv, const E3mStage &st, int j0, int rows, size_t sl,
+__device__ __forceinline__ T e3m_gload(const T *col, bool pv, const E3mStageS &st, int j0, int rows, size_t sl,
                                        int rr)
 {
     int js;
@@ -1067,7 +1083,6 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
     static_assert(TR >= 4 && (TR & (TR - 1)) == 0, "TR: power of two >= 4");
     constexpr int PPW = TR / 4;  // points per wave
     constexpr int TS = TR + 1;   // row stride of the output tile
-    constexpr int NPF = kE3mPF;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int PA = g.e3m_PA, nA = g.e3m_nA, nHe = g.e3m_nHe, PS = g.e3m_PS;
@@ -1084,55 +1099,60 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
     int t = xcd * per + bi;
     if (t >= t_end) return;
 
-    // Staging: thread tid always loads point pst = tid % TR, rows r0 + k RS
-    // (the 64 / TR rows of one wave at one k never straddle the P' / H'
-    // boundary, whose row indices are multiples of 32).  With buffer loads
-    // (both slice ranges below 4 GiB) rows of zeros get an out-of-range offset
-    // and read 0, and every load of a thread is in flight at once.
-    constexpr int RS = kThreads / TR;
-    const int pst = tid % TR, r0 = tid / TR;
+    // Staging with buffer loads (both slice ranges below 4 GiB): each lane
+    // loads VEC consecutive points (16 bytes) of one row, LR lanes per row,
+    // rows r0 + k RP (the 64 / LR rows of one wave at one k never straddle
+    // the P' / H' boundary, a multiple of 256); rows of zeros get an
+    // out-of-range offset and read 0.  Otherwise plain global loads, one
+    // point per lane.
+    constexpr int VEC = 16 / sizeof(T);
+    static_assert(TR >= VEC, "a tile row holds at least one 16-byte load");
+    constexpr int LR = TR / VEC, RP = kThreads / LR;
+    constexpr int NPF = (TR == 16 && sizeof(T) == 4) ? 10 : 6;  // 16-byte registers of the next tile
+    const int q = tid % LR, r0 = tid / LR;
     const bool buf = g.e3m_buf != 0;
-    const E3mStage st{PA, nA, nHe, pst, (unsigned)(sl * sizeof(T))};
+    const E3mStage st{PA, nA, nHe, (unsigned)(q * 16), (unsigned)(sl * sizeof(T))};
     auto stage_sync = [&](size_t p0) {
-        constexpr int UNR = 8;
         if (buf) {
+            constexpr int UNR = 4;
             const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, p0);
-            for (int rb = r0; rb < rows; rb += UNR * RS) {
-                T v[UNR];
+            for (int rb = r0; rb < rows; rb += UNR * RP) {
+                Vec16<T> v[UNR];
 #pragma unroll
-                for (int k = 0; k < UNR; ++k) v[k] = e3m_bload<T>(rs, st, rb + k * RS);
+                for (int k = 0; k < UNR; ++k) v[k] = e3m_bload<T>(rs, st, rb + k * RP);
 #pragma unroll
-                for (int k = 0; k < UNR; ++k)
-                    if (rb + k * RS < rows) lds[pst * PS + rb + k * RS] = v[k];
+                for (int k = 0; k < UNR; ++k) e3m_put<T>(lds, PS, q * VEC, rows, rb + k * RP, v[k]);
             }
         } else {
+            constexpr int UNR = 8, RS = kThreads / TR;
+            const int pst = tid % TR, r0s = tid / TR;
+            const E3mStageS sts{PA, nA, nHe, pst};
             const bool pv = p0 + pst < sl;
             const T *col = spec + (pv ? p0 + pst : 0);
-            for (int rb = r0; rb < rows; rb += UNR * RS) {
+            for (int rb = r0s; rb < rows; rb += UNR * RS) {
                 T v[UNR];
 #pragma unroll
-                for (int k = 0; k < UNR; ++k) v[k] = e3m_gload<T>(col, pv, st, j0, rows, sl, rb + k * RS);
+                for (int k = 0; k < UNR; ++k) v[k] = e3m_gload<T>(col, pv, sts, j0, rows, sl, rb + k * RS);
 #pragma unroll
                 for (int k = 0; k < UNR; ++k)
                     if (rb + k * RS < rows) lds[pst * PS + rb + k * RS] = v[k];
             }
         }
     };
-    T pf[NPF];
+    Vec16<T> pf[NPF];
 
     const int lane = tid & 63, wave = tid >> 6;
     const int c16 = lane & 15, k4 = lane >> 4;
     const bool overlay = NMG == 1;  // the output tile reuses the staging area
-    const bool prefetch = buf && overlay && rows <= NPF * RS;
+    const bool prefetch = buf && overlay && rows <= NPF * RP;
     T *tile = overlay ? lds : lds + (size_t)TR * PS;
 
     if (prefetch) {
         const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, (size_t)t * TR);
 #pragma unroll
-        for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0 + k * RS);
+        for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0 + k * RP);
 #pragma unroll
-        for (int k = 0; k < NPF; ++k)
-            if (r0 + k * RS < rows) lds[pst * PS + r0 + k * RS] = pf[k];
+        for (int k = 0; k < NPF; ++k) e3m_put<T>(lds, PS, q * VEC, rows, r0 + k * RP, pf[k]);
     } else {
         stage_sync((size_t)t * TR);
     }
@@ -1143,8 +1163,13 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
         const bool more = tn < t_end;
         if (prefetch && more) {  // in flight during the products
             const E3mRsrc rs = e3m_rsrc(spec, sl, j0, nA, nHe, (size_t)tn * TR);
+            // The row offsets do not change from tile to tile; hiding r0 from
+            // the optimiser keeps it from holding all NPF of them in registers
+            // for the whole kernel (they are cheap to recompute).
+            int r0v = r0;
+            asm volatile("" : "+v"(r0v));
 #pragma unroll
-            for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0 + k * RS);
+            for (int k = 0; k < NPF; ++k) pf[k] = e3m_bload<T>(rs, st, r0v + k * RP);
         }
         for (int gm = 0; gm < NMG; ++gm) {
             T res[PPW][4];
@@ -1185,10 +1210,21 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
                 __syncthreads();
             }
             const int mb = g.m_lo + 256 * gm;
-            for (int it = tid; it < 256 * TR; it += kThreads) {
-                const int row = it / TR, p = it % TR;
+            for (int it = tid; it < 256 * LR; it += kThreads) {
+                const int row = it / LR, pq = (it % LR) * VEC;
                 const int m = mb + row;
-                if (m <= g.m_hi && p0 + p < sl) spec[(size_t)(m - g.m_lo) * sl + p0 + p] = tile[row * TS + p];
+                if (m > g.m_hi) continue;
+                const size_t pb = p0 + pq;
+                T *dst = spec + (size_t)(m - g.m_lo) * sl + pb;
+                if (pb + VEC <= sl) {
+                    Vec16<T> v;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) v.v[i] = tile[row * TS + pq + i];
+                    *reinterpret_cast<lh_u4 *>(dst) = __builtin_bit_cast(lh_u4, v);
+                } else {
+                    for (int i = 0; i < VEC; ++i)
+                        if (pb + i < sl) dst[i] = tile[row * TS + pq + i];
+                }
             }
             __syncthreads();
         }
@@ -1196,8 +1232,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
         t = tn;
         if (prefetch) {
 #pragma unroll
-            for (int k = 0; k < NPF; ++k)
-                if (r0 + k * RS < rows) lds[pst * PS + r0 + k * RS] = pf[k];
+            for (int k = 0; k < NPF; ++k) e3m_put<T>(lds, PS, q * VEC, rows, r0 + k * RP, pf[k]);
         } else
             stage_sync((size_t)t * TR);
         __syncthreads();
