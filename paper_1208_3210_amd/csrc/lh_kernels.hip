@@ -138,6 +138,13 @@ __global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const 
     w[idx] = v;
 }
 
+// 16 bytes of consecutive elements (one vector load or store per lane).
+template <typename T>
+struct Vec16 {
+    T v[16 / sizeof(T)];
+};
+typedef unsigned lh_u4 __attribute__((ext_vector_type(4)));
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Map launch index b to a logical tile so that consecutive logical tiles run
 // on the same XCD: tiles sharing cache lines then meet in the same L2.
@@ -615,9 +622,10 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
         xb[s] = xi[(size_t)kyb * N + gg + s * G];
     }
     const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
-    const int Ce = g.Ce, logCe = g.logCe, H = N / 2;
+    const int Ce = g.Ce, H = N / 2;
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
-    const int nout = g.NTe * rows * Ce;
+    constexpr int VEC = 16 / sizeof(T), HV = 32 / 16, logHV = 1;  // 16-byte pieces of a 32-byte tile row
+    const int nvec = g.NTe * rows * HV;
     for (int j = jbeg; j < jend; ++j) {
         const double ej = emin + (j + 0.5) * deps;
         cx<T> v[E];
@@ -627,20 +635,30 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
             v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
         F::run(v, buf, tw, 0, gg, lds_xor_gfast<N, G>(line));
+        // only rx in [0, nkx/2] is stored
 #pragma unroll
-        for (int s = 0; s < E; ++s) buf[gg + s * G] = v[s];
+        for (int s = 0; s <= E / 2; ++s)
+            if (gg + s * G <= H) buf[gg + s * G] = v[s];
         __syncthreads();
+        // Each item: VEC consecutive rx of one output row (16 bytes), items
+        // ordered half-row, row, tile so that a block writes whole tiles.
         T *dst = spec + (size_t)(j - g.jA) * g.slice_e;
-        for (int it = tid; it < nout; it += R * G) {
-            const int c = it & (Ce - 1);
-            const int r = (it >> logCe) & (rows - 1);
-            const int tile = (it >> logCe) >> logRows;
-            const int rx = tile * Ce + c;
+        for (int it = tid; it < nvec; it += R * G) {
+            const int h = it & (HV - 1);
+            const int r = (it >> logHV) & (rows - 1);
+            const int tile = (it >> logHV) >> logRows;
             const int ky = 2 * p0 + r;
             if (ky >= g.Hy) continue;
-            const cx<T> z = lds[(r >> 1) * N + min(rx, H)];
-            const T val = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
-            dst[((size_t)tile * g.Hy + ky) * Ce + c] = val;
+            const cx<T> *zl = lds + (r >> 1) * N;
+            const int rx0 = tile * Ce + h * VEC;
+            Vec16<T> o;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                const int rx = rx0 + i;
+                const cx<T> z = zl[min(rx, H)];
+                o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
+            }
+            *reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.Hy + ky) * Ce + h * VEC) = __builtin_bit_cast(lh_u4, o);
         }
         __syncthreads();
     }
@@ -993,12 +1011,6 @@ __device__ __forceinline__ void e3m_some(const T *hb, const T (&b)[4], int e_lo,
     }
 }
 
-// 16-byte staging loads: VEC consecutive points of one row per lane.
-template <typename T>
-struct Vec16 {
-    T v[16 / sizeof(T)];
-};
-typedef unsigned lh_u4 __attribute__((ext_vector_type(4)));
 
 // Staging geometry of one thread: P' rows a < nA, H' rows x < nHe (at row
 // PA + 32 + x), byte offset qb of its points within the tile row, slice
@@ -1277,35 +1289,43 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
         }
         return;
     }
-    const int Ce = g.Ce, logCe = g.logCe;
+    const int Ce = g.Ce;
     const T *src = spec + (size_t)slot * g.slice_e;
-    const int nin = g.NTe * rows * Ce;
+    constexpr int VEC = 16 / sizeof(T), HV = 2, logHV = 1;  // 16-byte pieces of a 32-byte tile row
+    const int nvec = g.NTe * rows * HV;
     const cx<T> *tw = twx;
     if (sizeof(T) == 4) {
         cx<T> *twl = lds + R * N;
         for (int i = tid; i < N; i += nthr) twl[i] = twx[i];
         tw = twl;  // made visible by the barrier after the staging loop
     }
-    for (int it0 = tid; it0 < nin; it0 += 8 * nthr) {
-        T v[8];
+    // 16-byte loads (items ordered half-row, row, tile), independent in
+    // batches of 4 so that they overlap
+    for (int it0 = tid; it0 < nvec; it0 += 4 * nthr) {
+        Vec16<T> v[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const int it = it0 + k * nthr;
-            const int c = it & (Ce - 1);
-            const int r = (it >> logCe) & (rows - 1);
-            const int tile = (it >> logCe) >> logRows;
+            const int h = it & (HV - 1);
+            const int r = (it >> logHV) & (rows - 1);
+            const int tile = (it >> logHV) >> logRows;
             const int qy = 2 * p0 + r;
-            const bool ok = it < nin && qy < Hy;
-            const T x = src[ok ? ((size_t)tile * Hy + qy) * Ce + c : 0];
-            v[k] = ok ? x : (T)0;
+            const bool ok = it < nvec && qy < Hy;
+            const lh_u4 x = *reinterpret_cast<const lh_u4 *>(src + (ok ? ((size_t)tile * Hy + qy) * Ce + h * VEC : 0));
+            v[k] = __builtin_bit_cast(Vec16<T>, x);
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const int it = it0 + k * nthr;
-            const int c = it & (Ce - 1);
-            const int r = (it >> logCe) & (rows - 1);
-            const int rx = ((it >> logCe) >> logRows) * Ce + c;
-            if (it < nin && rx <= H) stage[r * SW + rx] = v[k];
+            const int h = it & (HV - 1);
+            const int r = (it >> logHV) & (rows - 1);
+            const int rx0 = ((it >> logHV) >> logRows) * Ce + h * VEC;
+            const int qy = 2 * p0 + r;
+            if (it < nvec) {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i)
+                    if (rx0 + i <= H) stage[r * SW + rx0 + i] = qy < Hy ? v[k].v[i] : (T)0;
+            }
         }
     }
     __syncthreads();
