@@ -236,15 +236,19 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.NTe = (g.L + 1 + g.Ce - 1) / g.Ce;
         g.Hy = p->nky / 2 + 1;
         g.slice_e = (size_t)g.NTe * g.Hy * g.Ce;
-        const int Ex = std::min(16, p->nkx), Gx = p->nkx / Ex;
         const int np = (g.Hy + 1) / 2;
-        int R = std::max(1, 256 / Gx);
-        // LDS: R line buffers of nkx complex (+ the FP32 twiddle table)
-        while (R > 1 && (size_t)(R + (g.fp64 ? 0 : 1)) * p->nkx * cs > 65536) R >>= 1;
-        R = std::min(R, 1 << ilog2(np));
-        if ((1 << ilog2(np)) > np) R = std::min(R, 1 << (ilog2(np) - 1));
-        g.e1_R = std::max(1, R);
-        g.e5_R = g.e1_R;
+        // row pairs per block for register FFTs of E elements per thread
+        auto rows_per_block = [&](int E) {
+            const int Gx = p->nkx / std::min(E, p->nkx);
+            int R = std::max(1, 256 / Gx);
+            // LDS: R line buffers of nkx complex (+ the FP32 twiddle table)
+            while (R > 1 && (size_t)(R + (g.fp64 ? 0 : 1)) * p->nkx * cs > 65536) R >>= 1;
+            R = std::min(R, 1 << ilog2(np));
+            if ((1 << ilog2(np)) > np) R = std::min(R, 1 << (ilog2(np) - 1));
+            return std::max(1, R);
+        };
+        g.e1_R = rows_per_block(kE1Elems);
+        g.e5_R = rows_per_block(16);
         {
             const long blocks = (np + g.e1_R - 1) / g.e1_R;
             long jc = (blocks * std::max(g.nS, 1)) / 4096;

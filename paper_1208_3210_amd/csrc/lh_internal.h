@@ -62,6 +62,12 @@ struct Geo {
     int tuned;                // 1: window schedule chosen by timing, 2: from the tuning cache
 };
 
+// Elements per thread of the register FFTs in the even builder pass (the
+// builder also keeps the band rows of its lines in registers).
+constexpr int kE1Elems = 8;
+
+constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
+
 struct Plan {
     lindhard_problem p{};
     std::vector<double> omega;

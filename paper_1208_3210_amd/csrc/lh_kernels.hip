@@ -595,7 +595,7 @@ template <typename T, int LOGNX>
 __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec)
 {
-    using F = RegFFT<T, LOGNX, false>;
+    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     constexpr int N = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N]
@@ -1566,7 +1566,7 @@ template <typename T, int LOGNX>
 static void launch_e1(const Plan &pl, T *spec, hipStream_t st)
 {
     const Geo &g = pl.g;
-    using F = RegFFT<T, LOGNX, false>;
+    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e1<T, LOGNX>), dim3(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc)), dim3(g.e1_R * F::G),
                        (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,

@@ -1,6 +1,7 @@
 // lh_regfft.h -- register-resident Stockham FFT for one line of length
 // N = 2^LOGN held by G = N/E threads with E = min(16, N) elements each.
 //
+// E = min(N, 2^LOGE_MAX), 16 by default.
 // Passes: radix E, ..., radix E, then one pass of the remaining radix
 // (2..E), each thread doing E / r butterflies of radix r per pass.  Values stay
 // in registers inside a pass; between passes they are exchanged through the
@@ -96,10 +97,10 @@ __device__ __forceinline__ void rdft(cx<T> *v)
 
 __device__ __forceinline__ int swz(int x) { return x ^ ((x >> 4) & 15); }
 
-template <typename T, int LOGN, bool INV>
+template <typename T, int LOGN, bool INV, int LOGE_MAX = 4>
 struct RegFFT {
     static constexpr int N = 1 << LOGN;
-    static constexpr int LOGE = LOGN < 4 ? LOGN : 4;
+    static constexpr int LOGE = LOGN < LOGE_MAX ? LOGN : LOGE_MAX;
     static constexpr int E = 1 << LOGE;
     static constexpr int G = N / E;
     static constexpr int NPASS = LOGN == 0 ? 0 : (LOGN + LOGE - 1) / LOGE;
