@@ -251,3 +251,51 @@ def rpa(re_chi, im_chi, U: float):
     chi = np.asarray(re_chi, dtype=np.float64) + 1j * np.asarray(im_chi, dtype=np.float64)
     r = chi / (1.0 - U * chi)
     return r.imag, r.real
+
+
+def coulomb_v(hx, hy, v: float) -> np.ndarray:
+    """Coulomb interaction V(Q) = v / |Q|^2 on the extended grid, the form
+    the paper gives for the RPA denominator (Sec. 4: V_q decays as 1/q^2),
+    with Q = 2 pi (h, l) in units of 1/a (h, l in reciprocal-lattice units,
+    see ``zone_axis``).  Shape (len(hy), len(hx)); +inf at Q = 0."""
+    hx = np.asarray(hx, dtype=np.float64)
+    hy = np.asarray(hy, dtype=np.float64)
+    q2 = (2.0 * np.pi) ** 2 * (hx[None, :] ** 2 + hy[:, None] ** 2)
+    with np.errstate(divide="ignore"):
+        return np.where(q2 > 0.0, v / np.where(q2 > 0.0, q2, 1.0), np.inf)
+
+
+def rpa_coulomb(re_chi, im_chi, hx, hy, v: float):
+    """chi_RPA = chi / (1 - V(Q) chi) with the Coulomb V of ``coulomb_v``,
+    diagonal in G (no local fields), in FP64 complex arithmetic.  Arrays are
+    [..., Y, X] on the extended grid.  At Q = 0 the interaction is infinite
+    and chi_RPA takes its limit, 0.  Returns (Im chi_RPA, Re chi_RPA)."""
+    chi = np.asarray(re_chi, dtype=np.float64) + 1j * np.asarray(im_chi, dtype=np.float64)
+    V = coulomb_v(hx, hy, v)
+    fin = np.isfinite(V)
+    Vf = np.where(fin, V, 0.0)
+    r = np.where(fin, chi / (1.0 - Vf * chi), 0.0)
+    return r.imag, r.real
+
+
+def structure_factor(im_chi, omega, kT: float) -> np.ndarray:
+    """Dynamical structure factor from Im chi by the fluctuation-dissipation
+    relation, Eq. (1): S = -(1/pi) Im chi / (1 - exp(-omega / kT)), omega and
+    kT in eV, axis 0 of ``im_chi`` running over ``omega``.  kT = 0 is the
+    zero-temperature limit (factor 1 for omega > 0, 0 for omega < 0); at
+    omega = 0 the discrete Im chi is exactly 0 and S is set to 0."""
+    im = np.asarray(im_chi, dtype=np.float64)
+    om = np.asarray(omega, dtype=np.float64).reshape((-1,) + (1,) * (im.ndim - 1))
+    if kT > 0.0:
+        safe = np.where(om == 0.0, 1.0, om)
+        bose = np.where(om == 0.0, 0.0, 1.0 / (-np.expm1(-safe / kT)))
+    else:
+        bose = np.where(om > 0.0, 1.0, 0.0) + 0.0 * om
+    return -(1.0 / np.pi) * im * bose
+
+
+def peak_index(im_chi) -> np.ndarray:
+    """Index along axis 0 of the largest -Im chi (the RPA plasmon peaks,
+    Sec. 4), the first one on ties."""
+    im = np.asarray(im_chi)
+    return np.argmin(im, axis=0).astype(np.int32)
