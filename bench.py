@@ -172,6 +172,50 @@ def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
             "latency_note": "submit -> result ready, host clock, requests after warm-up"}
 
 
+def bench_epilogues(LH, W, torch, reps=3):
+    """The RPA-side epilogues on the extended-zone workload (512^2 k, 256
+    energies, 5x5 zones, orbital form factor, 128 omegas, FP32): Kramers-
+    Kronig + contact RPA, Coulomb RPA, S(q, omega) and the peak search, each
+    timed with events on the launch stream against its algorithmic HBM bytes."""
+    cfg = W.config2()
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    im = plan.exec()
+    re, imr, rer = plan.empty(), plan.empty(), plan.empty()
+    s_out = plan.empty()
+    pk = torch.empty(plan.shape[1:], dtype=torch.int32, device="cuda")
+    h = plan.handle
+    sp = lambda: LH._stream_ptr(None)  # noqa: E731
+    n_out = im.numel() * 4
+    nk = cfg["nkx"] * cfg["nky"]
+    first_zone = nk * cfg["neps"] * 4 + 2 * nk * len(cfg["omega"]) * 4  # KK reads all lags, writes Re, RPA re-reads
+    steps = {
+        "rpa_contact": (lambda: LH.lindhard_rpa(h, W.CONFIG2_U, re.data_ptr(), imr.data_ptr(), rer.data_ptr(), sp()),
+                        first_zone + 3 * n_out),
+        "rpa_coulomb": (lambda: LH.lindhard_rpa_coulomb(h, 0.5, re.data_ptr(), imr.data_ptr(), rer.data_ptr(), sp()),
+                        first_zone + 3 * n_out),
+        "structure_factor": (lambda: LH.lindhard_structure_factor(h, 0.025, imr.data_ptr(), s_out.data_ptr(), sp()),
+                             2 * n_out),
+        "peak_index": (lambda: LH.lindhard_peak_index(h, imr.data_ptr(), pk.data_ptr(), sp()), n_out + pk.numel() * 4),
+    }
+    out = {"workload": "512^2 k, 256 energies, 5x5 zones, d(x2-y2) form factor, 128 omegas, FP32",
+           "points": int(im.numel())}
+    for name, (fn, nbytes) in steps.items():
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "alg_GB": nbytes / 1e9, "GB/s": nbytes / (ms * 1e-3) / 1e9,
+                     "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +232,8 @@ def main():
                     help="force the general complex path even for a mirror-symmetric band")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched run")
     ap.add_argument("--no-served", action="store_true", help="skip the served Poisson stream")
+    ap.add_argument("--no-epilogues", action="store_true",
+                    help="skip the RPA / structure-factor / peak epilogues on the extended-zone workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -316,6 +362,10 @@ def main():
     if served:
         print("bench: served p50 %.2f ms p99 %.2f ms" % (served["p50_ms"], served["p99_ms"]), file=sys.stderr,
               flush=True)
+    epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
+    if epi:
+        print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
+                                               if isinstance(v, dict)), file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
     res = {
         "metric": "chi(q,w) points/s at 2048^2 k x 512 eps, FP32 vs FP64 at <=1e-5 rel",
@@ -327,6 +377,7 @@ def main():
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
+        "epilogues": epi,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }

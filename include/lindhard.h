@@ -133,6 +133,34 @@ lindhard_status lindhard_exec_timed(lindhard_plan_t plan, void *im_chi, void *st
 lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void *im_rpa,
                              void *re_rpa, void *stream);
 
+/* lindhard_rpa with the Coulomb interaction the paper names for the RPA
+ * denominator (Sec. 4, V_q decaying as 1/q^2): V(Q) = v / |Q|^2 with
+ * Q = 2 pi (h, l) in units of 1/a, (h, l) the reciprocal-lattice coordinates
+ * of each extended output point, diagonal in G (no local fields); v in
+ * eV a^2.  At Q = 0 the interaction is infinite and im_rpa / re_rpa are 0
+ * (the limit of chi / (1 - V chi)).  Same buffers, ordering and errors as
+ * lindhard_rpa (EINVAL for non-finite v). */
+lindhard_status lindhard_rpa_coulomb(lindhard_plan_t plan, double v, void *re_chi, void *im_rpa,
+                                     void *re_rpa, void *stream);
+
+/* Dynamical structure factor by the fluctuation-dissipation relation,
+ * Eq. (1): s_out = -(1/pi) im / (1 - exp(-omega / kT)) for every element of
+ * `im` (device, out_elems elements of the plan's precision and output layout:
+ * Im chi from lindhard_exec or Im chi_RPA from lindhard_rpa*), omega = m d of
+ * each output plane, kT in eV.  kT = 0 is the zero-temperature limit (factor
+ * 1 for omega > 0); omega = 0 gives 0.  s_out may equal im (in place).
+ * Asynchronous on `stream`.  Errors: EINVAL (NULL, kT < 0 or not finite),
+ * EDEVICE. */
+lindhard_status lindhard_structure_factor(lindhard_plan_t plan, double kT, const void *im, void *s_out,
+                                          void *stream);
+
+/* Peak search (plasmon modes as the peaks of -Im chi_RPA, Sec. 4): for every
+ * extended point (X, Y), the index w in [0, nomega) of the largest -im[w][Y][X]
+ * (the first on ties, compared in the plan's precision) into peak (device,
+ * int32, out_ny * out_nx, row-major).  `im` as for lindhard_structure_factor.
+ * Asynchronous on `stream`.  Errors: EINVAL (NULL), EDEVICE. */
+lindhard_status lindhard_peak_index(lindhard_plan_t plan, const void *im, int32_t *peak, void *stream);
+
 /* Run n independent plans as one batch ordered on `stream`: the instances
  * are forked onto a pool of worker streams (largest first, round-robin) so
  * that instances of mixed grid sizes overlap on the device, and joined back

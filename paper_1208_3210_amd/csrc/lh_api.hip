@@ -314,7 +314,7 @@ size_t plan_footprint(const Plan &pl)
     if (pl.p.want_rpa) {
         b += al((size_t)g.neps * nk * es);
         b += al((size_t)pl.p.nomega * nk * es);
-        b += al((size_t)pl.p.nomega * g.neps * 8);
+        b += al((size_t)(pl.p.nomega + 7) / 8 * 8 * g.neps * 8);
     }
     return b;
 }
@@ -683,7 +683,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     if (pl.p.want_rpa) {
         LH_ALLOC(pl.im1, (size_t)g.neps * nk * es);
         LH_ALLOC(pl.re1, (size_t)pl.p.nomega * nk * es);
-        LH_ALLOC(pl.kkw, (size_t)pl.p.nomega * g.neps * 8);
+        LH_ALLOC(pl.kkw, (size_t)(pl.p.nomega + 7) / 8 * 8 * g.neps * 8);
     }
 #undef LH_ALLOC
     return LINDHARD_OK;
@@ -841,7 +841,45 @@ lindhard_status lindhard_rpa(lindhard_plan_t plan, double U, void *re_chi, void 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
     if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
-    hipError_t e = launch_rpa(plan->pl, U, re_chi, im_rpa, re_rpa, (hipStream_t)stream);
+    hipError_t e = launch_rpa(plan->pl, 0, U, re_chi, im_rpa, re_rpa, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_rpa_coulomb(lindhard_plan_t plan, double v, void *re_chi, void *im_rpa, void *re_rpa,
+                                     void *stream)
+{
+    if (!plan || !std::isfinite(v)) return LINDHARD_EINVAL;
+    if (!plan->pl.p.want_rpa || !plan->pl.executed) return LINDHARD_ESTATE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_rpa(plan->pl, 1, v, re_chi, im_rpa, re_rpa, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_structure_factor(lindhard_plan_t plan, double kT, const void *im, void *s_out, void *stream)
+{
+    if (!plan || !im || !s_out || !std::isfinite(kT) || kT < 0.0) return LINDHARD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_sqw(plan->pl, kT, im, s_out, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_peak_index(lindhard_plan_t plan, const void *im, int32_t *peak, void *stream)
+{
+    if (!plan || !im || !peak) return LINDHARD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_peak(plan->pl, im, peak, (hipStream_t)stream);
     if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
     if (dev != plan->pl.device) (void)hipSetDevice(dev);
     return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;

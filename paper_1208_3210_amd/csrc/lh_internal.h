@@ -65,6 +65,8 @@ struct Geo {
 // Elements per thread of the register FFTs in the even builder pass (the
 // builder also keeps the band rows of its lines in registers).
 constexpr int kE1Elems = 8;
+// ... and in the even column passes (sixteen measured faster than eight there).
+constexpr int kEcolElems = 16;
 
 constexpr int ilog2_c(int v) { return v <= 1 ? 0 : 1 + ilog2_c(v / 2); }
 
@@ -109,7 +111,9 @@ size_t plan_footprint(const Plan &pl);
 
 // Pass launchers (asynchronous on `st`).
 hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev = nullptr);
-hipError_t launch_rpa(const Plan &pl, double U, void *re, void *imr, void *rer, hipStream_t st);
+hipError_t launch_rpa(const Plan &pl, int vkind, double U, void *re, void *imr, void *rer, hipStream_t st);
+hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStream_t st);
+hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st);
 hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
 
 // Setup kernels.

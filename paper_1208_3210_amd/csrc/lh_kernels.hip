@@ -122,17 +122,19 @@ __global__ void __launch_bounds__(kThreads) k_fftab(double2 *__restrict__ tab, i
 }
 
 // Kramers-Kronig weights of the alternate-point rule (Sec. 4):
-// w[i][j] = (2/pi) 2j / (j^2 - i^2) for j - i odd, 1 <= j < neps, else 0.
+// w[i][j] = (2/pi) 2j / (j^2 - i^2) for j - i odd, 1 <= j < neps, else 0,
+// stored j-major, w[j * nwp + i] with nwp = nw rounded up to kKkW (zero
+// padding) so that the weights of consecutive output lags are contiguous.
+constexpr int kKkW = 8;
 __global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const int *__restrict__ lags, int nw,
-                                                 int neps)
+                                                 int nwp, int neps)
 {
     const long idx = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= (long)nw * neps) return;
-    const int wi = (int)(idx / neps), j = (int)(idx % neps);
-    const double i = (double)lags[wi];
+    if (idx >= (long)nwp * neps) return;
+    const int j = (int)(idx / nwp), wi = (int)(idx % nwp);
     double v = 0.0;
-    if (j >= 1 && (((long)j - (long)lags[wi]) & 1)) {
-        const double dj = (double)j;
+    if (wi < nw && j >= 1 && (((long)j - (long)lags[wi]) & 1)) {
+        const double i = (double)lags[wi], dj = (double)j;
         v = (2.0 / kPi) * 2.0 * dj / (dj * dj - i * i);
     }
     w[idx] = v;
@@ -670,7 +672,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
 template <typename T, int LOGN, bool INV>
 __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
 {
-    using F = RegFFT<T, LOGN, INV>;
+    using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems)>;
     constexpr int N = F::N, E = F::E, G = F::G;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;  // complex pairs per tile row
     constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
@@ -1375,32 +1377,48 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
 // Extended, form-factor weighted map from the first-zone planes (RPA path).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, int nkx, int nky, int neps,
-                                                    const int *__restrict__ lags, int zx, int zy, int ff,
+                                                    const int *__restrict__ lags, int nw, int zx, int zy, int ff,
                                                     double ffs, const double2 *__restrict__ ffx,
                                                     const double2 *__restrict__ ffy, T *__restrict__ out,
                                                     int out_nx, int out_ny)
 {
-    const int X = blockIdx.x * kThreads + threadIdx.x;
-    const int Y = blockIdx.y;
-    const int w = blockIdx.z;
-    if (X >= out_nx) return;
-    const int m = lags[w];
-    const int u = (X - (zx * nkx) / 2) & (nkx - 1);
-    const int v = (Y - (zy * nky) / 2) & (nky - 1);
-    T val = (T)0;
-    if (m >= 1 && m < neps) {
-        val = im1[((size_t)m * nky + v) * nkx + u];
-        if (ff) val = (T)((double)val * form_factor_sq(ffx[X], ffy[Y], ffs));
+    // one thread per first-zone point (u, v) and group of four planes: the
+    // first-zone values are read once and written to every zone image
+    const int u = blockIdx.x * kThreads + threadIdx.x;
+    const int v = blockIdx.y;
+    const int w0 = blockIdx.z * 4;
+    if (u >= nkx) return;
+    T vals[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = lags[min(w0 + i, nw - 1)];
+        const bool in = m >= 1 && m < neps;
+        const T x = im1[((size_t)(in ? m : 1) * nky + v) * nkx + u];
+        vals[i] = in ? x : (T)0;
     }
-    out[((size_t)w * out_ny + Y) * out_nx + X] = val;
+    const size_t plane = (size_t)out_nx * out_ny;
+    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
+    for (int zi = 0; zi < zy; ++zi) {
+        const int Y = zi * nky + yv;
+        for (int zj = 0; zj < zx; ++zj) {
+            const int X = zj * nkx + xu;
+            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Y], ffs) : 1.0;
+            const size_t o0 = (size_t)Y * out_nx + X;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (w0 + i < nw) out[(size_t)(w0 + i) * plane + o0] = ff ? (T)((double)vals[i] * m2) : vals[i];
+        }
+    }
 }
 
-// Kramers-Kronig: re1[w][q] = sum_j kkw[w][j] im1[j][q], FP64 accumulation.
-// One block: QT consecutive q with every lag staged in LDS.
+// Kramers-Kronig: re1[w][q] = sum_j kkw[j][w] im1[j][q], FP64 accumulation.
+// One block: QT consecutive q with every lag staged in LDS; each thread sums
+// kKkW output lags at once (independent accumulators sharing each staged
+// value; the zero weights of the other parity are multiplied too), the
+// weights of one j read as one contiguous, wave-uniform block.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int nk, int neps, int nw,
-                                                const int *__restrict__ lags, const double *__restrict__ kkw,
-                                                T *__restrict__ re1, int logQT)
+                                                const double *__restrict__ kkw, T *__restrict__ re1, int logQT)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
@@ -1421,47 +1439,142 @@ __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int 
     }
     __syncthreads();
     const int c = tid & (QT - 1);
-    const int grp = tid >> logQT, ngrp = kThreads >> logQT;
-    for (int w = grp; w < nw; w += ngrp) {
-        const double *kw = kkw + (size_t)w * neps;
-        const int js = (lags[w] & 1) ? 2 : 1;
-        double acc = 0.0;
-        for (int j = js; j < neps; j += 2) acc += kw[j] * (double)tile[(j << logQT) + c];
-        re1[(size_t)w * nk + q0 + c] = (T)acc;
+    // groups of QT lanes take groups of kKkW output lags; with QT >= 64 the
+    // group index is wave-uniform and the weights come through scalar loads
+    const int grp = logQT >= 6 ? __builtin_amdgcn_readfirstlane(tid >> logQT) : tid >> logQT;
+    const int ngrp = kThreads >> logQT;
+    const int nwp = (nw + kKkW - 1) / kKkW * kKkW;
+    for (int w0 = grp * kKkW; w0 < nw; w0 += ngrp * kKkW) {
+        double acc[kKkW];
+#pragma unroll
+        for (int i = 0; i < kKkW; ++i) acc[i] = 0.0;
+        for (int j = 1; j < neps; ++j) {
+            const double x = (double)tile[(j << logQT) + c];
+            const double *kr = kkw + (size_t)j * nwp + w0;
+#pragma unroll
+            for (int i = 0; i < kKkW; ++i) acc[i] += kr[i] * x;
+        }
+#pragma unroll
+        for (int i = 0; i < kKkW; ++i)
+            if (w0 + i < nw) re1[(size_t)(w0 + i) * nk + q0 + c] = (T)acc[i];
     }
 }
 
 // RPA epilogue on the extended map: chi = |M|^2 (Re + i Im),
-// chi_RPA = chi / (1 - U chi), FP64 arithmetic, rounded once to T.
+// chi_RPA = chi / (1 - V chi) with a contact (vkind 0) or Coulomb (vkind 1)
+// interaction, FP64 arithmetic, rounded once to T.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, const T *__restrict__ re1, int nkx,
-                                                 int nky, int neps, const int *__restrict__ lags, int zx, int zy,
-                                                 int ff, double ffs, const double2 *__restrict__ ffx,
-                                                 const double2 *__restrict__ ffy, double U, T *__restrict__ re_out,
-                                                 T *__restrict__ imr, T *__restrict__ rer, int out_nx, int out_ny)
+                                                 int nky, int neps, const int *__restrict__ lags, int nw, int zx,
+                                                 int zy, int ff, double ffs, const double2 *__restrict__ ffx,
+                                                 const double2 *__restrict__ ffy, int vkind, double V,
+                                                 T *__restrict__ re_out, T *__restrict__ imr, T *__restrict__ rer,
+                                                 int out_nx, int out_ny)
 {
-    const int X = blockIdx.x * kThreads + threadIdx.x;
-    const int Y = blockIdx.y;
-    const int w = blockIdx.z;
-    if (X >= out_nx) return;
-    const int m = lags[w];
-    const int u = (X - (zx * nkx) / 2) & (nkx - 1);
-    const int v = (Y - (zy * nky) / 2) & (nky - 1);
-    const size_t q = (size_t)v * nkx + u;
-    const size_t nk = (size_t)nkx * nky;
-    double im = (m >= 1 && m < neps) ? (double)im1[(size_t)m * nk + q] : 0.0;
-    double re = (double)re1[(size_t)w * nk + q];
-    if (ff) {
-        const double m2 = form_factor_sq(ffx[X], ffy[Y], ffs);
-        im = (double)(T)(im * m2);
-        re = (double)(T)(re * m2);
+    // one thread per first-zone point (u, v) and group of four planes: the
+    // first-zone Im / Re are read once and every zone image is written
+    const int u = blockIdx.x * kThreads + threadIdx.x;
+    const int v = blockIdx.y;
+    const int w0 = blockIdx.z * 4;
+    if (u >= nkx) return;
+    const size_t q = (size_t)v * nkx + u, nk = (size_t)nkx * nky;
+    double imv[4], rev[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int w = min(w0 + i, nw - 1);
+        const int m = lags[w];
+        const bool in = m >= 1 && m < neps;
+        const T x = im1[(size_t)(in ? m : 1) * nk + q];
+        const T y = re1[(size_t)w * nk + q];
+        imv[i] = in ? (double)x : 0.0;
+        rev[i] = (double)y;
     }
-    const double a = 1.0 - U * re, b = U * im;
-    const double D = a * a + b * b;
-    const size_t o = ((size_t)w * out_ny + Y) * out_nx + X;
-    if (re_out) re_out[o] = (T)re;
-    if (imr) imr[o] = (T)(im / D);
-    if (rer) rer[o] = (T)((re * a - U * im * im) / D);
+    const size_t plane = (size_t)out_nx * out_ny;
+    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
+    for (int zi = 0; zi < zy; ++zi) {
+        const int Y = zi * nky + yv;
+        for (int zj = 0; zj < zx; ++zj) {
+            const int X = zj * nkx + xu;
+            // interaction: contact U = V, or Coulomb V / |Q|^2 with
+            // Q = 2 pi (h, l) in units of 1/a (h, l the reciprocal-lattice
+            // coordinates of X, Y); at Q = 0 chi_RPA -> -1/V -> 0
+            double U = V;
+            bool q0 = false;
+            if (vkind == 1) {
+                const double h = (double)(X - (zx * nkx) / 2) / nkx, l = (double)(Y - (zy * nky) / 2) / nky;
+                const double q2 = (2.0 * kPi) * (2.0 * kPi) * (h * h + l * l);
+                q0 = q2 == 0.0;
+                U = q0 ? 0.0 : V / q2;
+            }
+            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Y], ffs) : 1.0;
+            const size_t o0 = (size_t)Y * out_nx + X;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (w0 + i >= nw) break;
+                double im = imv[i], re = rev[i];
+                if (ff) {
+                    im = (double)(T)(im * m2);
+                    re = (double)(T)(re * m2);
+                }
+                const double a = 1.0 - U * re, b = U * im;
+                const double inv = 1.0 / (a * a + b * b);
+                const size_t o = (size_t)(w0 + i) * plane + o0;
+                if (re_out) re_out[o] = (T)re;
+                if (imr) imr[o] = q0 ? (T)0 : (T)(im * inv);
+                if (rer) rer[o] = q0 ? (T)0 : (T)((re * a - U * im * im) * inv);
+            }
+        }
+    }
+}
+
+// Dynamical structure factor from Im chi (Eq. (1)): S = -(1/pi) Im chi /
+// (1 - exp(-omega / kT)) with omega = m d of each output plane; kT = 0 is the
+// zero-temperature limit (factor 1 for omega > 0); omega = 0 gives 0.  VEC
+// consecutive elements per thread (16-byte accesses) when both arrays allow.
+template <typename T, int VEC>
+__global__ void __launch_bounds__(kThreads) k_sqw(const T *__restrict__ im, T *__restrict__ s,
+                                                 const int *__restrict__ lags, double deps, double kT, size_t plane)
+{
+    const int w = blockIdx.y;
+    const double om = lags[w] * deps;
+    double f;
+    if (kT > 0.0)
+        f = om == 0.0 ? 0.0 : 1.0 / (-expm1(-om / kT));
+    else
+        f = om > 0.0 ? 1.0 : 0.0;
+    const double c = -(1.0 / kPi) * f;
+    const size_t base = (size_t)w * plane;
+    const size_t nv = plane / VEC;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv; i += (size_t)gridDim.x * kThreads) {
+        if constexpr (VEC > 1) {
+            Vec16<T> v = __builtin_bit_cast(Vec16<T>, *reinterpret_cast<const lh_u4 *>(im + base + i * VEC));
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) v.v[k] = (T)(c * (double)v.v[k]);
+            *reinterpret_cast<lh_u4 *>(s + base + i * VEC) = __builtin_bit_cast(lh_u4, v);
+        } else {
+            s[base + i] = (T)(c * (double)im[base + i]);
+        }
+    }
+}
+
+// Peak search over the output planes: for every (X, Y) the plane index with
+// the largest -Im (the first one on ties), compared in the array's precision.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_peak(const T *__restrict__ im, int32_t *__restrict__ idx, size_t plane,
+                                                  int nw)
+{
+    const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= plane) return;
+    T best = im[p];
+    int32_t bw = 0;
+    for (int w = 1; w < nw; ++w) {
+        const T x = im[(size_t)w * plane + p];
+        if (x < best) {
+            best = x;
+            bw = w;
+        }
+    }
+    idx[p] = bw;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1508,9 +1621,10 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
                            pl.ff_s);
     }
     if (pl.p.want_rpa) {
-        const long n = (long)pl.p.nomega * g.neps;
+        const int nwp = (pl.p.nomega + kKkW - 1) / kKkW * kKkW;
+        const long n = (long)nwp * g.neps;
         hipLaunchKernelGGL(k_kkw, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, pl.kkw, pl.d_lag, pl.p.nomega,
-                           g.neps);
+                           nwp, g.neps);
     }
     return hipGetLastError();
 }
@@ -1577,7 +1691,7 @@ template <typename T, int LOGN, bool INV>
 static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
 {
     const Geo &g = pl.g;
-    using F = RegFFT<T, LOGN, INV>;
+    using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems)>;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
     hipLaunchKernelGGL((k_ecol<T, LOGN, INV>), dim3(cdiv(g.NTe, TPB), nslices), dim3(F::G * TPB * C),
@@ -1658,8 +1772,8 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
                 LH_SWITCH_LOG(g.logNx, LH_E5)
 #undef LH_E5
             }
-            hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(pl.out_nx, kThreads), pl.out_ny, pl.p.nomega), dim3(kThreads),
-                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.zx, pl.zy, ff, pl.ff_s,
+            hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads),
+                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s,
                                pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
         } else {
 #define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
@@ -1699,8 +1813,8 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
             LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
         }
-        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(pl.out_nx, kThreads), pl.out_ny, pl.p.nomega), dim3(kThreads), 0,
-                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
+        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
+                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
                            pl.ffy, out, pl.out_nx, pl.out_ny);
     } else {
 #define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
@@ -1814,7 +1928,7 @@ hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev
 }
 
 template <typename T>
-static hipError_t rpa_t(const Plan &pl, double U, T *re, T *imr, T *rer, hipStream_t st)
+static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *rer, hipStream_t st)
 {
     const Geo &g = pl.g;
     const int nk = g.nkx * g.nky;
@@ -1822,18 +1936,50 @@ static hipError_t rpa_t(const Plan &pl, double U, T *re, T *imr, T *rer, hipStre
     while (logQT > 0 && ((size_t)g.neps << logQT) * sizeof(T) > 65536) --logQT;
     while ((1 << logQT) > nk) --logQT;
     hipLaunchKernelGGL(k_kk<T>, dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T), st,
-                       (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.d_lag, pl.kkw, (T *)pl.re1, logQT);
+                       (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
-    hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(pl.out_nx, kThreads), pl.out_ny, pl.p.nomega), dim3(kThreads), 0, st,
-                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.zx, pl.zy, ff,
-                       pl.ff_s, pl.ffx, pl.ffy, U, re, imr, rer, pl.out_nx, pl.out_ny);
+    hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
+                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff,
+                       pl.ff_s, pl.ffx, pl.ffy, vkind, U, re, imr, rer, pl.out_nx, pl.out_ny);
     return hipGetLastError();
 }
 
-hipError_t launch_rpa(const Plan &pl, double U, void *re, void *imr, void *rer, hipStream_t st)
+hipError_t launch_rpa(const Plan &pl, int vkind, double U, void *re, void *imr, void *rer, hipStream_t st)
 {
-    return pl.g.fp64 ? rpa_t<double>(pl, U, (double *)re, (double *)imr, (double *)rer, st)
-                     : rpa_t<float>(pl, U, (float *)re, (float *)imr, (float *)rer, st);
+    return pl.g.fp64 ? rpa_t<double>(pl, vkind, U, (double *)re, (double *)imr, (double *)rer, st)
+                     : rpa_t<float>(pl, vkind, U, (float *)re, (float *)imr, (float *)rer, st);
+}
+
+template <typename T>
+static hipError_t sqw_t(const Plan &pl, double kT, const T *im, T *s, hipStream_t st)
+{
+    const size_t plane = (size_t)pl.out_nx * pl.out_ny;
+    constexpr int VEC = 16 / sizeof(T);
+    const bool vec = plane % VEC == 0 && ((reinterpret_cast<uintptr_t>(im) | reinterpret_cast<uintptr_t>(s)) & 15) == 0;
+    const size_t n = vec ? plane / VEC : plane;
+    const dim3 grid((unsigned)std::min<size_t>(cdiv(n, kThreads), 4096), pl.p.nomega);
+    if (vec)
+        hipLaunchKernelGGL((k_sqw<T, VEC>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.deps, kT, plane);
+    else
+        hipLaunchKernelGGL((k_sqw<T, 1>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.deps, kT, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStream_t st)
+{
+    return pl.g.fp64 ? sqw_t<double>(pl, kT, (const double *)im, (double *)s, st)
+                     : sqw_t<float>(pl, kT, (const float *)im, (float *)s, st);
+}
+
+hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st)
+{
+    const size_t plane = (size_t)pl.out_nx * pl.out_ny;
+    const dim3 grid((unsigned)cdiv(plane, kThreads));
+    if (pl.g.fp64)
+        hipLaunchKernelGGL(k_peak<double>, grid, dim3(kThreads), 0, st, (const double *)im, idx, plane, pl.p.nomega);
+    else
+        hipLaunchKernelGGL(k_peak<float>, grid, dim3(kThreads), 0, st, (const float *)im, idx, plane, pl.p.nomega);
+    return hipGetLastError();
 }
 
 }  // namespace lh

@@ -85,7 +85,8 @@ class ServeStats(ctypes.Structure):
 
 
 EXPORTS = [
-    "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa", "lindhard_exec_batch",
+    "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa",
+    "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_peak_index", "lindhard_exec_batch",
     "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
     "lindhard_serve_wait", "lindhard_serve_cancel", "lindhard_serve_stats_get", "lindhard_serve_destroy",
     "lindhard_strerror",
@@ -111,6 +112,9 @@ def lib() -> ctypes.CDLL:
             L.lindhard_exec.argtypes = [_vp, _vp, _vp]
             L.lindhard_exec_timed.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]
             L.lindhard_rpa.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+            L.lindhard_rpa_coulomb.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+            L.lindhard_structure_factor.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp]
+            L.lindhard_peak_index.argtypes = [_vp, _vp, _vp, _vp]
             L.lindhard_exec_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp), _vp]
             L.lindhard_plan_destroy.argtypes = [_vp]
             L.lindhard_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(_vp)]
@@ -193,6 +197,20 @@ def lindhard_rpa(plan: int, U: float, re_ptr: int, imr_ptr: int, rer_ptr: int, s
            "lindhard_rpa")
 
 
+def lindhard_rpa_coulomb(plan: int, v: float, re_ptr: int, imr_ptr: int, rer_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_rpa_coulomb(_vp(plan), float(v), _vp(re_ptr), _vp(imr_ptr), _vp(rer_ptr),
+                                      _vp(stream_ptr)), "lindhard_rpa_coulomb")
+
+
+def lindhard_structure_factor(plan: int, kT: float, im_ptr: int, s_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_structure_factor(_vp(plan), float(kT), _vp(im_ptr), _vp(s_ptr), _vp(stream_ptr)),
+           "lindhard_structure_factor")
+
+
+def lindhard_peak_index(plan: int, im_ptr: int, peak_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_peak_index(_vp(plan), _vp(im_ptr), _vp(peak_ptr), _vp(stream_ptr)), "lindhard_peak_index")
+
+
 def lindhard_exec_batch(plans: Sequence[int], outs: Sequence[int], stream_ptr: int) -> None:
     n = len(plans)
     pa = (_vp * n)(*plans)
@@ -243,6 +261,28 @@ class Plan:
         re, imr, rer = self.empty(), self.empty(), self.empty()
         lindhard_rpa(self.handle, U, re.data_ptr(), imr.data_ptr(), rer.data_ptr(), _stream_ptr(stream))
         return re, imr, rer
+
+    def rpa_coulomb(self, v: float, stream=None):
+        """RPA with V(Q) = v / |Q|^2 (eV a^2); returns (Re chi, Im chi_RPA, Re chi_RPA)."""
+        re, imr, rer = self.empty(), self.empty(), self.empty()
+        lindhard_rpa_coulomb(self.handle, v, re.data_ptr(), imr.data_ptr(), rer.data_ptr(), _stream_ptr(stream))
+        return re, imr, rer
+
+    def structure_factor(self, im: torch.Tensor, kT: float, out: Optional[torch.Tensor] = None, stream=None):
+        """S(q, omega) from an Im chi array of this plan's output layout (Eq. (1))."""
+        assert im.is_cuda and im.dtype == self.dtype and tuple(im.shape) == self.shape and im.is_contiguous()
+        if out is None:
+            out = self.empty()
+        assert out.is_cuda and out.dtype == self.dtype and tuple(out.shape) == self.shape and out.is_contiguous()
+        lindhard_structure_factor(self.handle, kT, im.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+        return out
+
+    def peak_index(self, im: torch.Tensor, stream=None) -> torch.Tensor:
+        """Index into the omega list of the largest -Im at every extended point (int32 [out_ny, out_nx])."""
+        assert im.is_cuda and im.dtype == self.dtype and tuple(im.shape) == self.shape and im.is_contiguous()
+        out = torch.empty(self.shape[1:], dtype=torch.int32, device="cuda")
+        lindhard_peak_index(self.handle, im.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

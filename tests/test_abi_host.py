@@ -83,6 +83,9 @@ def test_null_handles_are_rejected():
     L = LH.lib()
     assert L.lindhard_exec(None, None, None) == -1
     assert L.lindhard_rpa(None, 1.0, None, None, None, None) == -1
+    assert L.lindhard_rpa_coulomb(None, 1.0, None, None, None, None) == -1
+    assert L.lindhard_structure_factor(None, 0.01, None, None, None) == -1
+    assert L.lindhard_peak_index(None, None, None, None) == -1
     assert L.lindhard_plan_destroy(None) == -1
     assert L.lindhard_plan_info(None, None) == -1
     assert L.lindhard_serve_create(None, ctypes.byref(ctypes.c_void_p())) == -1
