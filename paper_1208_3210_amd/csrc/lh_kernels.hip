@@ -1416,10 +1416,12 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
 // kKkW output lags at once (independent accumulators sharing each staged
 // value; the zero weights of the other parity are multiplied too), the
 // weights of one j read as one contiguous, wave-uniform block.
-template <typename T>
+template <typename T, bool WAVEQ>
 __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int nk, int neps, int nw,
                                                 const double *__restrict__ kkw, T *__restrict__ re1, int logQT)
 {
+    // WAVEQ: QT = 64, one wave per group of output lags (wave-uniform weights)
+    if constexpr (WAVEQ) logQT = 6;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
     const int QT = 1 << logQT;
@@ -1441,14 +1443,26 @@ __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int 
     const int c = tid & (QT - 1);
     // groups of QT lanes take groups of kKkW output lags; with QT >= 64 the
     // group index is wave-uniform and the weights come through scalar loads
-    const int grp = logQT >= 6 ? __builtin_amdgcn_readfirstlane(tid >> logQT) : tid >> logQT;
+    const int grp = WAVEQ ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> logQT;
     const int ngrp = kThreads >> logQT;
     const int nwp = (nw + kKkW - 1) / kKkW * kKkW;
     for (int w0 = grp * kKkW; w0 < nw; w0 += ngrp * kKkW) {
         double acc[kKkW];
 #pragma unroll
         for (int i = 0; i < kKkW; ++i) acc[i] = 0.0;
-        for (int j = 1; j < neps; ++j) {
+        // four energies per step so that their weight loads overlap
+        int j = 1;
+        for (; j + 3 < neps; j += 4) {
+            double x[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) x[jj] = (double)tile[((j + jj) << logQT) + c];
+            const double *kr = kkw + (size_t)j * nwp + w0;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int i = 0; i < kKkW; ++i) acc[i] += kr[jj * nwp + i] * x[jj];
+        }
+        for (; j < neps; ++j) {
             const double x = (double)tile[(j << logQT) + c];
             const double *kr = kkw + (size_t)j * nwp + w0;
 #pragma unroll
@@ -1935,8 +1949,12 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
     int logQT = 6;
     while (logQT > 0 && ((size_t)g.neps << logQT) * sizeof(T) > 65536) --logQT;
     while ((1 << logQT) > nk) --logQT;
-    hipLaunchKernelGGL(k_kk<T>, dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T), st,
-                       (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
+    if (logQT == 6)
+        hipLaunchKernelGGL((k_kk<T, true>), dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T),
+                           st, (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
+    else
+        hipLaunchKernelGGL((k_kk<T, false>), dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T),
+                           st, (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
                        (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff,
