@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the served Poisson stream")
     ap.add_argument("--no-epilogues", action="store_true",
                     help="skip the RPA / structure-factor / peak epilogues on the extended-zone workload")
+    ap.add_argument("--epilogues-only", action="store_true",
+                    help="only time the extended-zone epilogues (for profiling them on their own)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -262,6 +264,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
+    if args.epilogues_only:
+        print(json.dumps({"epilogues": bench_epilogues(LH, W, torch)}), flush=True)
         return
     cfg = W.config3(nk=args.nk, neps=args.neps)
     print("bench: planning %dx%d k, %d energies, %d omegas" % (cfg["nkx"], cfg["nky"], cfg["neps"],
