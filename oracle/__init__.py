@@ -299,3 +299,29 @@ def peak_index(im_chi) -> np.ndarray:
     Sec. 4), the first one on ties."""
     im = np.asarray(im_chi)
     return np.argmin(im, axis=0).astype(np.int32)
+
+
+def chi_qmean(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float, lags) -> np.ndarray:
+    """q-average of Im chi_1BZ at each lag (the q-integrated joint density of
+    states of Fig. 2(b), with the sign of Im chi), computed without any
+    q-sum: (1/Nk) sum_q Im chi(q, m) = -d sum_j D_P(j) D_H(j + m), where D is
+    the k-averaged spectral weight of Eq. (5) restricted to the occupied
+    (j < j0) or unoccupied points.  O(Nk Neps + Neps Nomega)."""
+    d = energy_step(neps, emin, emax)
+    e = energy_points(neps, emin, emax)
+    x = np.asarray(xi, dtype=np.float64).ravel()
+    D = np.zeros(neps)
+    for c in range(0, x.size, 1 << 16):
+        xs = x[c:c + (1 << 16), None]
+        D += ((gamma / np.pi) / ((e[None, :] - xs) ** 2 + gamma * gamma)).sum(axis=0)
+    D /= x.size
+    occ = e <= 0.0
+    DP, DH = np.where(occ, D, 0.0), np.where(~occ, D, 0.0)
+    out = []
+    for m in np.asarray(lags).ravel():
+        m = int(m)
+        if m < 1 or m >= neps:
+            out.append(0.0)
+        else:
+            out.append(-d * float(np.dot(DP[:neps - m], DH[m:])))
+    return np.array(out)

@@ -89,6 +89,17 @@ def test_q_sum_identity(nkx, nky, neps, emin, emax):
         assert abs(got - want) <= 1e-14 * max(abs(want), 1e-3), m
 
 
+def test_chi_qmean_matches_the_q_average_of_the_full_grid():
+    g = 0.07
+    xi = _tb_case(16, 8, 32, -1.0, 1.2, g)
+    ms = np.array([0, 1, 2, 5, 17, 31, 32, 40])
+    full = oracle.chi_full(xi, 32, -1.0, 1.2, g, ms)
+    got = oracle.chi_qmean(xi, 32, -1.0, 1.2, g, ms)
+    want = full.mean(axis=(1, 2))
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-17)
+    assert got[0] == 0 and got[-2] == 0 and got[-1] == 0 and np.all(got[1:-2] < 0)
+
+
 def test_energy_sum_identity():
     """Summing over every lag pairs each occupied point with each unoccupied one:
     sum_m Im chi(q, m) = -(d/Nk) sum_k nP(k) nH(k + q)."""
