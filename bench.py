@@ -175,14 +175,16 @@ def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
 def bench_epilogues(LH, W, torch, reps=3):
     """The RPA-side epilogues on the extended-zone workload (512^2 k, 256
     energies, 5x5 zones, orbital form factor, 128 omegas, FP32): Kramers-
-    Kronig + contact RPA, Coulomb RPA, S(q, omega) and the peak search, each
-    timed with events on the launch stream against its algorithmic HBM bytes."""
+    Kronig + contact RPA, Coulomb RPA, S(q, omega), the peak search and the
+    q-average, each timed with events on the launch stream against its
+    algorithmic HBM bytes."""
     cfg = W.config2()
     plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
     im = plan.exec()
     re, imr, rer = plan.empty(), plan.empty(), plan.empty()
     s_out = plan.empty()
     pk = torch.empty(plan.shape[1:], dtype=torch.int32, device="cuda")
+    qa = torch.empty(plan.shape[0], dtype=torch.float64, device="cuda")
     h = plan.handle
     sp = lambda: LH._stream_ptr(None)  # noqa: E731
     n_out = im.numel() * 4
@@ -196,6 +198,7 @@ def bench_epilogues(LH, W, torch, reps=3):
         "structure_factor": (lambda: LH.lindhard_structure_factor(h, 0.025, imr.data_ptr(), s_out.data_ptr(), sp()),
                              2 * n_out),
         "peak_index": (lambda: LH.lindhard_peak_index(h, imr.data_ptr(), pk.data_ptr(), sp()), n_out + pk.numel() * 4),
+        "q_average": (lambda: LH.lindhard_q_average(h, im.data_ptr(), qa.data_ptr(), sp()), n_out),
     }
     out = {"workload": "512^2 k, 256 energies, 5x5 zones, d(x2-y2) form factor, 128 omegas, FP32",
            "points": int(im.numel())}

@@ -154,6 +154,15 @@ lindhard_status lindhard_rpa_coulomb(lindhard_plan_t plan, double v, void *re_ch
 lindhard_status lindhard_structure_factor(lindhard_plan_t plan, double kT, const void *im, void *s_out,
                                           void *stream);
 
+/* q-average of every output plane: out[w] = mean over all (X, Y) of
+ * im[w][Y][X], accumulated in FP64 in a fixed order (deterministic), into
+ * `out` (device, nomega doubles).  On a plan with one zone and no form factor
+ * and the Im chi of lindhard_exec this is the q-integrated joint density of
+ * states of Fig. 2(b) (with the sign of Im chi).  Uses the plan's scratch
+ * memory: one call at a time per plan.  Asynchronous on `stream`.
+ * Errors: EINVAL (NULL), EDEVICE. */
+lindhard_status lindhard_q_average(lindhard_plan_t plan, const void *im, double *out, void *stream);
+
 /* Peak search (plasmon modes as the peaks of -Im chi_RPA, Sec. 4): for every
  * extended point (X, Y), the index w in [0, nomega) of the largest -im[w][Y][X]
  * (the first on ties, compared in the plan's precision) into peak (device,

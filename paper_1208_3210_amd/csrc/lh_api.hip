@@ -298,6 +298,12 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     return LINDHARD_OK;
 }
 
+// Plan scratch: the partial sums of the mu solve, or those of the q-average.
+static size_t scratch_bytes(const Plan &pl)
+{
+    return std::max<size_t>(2 * kOccBlocks + 2, (size_t)pl.p.nomega * kQavgBlocks) * sizeof(double);
+}
+
 size_t plan_footprint(const Plan &pl)
 {
     const Geo &g = pl.g;
@@ -310,7 +316,7 @@ size_t plan_footprint(const Plan &pl)
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += 2 * al(pl.p.nomega * sizeof(int));
     b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
-    b += al(2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
+    b += al(scratch_bytes(pl));
     if (pl.p.want_rpa) {
         b += al((size_t)g.neps * nk * es);
         b += al((size_t)pl.p.nomega * nk * es);
@@ -679,7 +685,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     LH_ALLOC(pl.d_slot, pl.p.nomega * sizeof(int));
     LH_ALLOC(pl.d_lag, pl.p.nomega * sizeof(int));
     LH_ALLOC(pl.spec, g.even ? (size_t)g.nslots * g.slice_e * es : (size_t)g.nslots * g.slice_elems * cs);
-    LH_ALLOC(pl.scratch, 2 * kOccBlocks * sizeof(double) + 2 * sizeof(double));
+    LH_ALLOC(pl.scratch, scratch_bytes(pl));
     if (pl.p.want_rpa) {
         LH_ALLOC(pl.im1, (size_t)g.neps * nk * es);
         LH_ALLOC(pl.re1, (size_t)pl.p.nomega * nk * es);
@@ -868,6 +874,18 @@ lindhard_status lindhard_structure_factor(lindhard_plan_t plan, double kT, const
     if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
     if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
     hipError_t e = launch_sqw(plan->pl, kT, im, s_out, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+    if (dev != plan->pl.device) (void)hipSetDevice(dev);
+    return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_q_average(lindhard_plan_t plan, const void *im, double *out, void *stream)
+{
+    if (!plan || !im || !out) return LINDHARD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != plan->pl.device && hipSetDevice(plan->pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    hipError_t e = launch_qavg(plan->pl, im, out, (hipStream_t)stream);
     if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
     if (dev != plan->pl.device) (void)hipSetDevice(dev);
     return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;

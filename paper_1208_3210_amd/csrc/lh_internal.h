@@ -65,6 +65,8 @@ struct Geo {
 // Elements per thread of the register FFTs in the even builder pass (the
 // builder also keeps the band rows of its lines in registers).
 constexpr int kE1Elems = 8;
+// Partial sums per output plane of the q-average (plan scratch holds them).
+constexpr int kQavgBlocks = 32;
 // ... and in the even column passes (sixteen measured faster than eight there).
 constexpr int kEcolElems = 16;
 
@@ -114,6 +116,7 @@ hipError_t launch_exec(const Plan &pl, void *out, hipStream_t st, hipEvent_t *ev
 hipError_t launch_rpa(const Plan &pl, int vkind, double U, void *re, void *imr, void *rer, hipStream_t st);
 hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStream_t st);
 hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st);
+hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t st);
 hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
 
 // Setup kernels.

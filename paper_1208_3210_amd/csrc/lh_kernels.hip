@@ -1571,6 +1571,38 @@ __global__ void __launch_bounds__(kThreads) k_sqw(const T *__restrict__ im, T *_
     }
 }
 
+// Average of every output plane over its (X, Y) points in FP64, in a fixed
+// order (no atomics): kQavgBlocks partial sums per plane, then one thread
+// per plane adds them up.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_qavg_part(const T *__restrict__ im, size_t plane,
+                                                       double *__restrict__ part)
+{
+    __shared__ double red[kThreads];
+    const int w = blockIdx.y;
+    const T *src = im + (size_t)w * plane;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < plane; i += (size_t)kQavgBlocks * kThreads)
+        acc += (double)src[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s2 = kThreads / 2; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)w * kQavgBlocks + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_qavg_final(const double *__restrict__ part, int nw, double inv,
+                                                        double *__restrict__ out)
+{
+    const int w = blockIdx.x * kThreads + threadIdx.x;
+    if (w >= nw) return;
+    double s2 = 0.0;
+    for (int b = 0; b < kQavgBlocks; ++b) s2 += part[(size_t)w * kQavgBlocks + b];
+    out[w] = s2 * inv;
+}
+
 // Peak search over the output planes: for every (X, Y) the plane index with
 // the largest -Im (the first one on ties), compared in the array's precision.
 template <typename T>
@@ -1987,6 +2019,19 @@ hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStr
 {
     return pl.g.fp64 ? sqw_t<double>(pl, kT, (const double *)im, (double *)s, st)
                      : sqw_t<float>(pl, kT, (const float *)im, (float *)s, st);
+}
+
+hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t st)
+{
+    const size_t plane = (size_t)pl.out_nx * pl.out_ny;
+    const dim3 grid(kQavgBlocks, pl.p.nomega);
+    if (pl.g.fp64)
+        hipLaunchKernelGGL(k_qavg_part<double>, grid, dim3(kThreads), 0, st, (const double *)im, plane, pl.scratch);
+    else
+        hipLaunchKernelGGL(k_qavg_part<float>, grid, dim3(kThreads), 0, st, (const float *)im, plane, pl.scratch);
+    hipLaunchKernelGGL(k_qavg_final, dim3(cdiv(pl.p.nomega, kThreads)), dim3(kThreads), 0, st, pl.scratch,
+                       pl.p.nomega, 1.0 / (double)plane, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st)

@@ -86,7 +86,8 @@ class ServeStats(ctypes.Structure):
 
 EXPORTS = [
     "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa",
-    "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_peak_index", "lindhard_exec_batch",
+    "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_q_average", "lindhard_peak_index",
+    "lindhard_exec_batch",
     "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
     "lindhard_serve_wait", "lindhard_serve_cancel", "lindhard_serve_stats_get", "lindhard_serve_destroy",
     "lindhard_strerror",
@@ -115,6 +116,7 @@ def lib() -> ctypes.CDLL:
             L.lindhard_rpa_coulomb.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
             L.lindhard_structure_factor.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp]
             L.lindhard_peak_index.argtypes = [_vp, _vp, _vp, _vp]
+            L.lindhard_q_average.argtypes = [_vp, _vp, _vp, _vp]
             L.lindhard_exec_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp), _vp]
             L.lindhard_plan_destroy.argtypes = [_vp]
             L.lindhard_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(_vp)]
@@ -207,6 +209,10 @@ def lindhard_structure_factor(plan: int, kT: float, im_ptr: int, s_ptr: int, str
            "lindhard_structure_factor")
 
 
+def lindhard_q_average(plan: int, im_ptr: int, out_ptr: int, stream_ptr: int) -> None:
+    _check(lib().lindhard_q_average(_vp(plan), _vp(im_ptr), _vp(out_ptr), _vp(stream_ptr)), "lindhard_q_average")
+
+
 def lindhard_peak_index(plan: int, im_ptr: int, peak_ptr: int, stream_ptr: int) -> None:
     _check(lib().lindhard_peak_index(_vp(plan), _vp(im_ptr), _vp(peak_ptr), _vp(stream_ptr)), "lindhard_peak_index")
 
@@ -275,6 +281,13 @@ class Plan:
             out = self.empty()
         assert out.is_cuda and out.dtype == self.dtype and tuple(out.shape) == self.shape and out.is_contiguous()
         lindhard_structure_factor(self.handle, kT, im.data_ptr(), out.data_ptr(), _stream_ptr(stream))
+        return out
+
+    def q_average(self, im: torch.Tensor, stream=None) -> torch.Tensor:
+        """Mean over the output q grid of every omega plane (FP64, [nomega])."""
+        assert im.is_cuda and im.dtype == self.dtype and tuple(im.shape) == self.shape and im.is_contiguous()
+        out = torch.empty(self.shape[0], dtype=torch.float64, device="cuda")
+        lindhard_q_average(self.handle, im.data_ptr(), out.data_ptr(), _stream_ptr(stream))
         return out
 
     def peak_index(self, im: torch.Tensor, stream=None) -> torch.Tensor:

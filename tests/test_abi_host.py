@@ -86,6 +86,7 @@ def test_null_handles_are_rejected():
     assert L.lindhard_rpa_coulomb(None, 1.0, None, None, None, None) == -1
     assert L.lindhard_structure_factor(None, 0.01, None, None, None) == -1
     assert L.lindhard_peak_index(None, None, None, None) == -1
+    assert L.lindhard_q_average(None, None, None, None) == -1
     assert L.lindhard_plan_destroy(None) == -1
     assert L.lindhard_plan_info(None, None) == -1
     assert L.lindhard_serve_create(None, ctypes.byref(ctypes.c_void_p())) == -1

@@ -183,3 +183,49 @@ def test_config2_coulomb_sampled(prec):
     print("config2 coulomb errs=%s" % ["%.2e" % e for e in errs])
     assert max(errs) <= TOL[prec]
     plan.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_q_average_is_the_q_integrated_jdos(prec):
+    """The 32x32 workload: the q-average of every omega plane against the
+    oracle's q-integrated joint density of states (no q-sum there), a plain
+    mean of the same array, and bitwise repeatability."""
+    cfg = W.config1()
+    eps = oracle.band_tb(cfg["t"], cfg["tp"], cfg["tpp"], cfg["nkx"], cfg["nky"])
+    mu = oracle.mu_solve(eps, cfg["gamma"], cfg["filling"])
+    ref = oracle.chi_qmean(eps - mu, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], lags_of(cfg))
+    plan = LH.Plan(precision=prec, **cfg)
+    im = plan.exec()
+    a = plan.q_average(im)
+    b = plan.q_average(im)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    err = normwise(a.cpu().numpy(), ref)
+    own = normwise(a.cpu().numpy(), im.double().mean(dim=(1, 2)).cpu().numpy())
+    print("q-average prec=%d err %.2e (own mean %.2e)" % (prec, err, own))
+    assert err <= TOL[prec] and own <= 1e-13
+    plan.close()
+
+
+def test_q_average_extended_zones_and_full_size():
+    # extended zones with the form factor: the mean of the array itself
+    cfg = small_cfg()
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    im = plan.exec()
+    qa = plan.q_average(im)
+    torch.cuda.synchronize()
+    assert normwise(qa.cpu().numpy(), im.double().mean(dim=(1, 2)).cpu().numpy()) <= 1e-13
+    plan.close()
+    # the 2048^2 x 512 instance: every lag against the oracle's JDOS
+    cfg = W.config3()
+    eps = oracle.band_tb(cfg["t"], cfg["tp"], cfg["tpp"], cfg["nkx"], cfg["nky"])
+    mu = oracle.mu_solve(eps, cfg["gamma"], cfg["filling"])
+    ref = oracle.chi_qmean(eps - mu, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], lags_of(cfg))
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    im = plan.exec()
+    qa = plan.q_average(im)
+    torch.cuda.synchronize()
+    err = normwise(qa.cpu().numpy(), ref)
+    print("q-average 2048^2 err %.2e" % err)
+    assert err <= 1e-5
+    plan.close()
