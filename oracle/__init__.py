@@ -57,20 +57,22 @@ def _load():
             lib = ctypes.CDLL(build())
             lib.oracle_band_tb.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int, ctypes.c_int, _dp]
             lib.oracle_band_tb.restype = None
+            lib.oracle_band_tb_z.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+            lib.oracle_band_tb_z.restype = None
             lib.oracle_filling.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double]
             lib.oracle_filling.restype = ctypes.c_double
             lib.oracle_mu.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_double]
             lib.oracle_mu.restype = ctypes.c_double
             lib.oracle_j0.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
             lib.oracle_j0.restype = ctypes.c_int
-            lib.oracle_chi_grid.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                            ctypes.c_int, _ip, _ip, ctypes.c_int, _ip, _dp]
-            lib.oracle_chi_grid.restype = ctypes.c_int
-            lib.oracle_chi_pairs.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                             ctypes.c_long, _ip, _ip, _ip, _dp]
-            lib.oracle_chi_pairs.restype = ctypes.c_int
+            lib.oracle_chi_grid_w.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, _ip, _ip, ctypes.c_int, _ip, _dp]
+            lib.oracle_chi_grid_w.restype = ctypes.c_int
+            lib.oracle_chi_pairs_w.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_long, _ip, _ip, _ip, _dp]
+            lib.oracle_chi_pairs_w.restype = ctypes.c_int
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
@@ -92,10 +94,15 @@ def num_threads() -> int:
 # --------------------------------------------------------------------------
 # Band and chemical potential (Sec. 3: single Cu-O band, rigid-band doping)
 # --------------------------------------------------------------------------
-def band_tb(t: float, tp: float, tpp: float, nkx: int, nky: int) -> np.ndarray:
-    """eps(k) of the square-lattice t-t'-t'' band on the periodic k-grid, [iy][ix]."""
+def band_tb(t: float, tp: float, tpp: float, nkx: int, nky: int, kzones: int = 1) -> np.ndarray:
+    """eps(k) of the square-lattice t-t'-t'' band on the periodic k-grid, [iy][ix];
+    with kzones > 1 the grid spans kzones Brillouin zones per axis (extended
+    momentum p = 2 pi kzones (ix/nkx, iy/nky), Eq. (9))."""
     out = np.empty((nky, nkx), dtype=np.float64)
-    _load().oracle_band_tb(float(t), float(tp), float(tpp), int(nkx), int(nky), _d(out))
+    if kzones == 1:
+        _load().oracle_band_tb(float(t), float(tp), float(tpp), int(nkx), int(nky), _d(out))
+    else:
+        _load().oracle_band_tb_z(float(t), float(tp), float(tpp), int(nkx), int(nky), int(kzones), _d(out))
     return out
 
 
@@ -131,45 +138,57 @@ def j0(neps: int, emin: float, emax: float) -> int:
 # --------------------------------------------------------------------------
 # Bare susceptibility, Eqs. (2), (5), (9), (A3)
 # --------------------------------------------------------------------------
+def _rho(rho, shape):
+    if rho is None:
+        return None
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    assert r.shape == shape
+    return r
+
+
 def chi_grid(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float,
-             qx, qy, ms) -> np.ndarray:
-    """Im chi_1BZ for every (q in the q-list) x (m in the lag list): shape (nq, nm)."""
+             qx, qy, ms, rho=None) -> np.ndarray:
+    """Im chi_1BZ for every (q in the q-list) x (m in the lag list): shape (nq, nm).
+    rho: optional momentum-density weights [iy][ix] on the spectral function
+    (A(p, e) = rho(p) A_band(p, e), Eq. (4))."""
     x = np.ascontiguousarray(xi, dtype=np.float64)
+    r = _rho(rho, x.shape)
     nky, nkx = x.shape
     qx = np.ascontiguousarray(qx, dtype=np.int32)
     qy = np.ascontiguousarray(qy, dtype=np.int32)
     ms = np.ascontiguousarray(ms, dtype=np.int32)
     assert qx.shape == qy.shape
     out = np.empty((qx.size, ms.size), dtype=np.float64)
-    rc = _load().oracle_chi_grid(_d(x), nkx, nky, int(neps), float(emin), float(emax),
-                                 float(gamma), qx.size, _i(qx), _i(qy), ms.size, _i(ms), _d(out))
+    rc = _load().oracle_chi_grid_w(_d(x), _d(r) if r is not None else None, nkx, nky, int(neps), float(emin),
+                                   float(emax), float(gamma), qx.size, _i(qx), _i(qy), ms.size, _i(ms), _d(out))
     if rc != 0:
         raise RuntimeError("oracle_chi_grid failed: %d" % rc)
     return out
 
 
 def chi_pairs(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float,
-              qx, qy, ms) -> np.ndarray:
-    """Im chi_1BZ at explicit samples (qx[i], qy[i], ms[i])."""
+              qx, qy, ms, rho=None) -> np.ndarray:
+    """Im chi_1BZ at explicit samples (qx[i], qy[i], ms[i]); rho as in chi_grid."""
     x = np.ascontiguousarray(xi, dtype=np.float64)
+    r = _rho(rho, x.shape)
     nky, nkx = x.shape
     qx = np.ascontiguousarray(qx, dtype=np.int32)
     qy = np.ascontiguousarray(qy, dtype=np.int32)
     ms = np.ascontiguousarray(ms, dtype=np.int32)
     assert qx.shape == qy.shape == ms.shape
     out = np.empty(qx.size, dtype=np.float64)
-    rc = _load().oracle_chi_pairs(_d(x), nkx, nky, int(neps), float(emin), float(emax),
-                                  float(gamma), qx.size, _i(qx), _i(qy), _i(ms), _d(out))
+    rc = _load().oracle_chi_pairs_w(_d(x), _d(r) if r is not None else None, nkx, nky, int(neps), float(emin),
+                                    float(emax), float(gamma), qx.size, _i(qx), _i(qy), _i(ms), _d(out))
     if rc != 0:
         raise RuntimeError("oracle_chi_pairs failed: %d" % rc)
     return out
 
 
-def chi_full(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float, ms) -> np.ndarray:
+def chi_full(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float, ms, rho=None) -> np.ndarray:
     """Im chi_1BZ on the whole q-grid, natural q order: shape (nm, nky, nkx)."""
     nky, nkx = xi.shape
     qy, qx = np.meshgrid(np.arange(nky), np.arange(nkx), indexing="ij")
-    g = chi_grid(xi, neps, emin, emax, gamma, qx.ravel(), qy.ravel(), ms)
+    g = chi_grid(xi, neps, emin, emax, gamma, qx.ravel(), qy.ravel(), ms, rho=rho)
     return np.ascontiguousarray(g.T.reshape(len(ms), nky, nkx))
 
 
@@ -301,19 +320,24 @@ def peak_index(im_chi) -> np.ndarray:
     return np.argmin(im, axis=0).astype(np.int32)
 
 
-def chi_qmean(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float, lags) -> np.ndarray:
+def chi_qmean(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float, lags, rho=None) -> np.ndarray:
     """q-average of Im chi_1BZ at each lag (the q-integrated joint density of
     states of Fig. 2(b), with the sign of Im chi), computed without any
     q-sum: (1/Nk) sum_q Im chi(q, m) = -d sum_j D_P(j) D_H(j + m), where D is
-    the k-averaged spectral weight of Eq. (5) restricted to the occupied
-    (j < j0) or unoccupied points.  O(Nk Neps + Neps Nomega)."""
+    the k-averaged spectral weight of Eq. (5) (times rho(k) when momentum
+    density weights are given) restricted to the occupied (j < j0) or
+    unoccupied points.  O(Nk Neps + Neps Nomega)."""
     d = energy_step(neps, emin, emax)
     e = energy_points(neps, emin, emax)
     x = np.asarray(xi, dtype=np.float64).ravel()
+    wt = None if rho is None else np.asarray(rho, dtype=np.float64).ravel()
     D = np.zeros(neps)
     for c in range(0, x.size, 1 << 16):
         xs = x[c:c + (1 << 16), None]
-        D += ((gamma / np.pi) / ((e[None, :] - xs) ** 2 + gamma * gamma)).sum(axis=0)
+        a = (gamma / np.pi) / ((e[None, :] - xs) ** 2 + gamma * gamma)
+        if wt is not None:
+            a = a * wt[c:c + (1 << 16), None]
+        D += a.sum(axis=0)
     D /= x.size
     occ = e <= 0.0
     DP, DH = np.where(occ, D, 0.0), np.where(~occ, D, 0.0)

@@ -55,15 +55,24 @@ static inline void nsum_add(nsum *a, double x)
 
 static inline double nsum_get(const nsum *a) { return a->s + a->c; }
 
+void oracle_band_tb_z(double t, double tp, double tpp, int nkx, int nky, int kz, double *eps);
+
 /* Tight-binding band of the square lattice (single Cu-O band, Sec. 3):
  * eps(k) = -2t (cos kx + cos ky) - 4t' cos kx cos ky - 2t'' (cos 2kx + cos 2ky).
  * eps is row major [iy][ix]. */
 void oracle_band_tb(double t, double tp, double tpp, int nkx, int nky, double *eps)
 {
+    oracle_band_tb_z(t, tp, tpp, nkx, nky, 1, eps);
+}
+
+/* The same band on a momentum grid spanning kz Brillouin zones per axis
+ * (extended momentum p = 2 pi kz (ix/nkx, iy/nky), Eq. (9)). */
+void oracle_band_tb_z(double t, double tp, double tpp, int nkx, int nky, int kz, double *eps)
+{
     for (int iy = 0; iy < nky; ++iy) {
-        double ky = 2.0 * ORACLE_PI * iy / nky;
+        double ky = 2.0 * ORACLE_PI * kz * iy / nky;
         for (int ix = 0; ix < nkx; ++ix) {
-            double kx = 2.0 * ORACLE_PI * ix / nkx;
+            double kx = 2.0 * ORACLE_PI * kz * ix / nkx;
             eps[(size_t)iy * nkx + ix] = -2.0 * t * (cos(kx) + cos(ky)) - 4.0 * tp * cos(kx) * cos(ky) -
                                          2.0 * tpp * (cos(2.0 * kx) + cos(2.0 * ky));
         }
@@ -136,8 +145,8 @@ static inline double lorentz(double e, double xi, double gamma)
  * Only the energy points that some requested lag can reach are evaluated:
  * occupied j >= j0 - max(m) for A(k, j), unoccupied j < j0 + max(m) for
  * A(k+q, j). */
-static void chi_one_q(const double *xi, int nkx, int nky, int neps, double emin, double d, int j0,
-                      double gamma, int qx, int qy, int nm, const int *ms, double *acc, double *arow,
+static void chi_one_q(const double *xi, const double *rho, int nkx, int nky, int neps, double emin, double d,
+                      int j0, double gamma, int qx, int qy, int nm, const int *ms, double *acc, double *arow,
                       double *brow, nsum *sums)
 {
     int mmax = 0;
@@ -167,7 +176,9 @@ static void chi_one_q(const double *xi, int nkx, int nky, int neps, double emin,
                 nsum p = {0.0, 0.0};
                 for (int j = jlo; j < jhi; ++j)
                     nsum_add(&p, arow[j] * brow[j + m]);
-                nsum_add(&sums[im], nsum_get(&p));
+                /* momentum-density weights of Eq. (4): rho(k) rho(k+q) */
+                double w = rho ? rho[(size_t)iy * nkx + ix] * rho[(size_t)iy2 * nkx + ix2] : 1.0;
+                nsum_add(&sums[im], w * nsum_get(&p));
             }
         }
     }
@@ -178,9 +189,22 @@ static void chi_one_q(const double *xi, int nkx, int nky, int neps, double emin,
 /* Im chi_1BZ(q, m) on a q-list x lag-list grid (Eq. (9) in the discrete
  * form above).  xi = eps - mu, row major [iy][ix].  out[iq * nm + im].
  * Lags outside 1 <= m < neps have an empty energy window and give 0. */
+int oracle_chi_grid_w(const double *xi, const double *rho, int nkx, int nky, int neps, double emin,
+                      double emax, double gamma, int nq, const int *qx, const int *qy, int nm, const int *ms,
+                      double *out);
+
 int oracle_chi_grid(const double *xi, int nkx, int nky, int neps, double emin, double emax,
                     double gamma, int nq, const int *qx, const int *qy, int nm, const int *ms,
                     double *out)
+{
+    return oracle_chi_grid_w(xi, NULL, nkx, nky, neps, emin, emax, gamma, nq, qx, qy, nm, ms, out);
+}
+
+/* The same with momentum-density weights rho[iy][ix] on the spectral
+ * function (A(p, e) = rho(p) A_band(p, e), Eq. (4)); rho = NULL means 1. */
+int oracle_chi_grid_w(const double *xi, const double *rho, int nkx, int nky, int neps, double emin,
+                      double emax, double gamma, int nq, const int *qx, const int *qy, int nm, const int *ms,
+                      double *out)
 {
     if (nkx <= 0 || nky <= 0 || neps <= 0 || !(emax > emin) || !(gamma > 0)) return -1;
     double d = (emax - emin) / neps;
@@ -199,7 +223,7 @@ int oracle_chi_grid(const double *xi, int nkx, int nky, int neps, double emin, d
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int iq = 0; iq < nq; ++iq) {
-                chi_one_q(xi, nkx, nky, neps, emin, d, j0, gamma, qx[iq], qy[iq], nm, ms, acc, arow,
+                chi_one_q(xi, rho, nkx, nky, neps, emin, d, j0, gamma, qx[iq], qy[iq], nm, ms, acc, arow,
                           brow, sums);
                 for (int im = 0; im < nm; ++im)
                     out[(size_t)iq * nm + im] = scale * acc[im];
@@ -214,9 +238,21 @@ int oracle_chi_grid(const double *xi, int nkx, int nky, int neps, double emin, d
 }
 
 /* Im chi_1BZ at an explicit list of (qx, qy, m) samples; out[i]. */
+int oracle_chi_pairs_w(const double *xi, const double *rho, int nkx, int nky, int neps, double emin,
+                       double emax, double gamma, long npairs, const int *qx, const int *qy, const int *ms,
+                       double *out);
+
 int oracle_chi_pairs(const double *xi, int nkx, int nky, int neps, double emin, double emax,
                      double gamma, long npairs, const int *qx, const int *qy, const int *ms,
                      double *out)
+{
+    return oracle_chi_pairs_w(xi, NULL, nkx, nky, neps, emin, emax, gamma, npairs, qx, qy, ms, out);
+}
+
+/* Sampled form with momentum-density weights (rho = NULL means 1). */
+int oracle_chi_pairs_w(const double *xi, const double *rho, int nkx, int nky, int neps, double emin,
+                       double emax, double gamma, long npairs, const int *qx, const int *qy, const int *ms,
+                       double *out)
 {
     if (nkx <= 0 || nky <= 0 || neps <= 0 || !(emax > emin) || !(gamma > 0)) return -1;
     double d = (emax - emin) / neps;
@@ -235,7 +271,7 @@ int oracle_chi_pairs(const double *xi, int nkx, int nky, int neps, double emin, 
             for (long i = 0; i < npairs; ++i) {
                 double acc;
                 nsum s;
-                chi_one_q(xi, nkx, nky, neps, emin, d, j0, gamma, qx[i], qy[i], 1, &ms[i], &acc,
+                chi_one_q(xi, rho, nkx, nky, neps, emin, d, j0, gamma, qx[i], qy[i], 1, &ms[i], &acc,
                           arow, brow, &s);
                 out[i] = scale * acc;
             }
