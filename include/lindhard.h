@@ -85,6 +85,14 @@ typedef struct {
     double ff_width;            /* orbital width w in lattice constants (> 0 if used) */
     int32_t precision;          /* lindhard_precision */
     int32_t want_rpa;           /* nonzero: keep every lag for lindhard_rpa */
+    /* Extended momentum (Eqs. (4), (9)): the k-grid spans k_zones Brillouin
+     * zones per axis (p = 2 pi k_zones (ix/nkx, iy/nky); 0 or 1 = the first
+     * zone; at most 64) and, if rho_table is given, the spectral function is
+     * A(p, e) = rho(p) A_band(p, e) with the momentum density rho[iy][ix]
+     * (host table, x fastest, finite; read only during lindhard_plan).  The
+     * output q-grid is then the same extended grid. */
+    int32_t k_zones;
+    const double *rho_table;
 } lindhard_problem;
 
 typedef struct lindhard_plan_s *lindhard_plan_t;

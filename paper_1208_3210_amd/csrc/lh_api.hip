@@ -98,10 +98,17 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     } else if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->tpp)) {
         return LINDHARD_EINVAL;
     }
+    if (p->k_zones < 0 || p->k_zones > 64) return LINDHARD_EINVAL;
+    if (p->rho_table)
+        for (long k = 0; k < nk; ++k)
+            if (!std::isfinite(p->rho_table[k])) return LINDHARD_EINVAL;
 
     pl.p = *p;
     pl.p.omega = nullptr;
     pl.p.eps_table = nullptr;
+    pl.p.rho_table = nullptr;
+    pl.p.k_zones = std::max(1, p->k_zones);
+    pl.has_rho = p->rho_table != nullptr;
     pl.omega.assign(p->omega, p->omega + p->nomega);
     pl.deps = (p->emax - p->emin) / p->neps;
     Geo &g = pl.g;
@@ -215,18 +222,20 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     // mirror symmetry of the band -> real even transforms on the quarter plane
     {
         bool sym = true;
-        if (p->eps_table) {
+        // a table (band or momentum density) must be mirror symmetric bit for bit
+        auto mirror = [&](const double *tab) {
             const int nx = p->nkx, ny = p->nky;
-            for (int iy = 0; iy < ny && sym; ++iy)
+            for (int iy = 0; iy < ny; ++iy)
                 for (int ix = 0; ix < nx; ++ix) {
-                    const double e = p->eps_table[(size_t)iy * nx + ix];
-                    if (e != p->eps_table[(size_t)iy * nx + ((nx - ix) & (nx - 1))] ||
-                        e != p->eps_table[(size_t)((ny - iy) & (ny - 1)) * nx + ix]) {
-                        sym = false;
-                        break;
-                    }
+                    const double e = tab[(size_t)iy * nx + ix];
+                    if (e != tab[(size_t)iy * nx + ((nx - ix) & (nx - 1))] ||
+                        e != tab[(size_t)((ny - iy) & (ny - 1)) * nx + ix])
+                        return false;
                 }
-        }
+            return true;
+        };
+        if (p->eps_table) sym = mirror(p->eps_table);
+        if (sym && p->rho_table) sym = mirror(p->rho_table);
         if (const char *ev = std::getenv("LINDHARD_SYMMETRY"))
             if (!std::strcmp(ev, "off")) sym = false;
         g.even = sym ? 1 : 0;
@@ -312,6 +321,7 @@ size_t plan_footprint(const Plan &pl)
     size_t b = 0;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     b += al(nk * 8);
+    if (pl.has_rho) b += al(nk * es);
     b += al(g.nkx * cs) + al(g.nky * cs) + al(((size_t)1 << g.logNE) * cs);
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += 2 * al(pl.p.nomega * sizeof(int));
@@ -415,7 +425,8 @@ void plan_free(Plan &pl)
     pl.allocs.clear();
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_slot, (void **)&pl.d_lag, &pl.spec,
-                     &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch};
+                     &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
+                     &pl.rho};
     for (void **p : ptrs) *p = nullptr;
 }
 
@@ -677,6 +688,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
         if (s != LINDHARD_OK) return s;                      \
     } while (0)
     LH_ALLOC(pl.xi, nk * 8);
+    if (pl.has_rho) LH_ALLOC(pl.rho, nk * es);
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
     LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
@@ -742,6 +754,16 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
         const double bnd = 4.0 * (std::fabs(p->t) + std::fabs(p->tp) + std::fabs(p->tpp));
         band_lo = -bnd;
         band_hi = bnd;
+    }
+    std::vector<float> rho32;
+    if (p->rho_table) {
+        // momentum-density weights, rounded once to the plan's precision
+        if (pl.g.fp64) {
+            LH_TRY(hipMemcpyAsync(pl.rho, p->rho_table, nk * sizeof(double), hipMemcpyHostToDevice, st));
+        } else {
+            rho32.assign(p->rho_table, p->rho_table + nk);
+            LH_TRY(hipMemcpyAsync(pl.rho, rho32.data(), nk * sizeof(float), hipMemcpyHostToDevice, st));
+        }
     }
     if (std::isnan(p->mu)) {
         s = solve_mu(pl, st, band_lo, band_hi);

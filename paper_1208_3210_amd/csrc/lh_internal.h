@@ -88,6 +88,8 @@ struct Plan {
     void *twx = nullptr;       // cx<T>[nkx]
     void *twy = nullptr;       // cx<T>[nky]
     void *twe = nullptr;       // cx<T>[2^logNE] (energy-axis FFT)
+    bool has_rho = false;
+    void *rho = nullptr;       // momentum-density weights rho[iy][ix] in T (or none)
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
     double2 *ffy = nullptr;    // per extended row
     int *d_slot = nullptr;     // per omega: window slot or -1

@@ -26,7 +26,7 @@ constexpr int kThreads = 256;
 
 // ---------------------------------------------------------------- setup
 __global__ void __launch_bounds__(kThreads) k_band_tb(double *__restrict__ eps, int nkx, int logNx, int nky,
-                                                     double t, double tp, double tpp)
+                                                     double t, double tp, double tpp, int kz)
 {
     const long nk = (long)nkx * nky;
     const long k = (long)blockIdx.x * kThreads + threadIdx.x;
@@ -34,8 +34,9 @@ __global__ void __launch_bounds__(kThreads) k_band_tb(double *__restrict__ eps, 
     // folded indices make eps(kx, ky) = eps(-kx, ky) = eps(kx, -ky) bit for bit
     const int ix = min((int)(k & (nkx - 1)), nkx - (int)(k & (nkx - 1)));
     const int iy = min((int)(k >> logNx), nky - (int)(k >> logNx));
-    const double cx = cospi(2.0 * ix / nkx), cy = cospi(2.0 * iy / nky);
-    const double c2x = cospi(4.0 * ix / nkx), c2y = cospi(4.0 * iy / nky);
+    // k_zones kz: the grid spans kz zones, k = 2 pi kz (ix / nkx, iy / nky)
+    const double cx = cospi(2.0 * kz * ix / nkx), cy = cospi(2.0 * kz * iy / nky);
+    const double c2x = cospi(4.0 * kz * ix / nkx), c2y = cospi(4.0 * kz * iy / nky);
     eps[k] = -2.0 * t * (cx + cy) - 4.0 * tp * cx * cy - 2.0 * tpp * (c2x + c2y);
 }
 
@@ -181,10 +182,10 @@ __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2
 // L = nkx/2, then split into X[k], k = 0..L (real-to-complex) and written to
 // the column-tiled spectral array.  e_j - xi_k is formed in FP64; the
 // Lorentzian and the transform run in T.
-template <typename T, int LOGL>
+template <typename T, int LOGL, bool W>
 __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx,
-                                                cx<T> *__restrict__ spec)
+                                                cx<T> *__restrict__ spec, const T *__restrict__ rho)
 {
     using F = RegFFT<T, LOGL, false>;
     constexpr int L = F::N, E = F::E, G = F::G;
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
     cx<T> *buf = lds + row * L;
 
     double xa[E], xb[E];
+    T ra[W ? E : 1], rb[W ? E : 1];  // momentum-density weights (W)
     {
         const double2 *xr = reinterpret_cast<const double2 *>(xi + (size_t)(ky0 + row) * g.nkx);
 #pragma unroll
@@ -206,6 +208,10 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
             const double2 x2 = xr[gg + s * G];
             xa[s] = x2.x;
             xb[s] = x2.y;
+            if constexpr (W) {
+                ra[s] = rho[(size_t)(ky0 + row) * g.nkx + 2 * (gg + s * G)];
+                rb[s] = rho[(size_t)(ky0 + row) * g.nkx + 2 * (gg + s * G) + 1];
+            }
         }
     }
     const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
@@ -218,7 +224,10 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
-            v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
+            if constexpr (W)
+                v[s] = mk<T>(lorentz(d0, gp, g2) * ra[s], lorentz(d1, gp, g2) * rb[s]);
+            else
+                v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
         F::run(v, buf, twx, 1, gg, lds_xor_gfast<L, G>(row));
 #pragma unroll
@@ -593,9 +602,10 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // rx in [0, nkx/2] and ry in [0, nky/2] are stored (see Geo).
 
 // P1 (even): R row pairs (ky = 2p, 2p+1, ky <= nky/2) for jc slices.
-template <typename T, int LOGNX>
+template <typename T, int LOGNX, bool W>
 __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
-                                                double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec)
+                                                double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
+                                                const T *__restrict__ rho)
 {
     using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -618,10 +628,15 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
         __syncthreads();
     }
     double xa[E], xb[E];
+    T ra[W ? E : 1], rb[W ? E : 1];  // momentum-density weights (W)
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         xa[s] = xi[(size_t)kya * N + gg + s * G];
         xb[s] = xi[(size_t)kyb * N + gg + s * G];
+        if constexpr (W) {
+            ra[s] = rho[(size_t)kya * N + gg + s * G];
+            rb[s] = rho[(size_t)kyb * N + gg + s * G];
+        }
     }
     const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
     const int Ce = g.Ce, H = N / 2;
@@ -634,7 +649,10 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const T d0 = (T)(ej - xa[s]), d1 = (T)(ej - xb[s]);
-            v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
+            if constexpr (W)
+                v[s] = mk<T>(lorentz(d0, gp, g2) * ra[s], lorentz(d1, gp, g2) * rb[s]);
+            else
+                v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
         F::run(v, buf, tw, 0, gg, lds_xor_gfast<N, G>(line));
         // only rx in [0, nkx/2] is stored
@@ -1632,7 +1650,7 @@ hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st)
     const long nk = (long)g.nkx * g.nky;
     if (d_table) return hipMemcpyAsync(pl.xi, d_table, nk * sizeof(double), hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_band_tb, dim3(cdiv(nk, kThreads)), dim3(kThreads), 0, st, pl.xi, g.nkx, g.logNx, g.nky,
-                       pl.p.t, pl.p.tp, pl.p.tpp);
+                       pl.p.t, pl.p.tp, pl.p.tpp, pl.p.k_zones);
     return hipGetLastError();
 }
 
@@ -1686,9 +1704,14 @@ static void launch_p1(const Plan &pl, cx<T> *spec, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, false>;
-    hipLaunchKernelGGL((k_p1<T, LOGL>), dim3(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc)), dim3(g.p1_R * F::G),
-                       (size_t)g.p1_R * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
-                       (const cx<T> *)pl.twx, spec);
+    const dim3 grid(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc));
+    const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>);
+    if (pl.rho)
+        hipLaunchKernelGGL((k_p1<T, LOGL, true>), grid, dim3(g.p1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho);
+    else
+        hipLaunchKernelGGL((k_p1<T, LOGL, false>), grid, dim3(g.p1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr);
 }
 
 template <typename T, int LOGN, bool INV>
@@ -1728,9 +1751,14 @@ static void launch_e1(const Plan &pl, T *spec, hipStream_t st)
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     const int np = (g.Hy + 1) / 2;
-    hipLaunchKernelGGL((k_e1<T, LOGNX>), dim3(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc)), dim3(g.e1_R * F::G),
-                       (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, pl.xi, g, pl.p.emin, pl.deps, pl.p.gamma,
-                       (const cx<T> *)pl.twx, spec);
+    const dim3 grid(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc));
+    const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);
+    if (pl.rho)
+        hipLaunchKernelGGL((k_e1<T, LOGNX, true>), grid, dim3(g.e1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho);
+    else
+        hipLaunchKernelGGL((k_e1<T, LOGNX, false>), grid, dim3(g.e1_R * F::G), lds, st, pl.xi, g, pl.p.emin,
+                           pl.deps, pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr);
 }
 
 template <typename T, int LOGN, bool INV>

@@ -57,6 +57,34 @@ def config3(nk: int = 2048, neps: int = 512) -> dict:
                 ff_width=0.0)
 
 
+def momentum_density_dx2y2(nkx: int, nky: int, k_zones: int, w: float) -> np.ndarray:
+    """Synthetic momentum density [iy][ix] of a Gaussian d_{x2-y2}-like orbital
+    (x^2 - y^2) exp(-r^2 / (2 w^2)) of width w (lattice constants), standing in
+    for the KKR momentum densities the paper uses: |phi(p)|^2 is proportional to
+    (px^2 - py^2)^2 exp(-w^2 |p|^2), here normalised to a peak of 1, on the grid
+    p = 2 pi k_zones (ix/nkx, iy/nky) taken with folded (mirror-symmetric)
+    indices so that the table is exactly even in px and py."""
+    ix = np.minimum(np.arange(nkx), nkx - np.arange(nkx))
+    iy = np.minimum(np.arange(nky), nky - np.arange(nky))
+    px = 2.0 * np.pi * k_zones * ix / nkx
+    py = 2.0 * np.pi * k_zones * iy / nky
+    PX, PY = np.meshgrid(px, py)
+    rho = (PX * PX - PY * PY) ** 2 * np.exp(-w * w * (PX * PX + PY * PY))
+    return rho / rho.max()
+
+
+def config_extended(nk: int = 2048, k_zones: int = 16, neps: int = 512) -> dict:
+    """Extended-momentum instance (the form the paper computes for its
+    extended-zone maps): a 2048^2 momentum grid spanning 16 x 16 Brillouin
+    zones (128 points per zone), the band of config 1 (filling 1.15), the
+    Gaussian d_{x2-y2} momentum density of width 0.6 on the spectral function,
+    512 energies on [-2, 2] eV, G = 0.02 eV, 256 omegas in (0, 2] eV."""
+    emin, emax = -2.0, 2.0
+    return dict(**BAND1, filling=1.15, nkx=nk, nky=nk, neps=neps, emin=emin, emax=emax, gamma=0.02,
+                omega=lag_omegas(neps, emin, emax, range(1, neps // 2 + 1)), zones=(1, 1), ff_kind=0,
+                ff_width=0.0, k_zones=k_zones, rho_table=momentum_density_dx2y2(nk, nk, k_zones, 0.6))
+
+
 def config4(n: int = 64, seed: int = 4) -> list:
     """Batched: 64 instances, k-grid uniform over {128,256,512,1024}^2, energies
     over {64,128,256,512} on [-2, 2] eV, doping x in [0, 0.2] (filling 1 + x),
