@@ -216,6 +216,19 @@ def bench_epilogues(LH, W, torch, reps=3):
         out[name] = {"ms": ms, "alg_GB": nbytes / 1e9, "GB/s": nbytes / (ms * 1e-3) / 1e9,
                      "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     plan.close()
+    # omegas between lag-grid points: the row-transform pass reads two lag
+    # slices per output plane and blends them (the other passes are unchanged)
+    d = (cfg["emax"] - cfg["emin"]) / cfg["neps"]
+    og = {}
+    for label, extra in (("on_grid", {}),
+                         ("between_lags", dict(omega_interp=True, omega=(np.arange(1, 129) + 0.5) * d))):
+        p2 = LH.Plan(precision=LH.LINDHARD_FP32C, **dict(cfg, want_rpa=False, **extra))
+        o2 = p2.empty()
+        p2.exec_timed(o2)
+        runs = [p2.exec_timed(o2) for _ in range(reps)]
+        og[label] = {"exec_ms": float(np.mean([sum(r) for r in runs])), "p5_ms": float(np.mean([r[4] for r in runs]))}
+        p2.close()
+    out["omega_between_lags"] = og
     return out
 
 

@@ -79,7 +79,8 @@ typedef struct {
     int32_t neps;               /* power of two, 4 .. 2048 */
     double emin, emax;          /* energy window, emin < 0 < emax */
     int32_t nomega;             /* number of requested omegas, 1 .. 65536 */
-    const double *omega;        /* host array of omegas, eV; each m*d, m >= 0 */
+    const double *omega;        /* host array of omegas, eV; each m*d, m >= 0
+                                   (or >= 0 anywhere with omega_interp) */
     int32_t zones_x, zones_y;   /* odd, >= 1, zones_x*nkx and zones_y*nky <= 65536 */
     int32_t ff_kind;            /* lindhard_ff */
     double ff_width;            /* orbital width w in lattice constants (> 0 if used) */
@@ -93,6 +94,12 @@ typedef struct {
      * output q-grid is then the same extended grid. */
     int32_t k_zones;
     const double *rho_table;
+    /* Omegas off the lag grid: 0 = rejected (LINDHARD_EOFFGRID); 1 = an omega
+     * with m d < omega < (m + 1) d takes the linear interpolation
+     * (1 - f) chi(m d) + f chi((m + 1) d), f = omega / d - m, of the lag-grid
+     * values (Im chi, and Re chi from the Kramers-Kronig pass); values at lags
+     * 0 and >= neps are 0.  Omegas within 1e-9 d of the grid are on it. */
+    int32_t omega_interp;
 } lindhard_problem;
 
 typedef struct lindhard_plan_s *lindhard_plan_t;

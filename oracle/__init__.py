@@ -349,3 +349,57 @@ def chi_qmean(xi: np.ndarray, neps: int, emin: float, emax: float, gamma: float,
         else:
             out.append(-d * float(np.dot(DP[:neps - m], DH[m:])))
     return np.array(out)
+
+
+# --------------------------------------------------------------------------
+# Omegas between lag-grid points (a reading: the method computes chi only at
+# omega = m d, the energy step of the spectral-function grid)
+# --------------------------------------------------------------------------
+def omega_lags(omega, neps: int, emin: float, emax: float, interp: bool = False):
+    """Lag m and fraction f of each omega, omega = (m + f) d, 0 <= f < 1.
+
+    An omega within 1e-9 d of a grid point is on it (f = 0).  Off the grid
+    the omega is rejected (ValueError) unless ``interp``."""
+    d = energy_step(neps, emin, emax)
+    ms, fs = [], []
+    for om in np.asarray(omega, dtype=np.float64).ravel():
+        r = om / d
+        m = int(np.rint(r))
+        if m >= 0 and abs(om - m * d) <= 1e-9 * d:
+            ms.append(m)
+            fs.append(0.0)
+        elif interp and r > 0.0:
+            m = int(np.floor(r))
+            ms.append(m)
+            fs.append(r - m)
+        else:
+            raise ValueError("omega %r is not on the lag grid" % om)
+    return np.array(ms, dtype=np.int64), np.array(fs)
+
+
+def lag_interp(values, m, f):
+    """Value at omega = (m + f) d from values on the lag grid (last axis,
+    lags 0 .. Neps-1): the straight line through the two neighbouring grid
+    values, (1 - f) V(m) + f V(m + 1), where V is 0 at lag 0 and at lags
+    beyond the grid (the discrete Im chi vanishes there)."""
+    v = np.asarray(values, dtype=np.float64)
+    neps = v.shape[-1]
+
+    def at(k):
+        if 1 <= k < neps:
+            return v[..., k]
+        return np.zeros(v.shape[:-1])
+
+    return np.stack([(1.0 - fi) * at(int(mi)) + fi * at(int(mi) + 1) if fi > 0.0 else at(int(mi))
+                     for mi, fi in zip(np.asarray(m).ravel(), np.asarray(f).ravel())], axis=-1)
+
+
+def kk_real_interp(im_all: np.ndarray, m, f) -> np.ndarray:
+    """Re chi at omega = (m + f) d: the straight line through ``kk_real`` at
+    lags m and m + 1 (Re chi does not vanish at lag 0 or beyond the grid, so
+    both ends come from the Kramers-Kronig sum itself)."""
+    m = np.asarray(m, dtype=np.int64).ravel()
+    f = np.asarray(f, dtype=np.float64).ravel()
+    lo = kk_real(im_all, m)
+    hi = kk_real(im_all, m + 1)
+    return np.where(f > 0.0, (1.0 - f) * lo + f * hi, lo)

@@ -126,21 +126,33 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     g.neps = p->neps;
     g.j0 = count_occupied(p->neps, p->emin, p->emax);
 
-    // omega -> lag m (omega = m d within 1e-9 d, m >= 0)
+    // omega -> lag m (omega = m d within 1e-9 d, m >= 0); with omega_interp an
+    // omega strictly between lags m and m + 1 keeps frac f = omega / d - m
     pl.lag.resize(p->nomega);
+    pl.frac.assign(p->nomega, 0.0);
     int mlo = INT_MAX, mhi = -1;
+    auto need = [&](long m) {
+        if (m >= 1 && m < p->neps) {
+            mlo = std::min(mlo, (int)m);
+            mhi = std::max(mhi, (int)m);
+        }
+    };
     for (int w = 0; w < p->nomega; ++w) {
         const double om = p->omega[w];
         if (!std::isfinite(om)) return LINDHARD_EOFFGRID;
         const double r = om / pl.deps;
         if (r < -0.5 || r > (double)INT_MAX / 2) return LINDHARD_EOFFGRID;
-        const long m = std::lround(r);
-        if (m < 0 || std::fabs(om - (double)m * pl.deps) > 1e-9 * pl.deps) return LINDHARD_EOFFGRID;
-        pl.lag[w] = (int)m;
-        if (m >= 1 && m < p->neps) {
-            mlo = std::min(mlo, (int)m);
-            mhi = std::max(mhi, (int)m);
+        long m = std::lround(r);
+        double f = 0.0;
+        if (m < 0 || std::fabs(om - (double)m * pl.deps) > 1e-9 * pl.deps) {
+            if (!p->omega_interp || r <= 0.0) return LINDHARD_EOFFGRID;
+            m = (long)std::floor(r);
+            f = r - (double)m;
+            need(m + 1);
         }
+        pl.lag[w] = (int)m;
+        pl.frac[w] = f;
+        need(m);
     }
     if (p->want_rpa) {
         mlo = 1;
@@ -160,10 +172,25 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     }
     g.nslots = std::max(g.nS, g.nL);
     g.slice_elems = (size_t)g.NT * g.nky * g.C;
-    pl.slot.resize(p->nomega);
+    pl.src.resize(p->nomega);
     for (int w = 0; w < p->nomega; ++w) {
+        auto slot_of = [&](int m) { return (g.nL > 0 && m >= g.m_lo && m <= g.m_hi) ? m - g.m_lo : -1; };
         const int m = pl.lag[w];
-        pl.slot[w] = (g.nL > 0 && m >= g.m_lo && m <= g.m_hi) ? m - g.m_lo : -1;
+        const double f = pl.frac[w];
+        PlaneSrc ps{slot_of(m), -1, 1.0, 0.0};
+        if (f > 0.0) {
+            ps.wa = 1.0 - f;
+            ps.b = slot_of(m + 1);
+            ps.wb = f;
+            if (ps.a < 0) {  // lag m contributes 0: keep the other term alone
+                ps.a = ps.b;
+                ps.wa = ps.wb;
+                ps.b = -1;
+                ps.wb = 0.0;
+            }
+            if (ps.b < 0) ps.wb = 0.0;
+        }
+        pl.src[w] = ps;
     }
 
     // launch shapes
@@ -324,7 +351,7 @@ size_t plan_footprint(const Plan &pl)
     if (pl.has_rho) b += al(nk * es);
     b += al(g.nkx * cs) + al(g.nky * cs) + al(((size_t)1 << g.logNE) * cs);
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
-    b += 2 * al(pl.p.nomega * sizeof(int));
+    b += al(pl.p.nomega * sizeof(PlaneSrc)) + al(pl.p.nomega * sizeof(int)) + al(pl.p.nomega * sizeof(double));
     b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
     b += al(scratch_bytes(pl));
     if (pl.p.want_rpa) {
@@ -424,7 +451,7 @@ void plan_free(Plan &pl)
     for (auto &a : pl.allocs) pool_free(a.first, a.second, pl.device);
     pl.allocs.clear();
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
-                     (void **)&pl.ffy,    (void **)&pl.d_slot, (void **)&pl.d_lag, &pl.spec,
+                     (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
                      &pl.rho};
     for (void **p : ptrs) *p = nullptr;
@@ -694,7 +721,8 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
     LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
     LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
-    LH_ALLOC(pl.d_slot, pl.p.nomega * sizeof(int));
+    LH_ALLOC(pl.d_src, pl.p.nomega * sizeof(PlaneSrc));
+    LH_ALLOC(pl.d_frac, pl.p.nomega * sizeof(double));
     LH_ALLOC(pl.d_lag, pl.p.nomega * sizeof(int));
     LH_ALLOC(pl.spec, g.even ? (size_t)g.nslots * g.slice_e * es : (size_t)g.nslots * g.slice_elems * cs);
     LH_ALLOC(pl.scratch, scratch_bytes(pl));
@@ -773,7 +801,8 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
         pl.mu_iters = 0;
     }
     LH_TRY(launch_xi_shift(pl, pl.mu, st));
-    LH_TRY(hipMemcpyAsync(pl.d_slot, pl.slot.data(), pl.slot.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    LH_TRY(hipMemcpyAsync(pl.d_src, pl.src.data(), pl.src.size() * sizeof(PlaneSrc), hipMemcpyHostToDevice, st));
+    LH_TRY(hipMemcpyAsync(pl.d_frac, pl.frac.data(), pl.frac.size() * sizeof(double), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_lag, pl.lag.data(), pl.lag.size() * sizeof(int), hipMemcpyHostToDevice, st));
     LH_TRY(launch_tables(pl, st));
     if (pl.p.want_rpa)

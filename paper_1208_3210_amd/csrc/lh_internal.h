@@ -20,6 +20,14 @@ namespace lh {
 // A column pass reads one tile (nky * C values) as one contiguous block, a row
 // pass reads R rows * C values per tile, the energy-window pass reads RY rows
 // * C values per slice.
+// Source of one output plane: wa S[a] + wb S[b] over window slots a, b
+// (a < 0: the plane is zero; b < 0: no second term).  On-grid omegas have
+// a single slot with wa = 1; an omega between lags m and m + 1 blends the two.
+struct PlaneSrc {
+    int a, b;
+    double wa, wb;
+};
+
 struct Geo {
     int fp64;
     int nkx, nky, logNx, logNy;
@@ -76,7 +84,8 @@ struct Plan {
     lindhard_problem p{};
     std::vector<double> omega;
     std::vector<int> lag;      // lag m of each requested omega (>= 0)
-    std::vector<int> slot;     // window slot of each omega, -1 if the value is 0
+    std::vector<double> frac;  // omega = (lag + frac) d, 0 <= frac < 1 (0 on the grid)
+    std::vector<PlaneSrc> src; // window slots of each omega's plane
     int device = 0;
     Geo g{};
     double mu = 0.0, deps = 0.0, scale = 0.0, ff_s = 0.0;
@@ -92,7 +101,8 @@ struct Plan {
     void *rho = nullptr;       // momentum-density weights rho[iy][ix] in T (or none)
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
     double2 *ffy = nullptr;    // per extended row
-    int *d_slot = nullptr;     // per omega: window slot or -1
+    PlaneSrc *d_src = nullptr; // per omega: window slots and weights
+    double *d_frac = nullptr;  // per omega: frac
     int *d_lag = nullptr;      // per omega: lag
     void *spec = nullptr;      // spectral / real-space array, nslots slices
     void *im1 = nullptr;       // RPA: Im chi_1BZ [neps][nky][nkx]

@@ -127,16 +127,24 @@ __global__ void __launch_bounds__(kThreads) k_fftab(double2 *__restrict__ tab, i
 // stored j-major, w[j * nwp + i] with nwp = nw rounded up to kKkW (zero
 // padding) so that the weights of consecutive output lags are contiguous.
 constexpr int kKkW = 8;
-__global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const int *__restrict__ lags, int nw,
-                                                 int nwp, int neps)
+// An omega between lags m and m + 1 (frac f > 0) takes (1 - f) w[m] + f w[m + 1].
+__device__ __forceinline__ double kk_weight(long i, int j)
+{
+    if (j < 1 || !(((long)j - i) & 1)) return 0.0;
+    const double di = (double)i, dj = (double)j;
+    return (2.0 / kPi) * 2.0 * dj / (dj * dj - di * di);
+}
+__global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const int *__restrict__ lags,
+                                                 const double *__restrict__ fracs, int nw, int nwp, int neps)
 {
     const long idx = (long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= (long)nwp * neps) return;
     const int j = (int)(idx / nwp), wi = (int)(idx % nwp);
     double v = 0.0;
-    if (wi < nw && j >= 1 && (((long)j - (long)lags[wi]) & 1)) {
-        const double i = (double)lags[wi], dj = (double)j;
-        v = (2.0 / kPi) * 2.0 * dj / (dj * dj - i * i);
+    if (wi < nw) {
+        const double f = fracs[wi];
+        v = kk_weight(lags[wi], j);
+        if (f > 0.0) v = (1.0 - f) * v + f * kk_weight((long)lags[wi] + 1, j);
     }
     w[idx] = v;
 }
@@ -496,7 +504,7 @@ __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, co
 // MODE 1: plane = window slot; writes the first-zone map out[m][qy][qx].
 template <typename T, int LOGL, int MODE>
 __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec, Geo g,
-                                                const cx<T> *__restrict__ twx, const int *__restrict__ plane_slot,
+                                                const cx<T> *__restrict__ twx, const PlaneSrc *__restrict__ psrc,
                                                 double scale, int zx, int zy, int ff, double ffs,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
                                                 T *__restrict__ out, int out_nx, int out_ny)
@@ -511,7 +519,8 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int row = tid / G, gg = tid % G;
     const int plane = blockIdx.y;
     const int qy0 = blockIdx.x * R;
-    const int slot = MODE == 0 ? plane_slot[plane] : plane;
+    const PlaneSrc ps = MODE == 0 ? psrc[plane] : PlaneSrc{plane, -1, 1.0, 0.0};
+    const int slot = ps.a;
     const int nkx = g.nkx, nky = g.nky;
 
     if (MODE == 0 && slot < 0) {
@@ -526,6 +535,10 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 
     const int C = g.C, logC = g.logC;
     const cx<T> *src = spec + (size_t)slot * g.slice_elems;
+    // an omega between two lags: wa S[a] + wb S[b] (wb = 0 reads S[a] twice)
+    const bool blend = ps.b >= 0 || ps.wa != 1.0;
+    const cx<T> *src2 = spec + (size_t)(ps.b >= 0 ? ps.b : slot) * g.slice_elems;
+    const T wa = (T)ps.wa, wb = (T)ps.wb;
     const int nin = g.NT * (R << logC);
     for (int it0 = tid; it0 < nin; it0 += 8 * nthr) {
         cx<T> v[8];
@@ -535,7 +548,12 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
             const int c = it & (C - 1);
             const int r = (it >> logC) & (R - 1);
             const int tile = it >> (logC + logR);
-            v[k] = src[it < nin ? ((size_t)tile * nky + qy0 + r) * C + c : 0];
+            const size_t o = it < nin ? ((size_t)tile * nky + qy0 + r) * C + c : 0;
+            v[k] = src[o];
+            if (blend) {
+                const cx<T> y = src2[o];
+                v[k] = mk<T>(wa * v[k].x + wb * y.x, wa * v[k].y + wb * y.y);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -1278,7 +1296,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
 // planes (natural order) for the RPA path.
 template <typename T, int LOGNX, int MODE>
 __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
-                                                const int *__restrict__ plane_slot, double scale, int zx, int zy,
+                                                const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
                                                 int out_ny)
@@ -1293,7 +1311,8 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int line = tid / G, gg = tid % G;
     const int plane = blockIdx.y;
     const int p0 = blockIdx.x * R;
-    const int slot = MODE == 0 ? plane_slot[plane] : plane;
+    const PlaneSrc ps = MODE == 0 ? psrc[plane] : PlaneSrc{plane, -1, 1.0, 0.0};
+    const int slot = ps.a;
     const int nkx = g.nkx, nky = g.nky, Hy = g.Hy, H = N / 2, SW = H + 1;
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
 
@@ -1311,6 +1330,10 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     }
     const int Ce = g.Ce;
     const T *src = spec + (size_t)slot * g.slice_e;
+    // an omega between two lags: wa S[a] + wb S[b] (wb = 0 reads S[a] twice)
+    const bool blend = ps.b >= 0 || ps.wa != 1.0;
+    const T *src2 = spec + (size_t)(ps.b >= 0 ? ps.b : slot) * g.slice_e;
+    const T wa = (T)ps.wa, wb = (T)ps.wb;
     constexpr int VEC = 16 / sizeof(T), HV = 2, logHV = 1;  // 16-byte pieces of a 32-byte tile row
     const int nvec = g.NTe * rows * HV;
     const cx<T> *tw = twx;
@@ -1331,8 +1354,13 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
             const int tile = (it >> logHV) >> logRows;
             const int qy = 2 * p0 + r;
             const bool ok = it < nvec && qy < Hy;
-            const lh_u4 x = *reinterpret_cast<const lh_u4 *>(src + (ok ? ((size_t)tile * Hy + qy) * Ce + h * VEC : 0));
-            v[k] = __builtin_bit_cast(Vec16<T>, x);
+            const size_t o = ok ? ((size_t)tile * Hy + qy) * Ce + h * VEC : 0;
+            v[k] = __builtin_bit_cast(Vec16<T>, *reinterpret_cast<const lh_u4 *>(src + o));
+            if (blend) {
+                const Vec16<T> y = __builtin_bit_cast(Vec16<T>, *reinterpret_cast<const lh_u4 *>(src2 + o));
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) v[k].v[i] = wa * v[k].v[i] + wb * y.v[i];
+            }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -1392,13 +1420,29 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     }
 }
 
+// First-zone value at lag m (0 outside 1 <= m < neps), and the blend
+// (1 - f) value(m) + f value(m + 1) in FP64 for an omega between two lags.
+template <typename T>
+__device__ __forceinline__ T lag_value(const T *__restrict__ im1, size_t nk, size_t q, int neps, long m)
+{
+    const bool in = m >= 1 && m < neps;
+    const T x = im1[(size_t)(in ? m : 1) * nk + q];
+    return in ? x : (T)0;
+}
+template <typename T>
+__device__ __forceinline__ double lag_blend(const T *__restrict__ im1, size_t nk, size_t q, int neps, long m,
+                                            double f)
+{
+    return (1.0 - f) * (double)lag_value(im1, nk, q, neps, m) + f * (double)lag_value(im1, nk, q, neps, m + 1);
+}
+
 // Extended, form-factor weighted map from the first-zone planes (RPA path).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, int nkx, int nky, int neps,
-                                                    const int *__restrict__ lags, int nw, int zx, int zy, int ff,
-                                                    double ffs, const double2 *__restrict__ ffx,
-                                                    const double2 *__restrict__ ffy, T *__restrict__ out,
-                                                    int out_nx, int out_ny)
+                                                    const int *__restrict__ lags, const double *__restrict__ fracs,
+                                                    int nw, int zx, int zy, int ff, double ffs,
+                                                    const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
+                                                    T *__restrict__ out, int out_nx, int out_ny)
 {
     // one thread per first-zone point (u, v) and group of four planes: the
     // first-zone values are read once and written to every zone image
@@ -1409,10 +1453,10 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
     T vals[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int m = lags[min(w0 + i, nw - 1)];
-        const bool in = m >= 1 && m < neps;
-        const T x = im1[((size_t)(in ? m : 1) * nky + v) * nkx + u];
-        vals[i] = in ? x : (T)0;
+        const int w = min(w0 + i, nw - 1);
+        const double f = fracs[w];
+        vals[i] = f > 0.0 ? (T)lag_blend(im1, (size_t)nkx * nky, (size_t)v * nkx + u, neps, lags[w], f)
+                          : lag_value(im1, (size_t)nkx * nky, (size_t)v * nkx + u, neps, lags[w]);
     }
     const size_t plane = (size_t)out_nx * out_ny;
     const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
@@ -1497,7 +1541,8 @@ __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int 
 // interaction, FP64 arithmetic, rounded once to T.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, const T *__restrict__ re1, int nkx,
-                                                 int nky, int neps, const int *__restrict__ lags, int nw, int zx,
+                                                 int nky, int neps, const int *__restrict__ lags,
+                                                 const double *__restrict__ fracs, int nw, int zx,
                                                  int zy, int ff, double ffs, const double2 *__restrict__ ffx,
                                                  const double2 *__restrict__ ffy, int vkind, double V,
                                                  T *__restrict__ re_out, T *__restrict__ imr, T *__restrict__ rer,
@@ -1514,12 +1559,10 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int w = min(w0 + i, nw - 1);
-        const int m = lags[w];
-        const bool in = m >= 1 && m < neps;
-        const T x = im1[(size_t)(in ? m : 1) * nk + q];
-        const T y = re1[(size_t)w * nk + q];
-        imv[i] = in ? (double)x : 0.0;
-        rev[i] = (double)y;
+        const double f = fracs[w];
+        imv[i] = f > 0.0 ? (double)(T)lag_blend(im1, nk, q, neps, lags[w], f)
+                         : (double)lag_value(im1, nk, q, neps, lags[w]);
+        rev[i] = (double)re1[(size_t)w * nk + q];
     }
     const size_t plane = (size_t)out_nx * out_ny;
     const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
@@ -1565,10 +1608,11 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
 // consecutive elements per thread (16-byte accesses) when both arrays allow.
 template <typename T, int VEC>
 __global__ void __launch_bounds__(kThreads) k_sqw(const T *__restrict__ im, T *__restrict__ s,
-                                                 const int *__restrict__ lags, double deps, double kT, size_t plane)
+                                                 const int *__restrict__ lags, const double *__restrict__ fracs,
+                                                 double deps, double kT, size_t plane)
 {
     const int w = blockIdx.y;
-    const double om = lags[w] * deps;
+    const double om = fracs[w] > 0.0 ? (lags[w] + fracs[w]) * deps : lags[w] * deps;
     double f;
     if (kT > 0.0)
         f = om == 0.0 ? 0.0 : 1.0 / (-expm1(-om / kT));
@@ -1687,7 +1731,7 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
     if (pl.p.want_rpa) {
         const int nwp = (pl.p.nomega + kKkW - 1) / kKkW * kKkW;
         const long n = (long)nwp * g.neps;
-        hipLaunchKernelGGL(k_kkw, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, pl.kkw, pl.d_lag, pl.p.nomega,
+        hipLaunchKernelGGL(k_kkw, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, pl.kkw, pl.d_lag, pl.d_frac, pl.p.nomega,
                            nwp, g.neps);
     }
     return hipGetLastError();
@@ -1741,7 +1785,7 @@ static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, in
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
-                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
+                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
                        pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
 }
 
@@ -1780,7 +1824,7 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
-                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_slot,
+                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
                        pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
 }
 
@@ -1847,7 +1891,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 #undef LH_E5
             }
             hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads),
-                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s,
+                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s,
                                pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
         } else {
 #define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
@@ -1888,7 +1932,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 #undef LH_P5
         }
         hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
-                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
+                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
                            pl.ffy, out, pl.out_nx, pl.out_ny);
     } else {
 #define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
@@ -2017,7 +2061,7 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
                            st, (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
-                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.p.nomega, pl.zx, pl.zy, ff,
+                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff,
                        pl.ff_s, pl.ffx, pl.ffy, vkind, U, re, imr, rer, pl.out_nx, pl.out_ny);
     return hipGetLastError();
 }
@@ -2037,9 +2081,9 @@ static hipError_t sqw_t(const Plan &pl, double kT, const T *im, T *s, hipStream_
     const size_t n = vec ? plane / VEC : plane;
     const dim3 grid((unsigned)std::min<size_t>(cdiv(n, kThreads), 4096), pl.p.nomega);
     if (vec)
-        hipLaunchKernelGGL((k_sqw<T, VEC>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.deps, kT, plane);
+        hipLaunchKernelGGL((k_sqw<T, VEC>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.d_frac, pl.deps, kT, plane);
     else
-        hipLaunchKernelGGL((k_sqw<T, 1>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.deps, kT, plane);
+        hipLaunchKernelGGL((k_sqw<T, 1>), grid, dim3(kThreads), 0, st, im, s, pl.d_lag, pl.d_frac, pl.deps, kT, plane);
     return hipGetLastError();
 }
 

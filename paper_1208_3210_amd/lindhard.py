@@ -58,6 +58,7 @@ class Problem(ctypes.Structure):
         ("ff_kind", ctypes.c_int32), ("ff_width", ctypes.c_double),
         ("precision", ctypes.c_int32), ("want_rpa", ctypes.c_int32),
         ("k_zones", ctypes.c_int32), ("rho_table", ctypes.POINTER(ctypes.c_double)),
+        ("omega_interp", ctypes.c_int32),
     ]
 
 
@@ -152,7 +153,7 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
                  eps_table: Optional[np.ndarray] = None, mu: float = float("nan"), filling: float = 1.0,
                  zones: tuple = (1, 1), ff_kind: int = LINDHARD_FF_NONE, ff_width: float = 0.0,
                  precision: int = LINDHARD_FP32C, want_rpa: bool = False, k_zones: int = 1,
-                 rho_table: Optional[np.ndarray] = None):
+                 rho_table: Optional[np.ndarray] = None, omega_interp: bool = False):
     """Fill a Problem; returns (problem, keepalive) -- keep `keepalive` until the call."""
     om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
     keep = [om]
@@ -171,6 +172,7 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
     p.ff_kind, p.ff_width = int(ff_kind), float(ff_width)
     p.precision, p.want_rpa = int(precision), int(bool(want_rpa))
     p.k_zones = int(k_zones)
+    p.omega_interp = int(bool(omega_interp))
     if rho_table is not None:
         rt = np.ascontiguousarray(np.asarray(rho_table, dtype=np.float64))
         keep.append(rt)
