@@ -177,7 +177,8 @@ def bench_epilogues(LH, W, torch, reps=3):
     energies, 5x5 zones, orbital form factor, 128 omegas, FP32): Kramers-
     Kronig + contact RPA, Coulomb RPA, S(q, omega), the peak search and the
     q-average, each timed with events on the launch stream against its
-    algorithmic HBM bytes."""
+    algorithmic HBM bytes; then the cuts (high-symmetry path, zone envelope
+    with its fit) and omegas between lag-grid points."""
     cfg = W.config2()
     plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
     im = plan.exec()
@@ -215,6 +216,28 @@ def bench_epilogues(LH, W, torch, reps=3):
         ms = e0.elapsed_time(e1) / reps
         out[name] = {"ms": ms, "alg_GB": nbytes / 1e9, "GB/s": nbytes / (ms * 1e-3) / 1e9,
                      "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    # cuts: the high-symmetry path of every plane (a gather), and the zone
+    # envelope with its Lorentzian fit of one plane (synchronous, host clock)
+    X, Y = plan.high_symmetry_path()
+    cut_out = torch.empty((plan.shape[0], X.size), dtype=im.dtype, device="cuda")
+    cut = lambda: LH.lindhard_cut(h, im.data_ptr(), X, Y, cut_out.data_ptr(), sp())  # noqa: E731
+    cut()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cut()
+    e1.record()
+    torch.cuda.synchronize()
+    out["high_symmetry_cut"] = {"ms": e0.elapsed_time(e1) / reps, "points": int(X.size),
+                                "note": "includes the host-to-device copy of the path indices"}
+    plan.zone_envelope(im, 0, 0, 1.0)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        env = plan.zone_envelope(im, len(cfg["omega"]) // 2, 0, 1.0 / 7.46)
+    out["zone_envelope"] = {"ms_host": (time.perf_counter() - t0) * 1e3 / reps, "k0_au": env["k0"],
+                            "segments": int(env["X"].size), "note": "one plane, [100], synchronous call"}
     plan.close()
     # omegas between lag-grid points: the row-transform pass reads two lag
     # slices per output plane and blends them (the other passes are unchanged)

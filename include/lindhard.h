@@ -185,6 +185,59 @@ lindhard_status lindhard_q_average(lindhard_plan_t plan, const void *im, double 
  * Asynchronous on `stream`.  Errors: EINVAL (NULL), EDEVICE. */
 lindhard_status lindhard_peak_index(lindhard_plan_t plan, const void *im, int32_t *peak, void *stream);
 
+/* Cut through the output planes along a path (Fig. 2(a): -Im chi along the
+ * high-symmetry lines as a function of omega): out[w][p] = im[w][Y[p]][X[p]]
+ * for every plane w and path point p.  X, Y: host arrays of npts extended-grid
+ * indices (0 <= X < out_nx, 0 <= Y < out_ny; read during the call); out:
+ * device, nomega * npts elements of the plan's precision; `im` as for
+ * lindhard_structure_factor.  Asynchronous on `stream` (the indices are staged
+ * in plan memory: calls on one plan must not overlap).  Errors: EINVAL (NULL,
+ * npts < 1, an index off the grid), ENOMEM, EDEVICE. */
+lindhard_status lindhard_cut(lindhard_plan_t plan, const void *im, const int32_t *X, const int32_t *Y, int32_t npts,
+                             void *out, void *stream);
+
+/* The high-symmetry path Gamma -> X -> M -> Gamma of the central zone on the
+ * extended grid (Gamma = (out_nx/2, out_ny/2), X = (pi, 0), M = (pi, pi)), one
+ * point per grid step: 3 W / 2 + 1 points for a zone W = nkx / k_zones steps
+ * wide (nkx == nky required; the zone boundary wraps to the opposite edge
+ * when the grid holds one zone).  Host only:
+ * writes at most `capacity` points to X, Y and the count to *npts.  Errors:
+ * EINVAL (NULL, nkx != nky or not a multiple of 2 k_zones, capacity too
+ * small; *npts still gets the count). */
+lindhard_status lindhard_high_symmetry_path(lindhard_plan_t plan, int32_t *X, int32_t *Y, int32_t capacity,
+                                            int32_t *npts);
+
+#define LINDHARD_ENVELOPE_MAX 64
+
+typedef struct {
+    double k0;      /* fitted decay momentum of 1 / (1 + (q/k0)^2), in q_scale units */
+    double c_max;   /* largest -Im chi along the cut (the normalisation) */
+    int32_t nseg;   /* envelope points: the central half zone, then one per zone */
+    int32_t X[LINDHARD_ENVELOPE_MAX], Y[LINDHARD_ENVELOPE_MAX]; /* point of each maximum */
+    double q[LINDHARD_ENVELOPE_MAX]; /* its |q| in q_scale units */
+    double y[LINDHARD_ENVELOPE_MAX]; /* its -Im chi / c_max */
+} lindhard_envelope;
+
+/* Zone-to-zone decay along a cut from the extended-grid centre (Fig. 5):
+ * plane `omega_index` of `im` is followed along [100] (direction 0: Y = out_ny/2,
+ * X >= out_nx/2) or [110] (direction 1, nkx == nky); the central half zone and
+ * each further zone crossed give one envelope point, the largest -Im chi in
+ * that segment (first on ties, decided in the plan's precision), normalised by
+ * the largest of them; the Lorentzian 1 / (1 + (q/k0)^2) is then fitted to
+ * these points by least squares in u = 1/k0^2 over [1e-8, 1e8] (a log-spaced
+ * scan, then bisection of dF/du; a minimum at the range end returns that end).
+ * q = |Q| q_scale with Q = 2 pi (h, l) in units of 1/a, so q_scale = 1/a gives
+ * q in the inverse units of a (e.g. atomic units for a in bohr).  A zone is
+ * nkx / k_zones grid steps wide; segments: (zones + 1) / 2 along the cut, with
+ * zones = k_zones zones_x for [100] and k_zones min(zones_x, zones_y) for
+ * [110] (a half zone left at the grid edge is not used), at most
+ * LINDHARD_ENVELOPE_MAX.  Synchronous: returns when `out` is
+ * filled.  Errors: EINVAL (NULL, bad index or direction, q_scale <= 0, too
+ * many zones, nkx != nky for [110], nkx not a multiple of 2 k_zones),
+ * EDEVICE. */
+lindhard_status lindhard_zone_envelope(lindhard_plan_t plan, const void *im, int32_t omega_index, int32_t direction,
+                                       double q_scale, lindhard_envelope *out, void *stream);
+
 /* Run n independent plans as one batch ordered on `stream`: the instances
  * are forked onto a pool of worker streams (largest first, round-robin) so
  * that instances of mixed grid sizes overlap on the device, and joined back

@@ -403,3 +403,82 @@ def kk_real_interp(im_all: np.ndarray, m, f) -> np.ndarray:
     lo = kk_real(im_all, m)
     hi = kk_real(im_all, m + 1)
     return np.where(f > 0.0, (1.0 - f) * lo + f * hi, lo)
+
+
+# --------------------------------------------------------------------------
+# Cuts through the extended maps (Fig. 2(a) and Fig. 5)
+# --------------------------------------------------------------------------
+def high_symmetry_path(nk: int, zx: int, zy: int, kzones: int = 1):
+    """Extended-grid indices of Gamma -> X -> M -> Gamma in the central zone,
+    one point per grid step (the central zone is nk / kzones steps wide;
+    indices wrap on a one-zone grid, where the zone boundary is the grid edge)."""
+    W = nk // kzones
+    nx, ny = zx * nk, zy * nk
+    gx, gy = nx // 2, ny // 2
+    pts = [(gx + s, gy) for s in range(W // 2)]                       # Gamma -> X
+    pts += [(gx + W // 2, gy + s) for s in range(W // 2)]             # X -> M
+    pts += [(gx + W // 2 - s, gy + W // 2 - s) for s in range(W // 2 + 1)]  # M -> Gamma
+    X = np.array([p[0] % nx for p in pts], dtype=np.int32)
+    Y = np.array([p[1] % ny for p in pts], dtype=np.int32)
+    return X, Y
+
+
+def envelope_fit(q, y, ulo: float = 1e-8, uhi: float = 1e8, nscan: int = 200001):
+    """Least-squares k0 of y ~ 1 / (1 + (q/k0)^2) (the envelope model of
+    Fig. 5): minimise F(u) = sum (y - 1/(1 + q^2 u))^2 over u = 1/k0^2 in
+    [ulo, uhi] -- a dense log-spaced scan, then the root of dF/du inside the
+    best scan cell (brentq); a minimum at the range end returns that end."""
+    from scipy.optimize import brentq
+    q = np.asarray(q, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+
+    def F(u):
+        u = np.asarray(u, dtype=np.float64)
+        g = 1.0 / (1.0 + q[:, None] ** 2 * u[None, :])
+        return ((y[:, None] - g) ** 2).sum(axis=0)
+
+    def dF(u):
+        g = 1.0 / (1.0 + q ** 2 * u)
+        return 2.0 * float(np.sum((y - g) * q ** 2 * g * g))
+
+    s = np.linspace(np.log(ulo), np.log(uhi), nscan)
+    f = F(np.exp(s))
+    i = int(np.argmin(f))
+    a, b = s[max(i - 1, 0)], s[min(i + 1, nscan - 1)]
+    sx = s[i]
+    if dF(np.exp(a)) < 0.0 < dF(np.exp(b)):
+        sx = brentq(lambda t: dF(np.exp(t)), a, b, xtol=1e-15, rtol=1e-15, maxiter=500)
+    return float(np.exp(-0.5 * sx))
+
+
+def zone_envelope(plane, nk: int, zx: int, zy: int, direction: int, q_scale: float, kzones: int = 1):
+    """Envelope of one extended map ``plane`` [Y][X] of Im chi along [100]
+    (direction 0) or [110] (1) from the grid centre: the central half zone and
+    every further zone crossed give the point of largest -Im chi (the first
+    on ties), normalised by the largest of them, at |q| = |Q| q_scale with
+    Q = 2 pi (h, l); then ``envelope_fit``.  Returns a dict (k0, c_max, X, Y,
+    q, y)."""
+    plane = np.asarray(plane)
+    W = nk // kzones
+    zones = (zx if direction == 0 else min(zx, zy)) * kzones
+    nseg = (zones + 1) // 2
+    gx, gy = plane.shape[1] // 2, plane.shape[0] // 2
+    Xs, Ys, cs, ss = [], [], [], []
+    for k in range(nseg):
+        lo = 0 if k == 0 else W // 2 + (k - 1) * W
+        hi = W // 2 if k == 0 else lo + W
+        best, bs = None, None
+        for s in range(lo, hi):
+            X, Y = gx + s, (gy + s if direction else gy)
+            c = -plane[Y, X]
+            if best is None or c > best:
+                best, bs = c, s
+        Xs.append(gx + bs)
+        Ys.append(gy + bs if direction else gy)
+        cs.append(float(best))
+        ss.append(bs)
+    cmax = max(cs)
+    y = np.array(cs) / cmax
+    step = 2.0 * np.pi / W * (np.sqrt(2.0) if direction else 1.0)
+    q = np.array(ss, dtype=np.float64) * step * q_scale
+    return {"k0": envelope_fit(q, y), "c_max": cmax, "X": np.array(Xs), "Y": np.array(Ys), "q": q, "y": y}

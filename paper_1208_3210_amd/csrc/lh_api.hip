@@ -743,6 +743,8 @@ struct lindhard_plan_s {
     Plan pl;
     hipStream_t setup = nullptr;
     hipEvent_t done = nullptr;  // recorded after each exec / rpa
+    int32_t *d_cut = nullptr;   // staged (X, Y) pairs of lindhard_cut (owned by pl.allocs)
+    size_t cut_cap = 0;
 };
 
 // One setup stream per host thread and device, kept for the life of the
@@ -952,6 +954,105 @@ lindhard_status lindhard_peak_index(lindhard_plan_t plan, const void *im, int32_
     if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
     if (dev != plan->pl.device) (void)hipSetDevice(dev);
     return e == hipSuccess ? LINDHARD_OK : LINDHARD_EDEVICE;
+}
+
+lindhard_status lindhard_cut(lindhard_plan_t plan, const void *im, const int32_t *X, const int32_t *Y, int32_t npts,
+                             void *out, void *stream)
+{
+    if (!plan || !im || !X || !Y || !out || npts < 1) return LINDHARD_EINVAL;
+    Plan &pl = plan->pl;
+    std::vector<int32_t> xy((size_t)2 * npts);
+    for (int32_t p = 0; p < npts; ++p) {
+        if (X[p] < 0 || X[p] >= pl.out_nx || Y[p] < 0 || Y[p] >= pl.out_ny) return LINDHARD_EINVAL;
+        xy[2 * p] = X[p];
+        xy[2 * p + 1] = Y[p];
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != pl.device && hipSetDevice(pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    lindhard_status st = LINDHARD_OK;
+    if ((size_t)npts > plan->cut_cap) {
+        void *p = nullptr;
+        st = dalloc(pl, &p, (size_t)2 * npts * sizeof(int32_t));
+        if (st == LINDHARD_OK) {
+            plan->d_cut = (int32_t *)p;
+            plan->cut_cap = (size_t)npts;
+        }
+    }
+    if (st == LINDHARD_OK) {
+        hipError_t e = hipMemcpyAsync(plan->d_cut, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      (hipStream_t)stream);
+        if (e == hipSuccess) e = launch_cut(pl, im, plan->d_cut, npts, out, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipEventRecord(plan->done, (hipStream_t)stream);
+        if (e != hipSuccess) st = LINDHARD_EDEVICE;
+    }
+    if (dev != pl.device) (void)hipSetDevice(dev);
+    return st;
+}
+
+lindhard_status lindhard_high_symmetry_path(lindhard_plan_t plan, int32_t *X, int32_t *Y, int32_t capacity,
+                                            int32_t *npts)
+{
+    if (!plan || !X || !Y || !npts) return LINDHARD_EINVAL;
+    const Plan &pl = plan->pl;
+    const int kz = std::max(1, pl.p.k_zones);
+    if (pl.g.nkx != pl.g.nky || pl.g.nkx % (2 * kz)) return LINDHARD_EINVAL;
+    const int h = pl.g.nkx / kz / 2, Xc = pl.out_nx / 2, Yc = pl.out_ny / 2;
+    const int n = 3 * h + 1;
+    *npts = n;
+    if (capacity < n) return LINDHARD_EINVAL;
+    int p = 0;
+    auto put = [&](int x, int y) {
+        X[p] = x % pl.out_nx;
+        Y[p] = y % pl.out_ny;
+        ++p;
+    };
+    for (int s = 0; s < h; ++s) put(Xc + s, Yc);          // Gamma -> X
+    for (int s = 0; s < h; ++s) put(Xc + h, Yc + s);      // X -> M
+    for (int s = 0; s <= h; ++s) put(Xc + h - s, Yc + h - s);  // M -> Gamma
+    return LINDHARD_OK;
+}
+
+lindhard_status lindhard_zone_envelope(lindhard_plan_t plan, const void *im, int32_t omega_index, int32_t direction,
+                                       double q_scale, lindhard_envelope *out, void *stream)
+{
+    if (!plan || !im || !out) return LINDHARD_EINVAL;
+    const Plan &pl = plan->pl;
+    if (omega_index < 0 || omega_index >= pl.p.nomega || (direction != 0 && direction != 1)) return LINDHARD_EINVAL;
+    if (!(q_scale > 0.0) || !std::isfinite(q_scale)) return LINDHARD_EINVAL;
+    if (direction == 1 && pl.g.nkx != pl.g.nky) return LINDHARD_EINVAL;
+    // zone width W grid steps: the whole k-grid, or 1/k_zones of it
+    const int kz = std::max(1, pl.p.k_zones);
+    if (pl.g.nkx % (2 * kz)) return LINDHARD_EINVAL;
+    const int W = pl.g.nkx / kz;
+    const int zones = (direction == 0 ? pl.zx : std::min(pl.zx, pl.zy)) * kz;
+    const int nseg = (zones + 1) / 2;
+    if (nseg > LINDHARD_ENVELOPE_MAX) return LINDHARD_EINVAL;
+    const double qstep = 2.0 * M_PI / W * (direction ? std::sqrt(2.0) : 1.0) * q_scale;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINDHARD_EDEVICE;
+    if (dev != pl.device && hipSetDevice(pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    const hipStream_t st = (hipStream_t)stream;
+    const void *plane = (const char *)im + (size_t)omega_index * pl.out_nx * pl.out_ny * pl.elem_bytes;
+    std::vector<double> res(3 + 4 * (size_t)nseg);
+    static_assert(3 + 4 * LINDHARD_ENVELOPE_MAX <= 2 * kOccBlocks + 2, "envelope results fit the scratch");
+    hipError_t e = launch_envelope(pl, plane, direction, W, nseg, qstep, pl.scratch, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(res.data(), pl.scratch, res.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (dev != pl.device) (void)hipSetDevice(dev);
+    if (e != hipSuccess) return LINDHARD_EDEVICE;
+    *out = lindhard_envelope{};
+    out->k0 = res[0];
+    out->c_max = res[1];
+    out->nseg = nseg;
+    for (int k = 0; k < nseg; ++k) {
+        out->X[k] = (int32_t)res[3 + 4 * k];
+        out->Y[k] = (int32_t)res[4 + 4 * k];
+        out->q[k] = res[5 + 4 * k];
+        out->y[k] = res[6 + 4 * k];
+    }
+    return LINDHARD_OK;
 }
 
 // Batched execution: the instances are spread over a small pool of worker

@@ -130,6 +130,10 @@ hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStr
 hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st);
 hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t st);
 hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
+hipError_t launch_cut(const Plan &pl, const void *im, const int *xy, int npts, void *out, hipStream_t st);
+// res: 3 + 4 * nseg doubles of device memory; im_plane: the plane to cut
+hipError_t launch_envelope(const Plan &pl, const void *im_plane, int dir, int W, int nseg, double qstep, double *res,
+                           hipStream_t st);
 
 // Setup kernels.
 hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st);

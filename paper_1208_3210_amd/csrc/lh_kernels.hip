@@ -1685,6 +1685,154 @@ __global__ void __launch_bounds__(kThreads) k_peak(const T *__restrict__ im, int
     idx[p] = bw;
 }
 
+// ---------------------------------------------------------------- cuts
+// Every output plane at caller-chosen extended points (a path such as the
+// high-symmetry lines of Fig. 2(a)): out[w][p] = im[w][Y_p][X_p], with xy the
+// (X, Y) pairs (checked against the grid on the host).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_cut(const T *__restrict__ im, size_t plane, int out_nx,
+                                                 const int *__restrict__ xy, int npts, T *__restrict__ out)
+{
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    const int w = blockIdx.y;
+    if (p >= npts) return;
+    out[(size_t)w * npts + p] = im[(size_t)w * plane + (size_t)xy[2 * p + 1] * out_nx + xy[2 * p]];
+}
+
+// Zone-by-zone envelope of one plane along a cut from the extended-grid
+// centre (Fig. 5): direction 0 runs along [100] (X = Xc + s, Y = Yc), 1 along
+// [110] (X = Xc + s, Y = Yc + s).  With zones nk grid steps wide, segment 0
+// is s in [0, nk/2) (the central zone up to its boundary) and segment k >= 1
+// is s in [nk/2 + (k-1) nk, nk/2 + k nk) (the k-th zone along the cut).  Each segment contributes the point of its
+// largest -Im chi (decided in the array's precision, the first on ties),
+// normalised by the largest of them; then the one-parameter Lorentzian
+// 1 / (1 + (q / k0)^2) is fitted by least squares over u = 1 / k0^2: a scan of
+// F(u) = sum_k (y_k - 1/(1 + q_k^2 u))^2 over kEnvScan log-spaced u in
+// [kEnvUlo, kEnvUhi], then bisection on dF/du inside the best scan cell.
+// res: [k0, c_max, nseg, then (X, Y, q, y) per segment]; one block.
+constexpr int kEnvScan = 4096;
+constexpr double kEnvUlo = 1e-8, kEnvUhi = 1e8;
+
+__device__ __forceinline__ double env_F(const double *q, const double *y, int n, double u)
+{
+    double f = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double r = y[k] - 1.0 / (1.0 + q[k] * q[k] * u);
+        f += r * r;
+    }
+    return f;
+}
+__device__ __forceinline__ double env_dF(const double *q, const double *y, int n, double u)
+{
+    double f = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double q2 = q[k] * q[k], g = 1.0 / (1.0 + q2 * u);
+        f += (y[k] - g) * q2 * g * g;
+    }
+    return 2.0 * f;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_envelope(const T *__restrict__ im, int out_nx, int Xc, int Yc, int nk,
+                                                      int dir, int nseg, double qstep, double *__restrict__ res)
+{
+    __shared__ T bv[kThreads];
+    __shared__ int bs[kThreads];
+    __shared__ double fv[kThreads];
+    __shared__ int fi[kThreads];
+    __shared__ double sq[LINDHARD_ENVELOPE_MAX], sy[LINDHARD_ENVELOPE_MAX];
+    __shared__ int ss[LINDHARD_ENVELOPE_MAX];
+    const int tid = threadIdx.x;
+    for (int k = 0; k < nseg; ++k) {
+        const int lo = k == 0 ? 0 : nk / 2 + (k - 1) * nk, hi = k == 0 ? nk / 2 : lo + nk;
+        T best = (T)0;
+        int bi = INT_MAX;
+        for (int s = lo + tid; s < hi; s += kThreads) {  // increasing s: ties keep the first
+            const T c = -im[(size_t)(dir ? Yc + s : Yc) * out_nx + Xc + s];
+            if (bi == INT_MAX || c > best) {
+                best = c;
+                bi = s;
+            }
+        }
+        bv[tid] = best;
+        bs[tid] = bi;
+        __syncthreads();
+        for (int o = kThreads / 2; o > 0; o >>= 1) {
+            if (tid < o) {
+                const T vo = bv[tid + o];
+                const int io = bs[tid + o];
+                if (io != INT_MAX && (bs[tid] == INT_MAX || vo > bv[tid] || (vo == bv[tid] && io < bs[tid]))) {
+                    bv[tid] = vo;
+                    bs[tid] = io;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            ss[k] = bs[0];
+            sy[k] = (double)bv[0];
+            sq[k] = qstep * (double)bs[0];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double cmax = sy[0];
+        for (int k = 1; k < nseg; ++k) cmax = sy[k] > cmax ? sy[k] : cmax;
+        for (int k = 0; k < nseg; ++k) sy[k] = sy[k] / cmax;
+        res[1] = cmax;
+        res[2] = (double)nseg;
+        for (int k = 0; k < nseg; ++k) {
+            res[3 + 4 * k] = (double)(Xc + ss[k]);
+            res[4 + 4 * k] = (double)(dir ? Yc + ss[k] : Yc);
+            res[5 + 4 * k] = sq[k];
+            res[6 + 4 * k] = sy[k];
+        }
+    }
+    __syncthreads();
+    // scan of F over log u
+    const double sl = log(kEnvUlo), sh = log(kEnvUhi), ds = (sh - sl) / (kEnvScan - 1);
+    double fb = 0.0;
+    int ib = INT_MAX;
+    for (int i = tid; i < kEnvScan; i += kThreads) {
+        const double f = env_F(sq, sy, nseg, exp(sl + i * ds));
+        if (ib == INT_MAX || f < fb) {
+            fb = f;
+            ib = i;
+        }
+    }
+    fv[tid] = fb;
+    fi[tid] = ib;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            const double vo = fv[tid + o];
+            const int io = fi[tid + o];
+            if (vo < fv[tid] || (vo == fv[tid] && io < fi[tid])) {
+                fv[tid] = vo;
+                fi[tid] = io;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int i = fi[0];
+        double a = sl + (i > 0 ? i - 1 : 0) * ds, b = sl + (i < kEnvScan - 1 ? i + 1 : i) * ds;
+        double sx = sl + i * ds;
+        if (env_dF(sq, sy, nseg, exp(a)) < 0.0 && env_dF(sq, sy, nseg, exp(b)) > 0.0) {
+            for (int it = 0; it < 200; ++it) {
+                const double m = 0.5 * (a + b);
+                if (m <= a || m >= b) break;
+                if (env_dF(sq, sy, nseg, exp(m)) < 0.0)
+                    a = m;
+                else
+                    b = m;
+            }
+            sx = 0.5 * (a + b);
+        }
+        res[0] = exp(-0.5 * sx);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
@@ -2114,6 +2262,32 @@ hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t
         hipLaunchKernelGGL(k_peak<double>, grid, dim3(kThreads), 0, st, (const double *)im, idx, plane, pl.p.nomega);
     else
         hipLaunchKernelGGL(k_peak<float>, grid, dim3(kThreads), 0, st, (const float *)im, idx, plane, pl.p.nomega);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut(const Plan &pl, const void *im, const int *xy, int npts, void *out, hipStream_t st)
+{
+    const size_t plane = (size_t)pl.out_nx * pl.out_ny;
+    const dim3 grid(cdiv(npts, kThreads), pl.p.nomega);
+    if (pl.g.fp64)
+        hipLaunchKernelGGL(k_cut<double>, grid, dim3(kThreads), 0, st, (const double *)im, plane, pl.out_nx, xy, npts,
+                           (double *)out);
+    else
+        hipLaunchKernelGGL(k_cut<float>, grid, dim3(kThreads), 0, st, (const float *)im, plane, pl.out_nx, xy, npts,
+                           (float *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_envelope(const Plan &pl, const void *im_plane, int dir, int W, int nseg, double qstep, double *res,
+                           hipStream_t st)
+{
+    const int Xc = pl.out_nx / 2, Yc = pl.out_ny / 2, nk = W;
+    if (pl.g.fp64)
+        hipLaunchKernelGGL(k_envelope<double>, dim3(1), dim3(kThreads), 0, st, (const double *)im_plane, pl.out_nx, Xc,
+                           Yc, nk, dir, nseg, qstep, res);
+    else
+        hipLaunchKernelGGL(k_envelope<float>, dim3(1), dim3(kThreads), 0, st, (const float *)im_plane, pl.out_nx, Xc,
+                           Yc, nk, dir, nseg, qstep, res);
     return hipGetLastError();
 }
 

@@ -86,10 +86,21 @@ class ServeStats(ctypes.Structure):
     ]
 
 
+ENVELOPE_MAX = 64
+
+
+class Envelope(ctypes.Structure):
+    _fields_ = [
+        ("k0", ctypes.c_double), ("c_max", ctypes.c_double), ("nseg", ctypes.c_int32),
+        ("X", ctypes.c_int32 * ENVELOPE_MAX), ("Y", ctypes.c_int32 * ENVELOPE_MAX),
+        ("q", ctypes.c_double * ENVELOPE_MAX), ("y", ctypes.c_double * ENVELOPE_MAX),
+    ]
+
+
 EXPORTS = [
     "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa",
     "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_q_average", "lindhard_peak_index",
-    "lindhard_exec_batch",
+    "lindhard_cut", "lindhard_high_symmetry_path", "lindhard_zone_envelope", "lindhard_exec_batch",
     "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
     "lindhard_serve_wait", "lindhard_serve_cancel", "lindhard_serve_stats_get", "lindhard_serve_destroy",
     "lindhard_strerror",
@@ -119,6 +130,11 @@ def lib() -> ctypes.CDLL:
             L.lindhard_structure_factor.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp]
             L.lindhard_peak_index.argtypes = [_vp, _vp, _vp, _vp]
             L.lindhard_q_average.argtypes = [_vp, _vp, _vp, _vp]
+            _i32p = ctypes.POINTER(ctypes.c_int32)
+            L.lindhard_cut.argtypes = [_vp, _vp, _i32p, _i32p, ctypes.c_int32, _vp, _vp]
+            L.lindhard_high_symmetry_path.argtypes = [_vp, _i32p, _i32p, ctypes.c_int32, _i32p]
+            L.lindhard_zone_envelope.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                                 ctypes.POINTER(Envelope), _vp]
             L.lindhard_exec_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp), _vp]
             L.lindhard_plan_destroy.argtypes = [_vp]
             L.lindhard_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(_vp)]
@@ -222,6 +238,40 @@ def lindhard_q_average(plan: int, im_ptr: int, out_ptr: int, stream_ptr: int) ->
     _check(lib().lindhard_q_average(_vp(plan), _vp(im_ptr), _vp(out_ptr), _vp(stream_ptr)), "lindhard_q_average")
 
 
+def _i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def lindhard_cut(plan: int, im_ptr: int, X: np.ndarray, Y: np.ndarray, out_ptr: int, stream_ptr: int) -> None:
+    X = np.ascontiguousarray(X, dtype=np.int32)
+    Y = np.ascontiguousarray(Y, dtype=np.int32)
+    if X.shape != Y.shape:
+        raise ValueError("X and Y differ in length")
+    _check(lib().lindhard_cut(_vp(plan), _vp(im_ptr), _i32(X), _i32(Y), int(X.size), _vp(out_ptr), _vp(stream_ptr)),
+           "lindhard_cut")
+
+
+def lindhard_high_symmetry_path(plan: int):
+    n = ctypes.c_int32(0)
+    dummy = np.zeros(1, dtype=np.int32)
+    st = lib().lindhard_high_symmetry_path(_vp(plan), _i32(dummy), _i32(dummy), 0, ctypes.byref(n))
+    if n.value <= 0:
+        _check(st, "lindhard_high_symmetry_path")
+    X = np.zeros(n.value, dtype=np.int32)
+    Y = np.zeros(n.value, dtype=np.int32)
+    _check(lib().lindhard_high_symmetry_path(_vp(plan), _i32(X), _i32(Y), n.value, ctypes.byref(n)),
+           "lindhard_high_symmetry_path")
+    return X, Y
+
+
+def lindhard_zone_envelope(plan: int, im_ptr: int, omega_index: int, direction: int, q_scale: float,
+                           stream_ptr: int) -> Envelope:
+    env = Envelope()
+    _check(lib().lindhard_zone_envelope(_vp(plan), _vp(im_ptr), int(omega_index), int(direction), float(q_scale),
+                                        ctypes.byref(env), _vp(stream_ptr)), "lindhard_zone_envelope")
+    return env
+
+
 def lindhard_peak_index(plan: int, im_ptr: int, peak_ptr: int, stream_ptr: int) -> None:
     _check(lib().lindhard_peak_index(_vp(plan), _vp(im_ptr), _vp(peak_ptr), _vp(stream_ptr)), "lindhard_peak_index")
 
@@ -305,6 +355,27 @@ class Plan:
         out = torch.empty(self.shape[1:], dtype=torch.int32, device="cuda")
         lindhard_peak_index(self.handle, im.data_ptr(), out.data_ptr(), _stream_ptr(stream))
         return out
+
+    def cut(self, im: torch.Tensor, X, Y, stream=None) -> torch.Tensor:
+        """Every omega plane at the extended points (X[p], Y[p]): [nomega, npts]."""
+        assert im.is_cuda and im.dtype == self.dtype and tuple(im.shape) == self.shape and im.is_contiguous()
+        out = torch.empty((self.shape[0], len(X)), dtype=self.dtype, device="cuda")
+        lindhard_cut(self.handle, im.data_ptr(), X, Y, out.data_ptr(), _stream_ptr(stream))
+        return out
+
+    def high_symmetry_path(self):
+        """(X, Y) of the Gamma -> X -> M -> Gamma path of the central zone."""
+        return lindhard_high_symmetry_path(self.handle)
+
+    def zone_envelope(self, im: torch.Tensor, omega_index: int, direction: int = 0, q_scale: float = 1.0,
+                      stream=None) -> dict:
+        """Per-zone maxima of -Im chi along [100] (0) or [110] (1) from the
+        grid centre and the fitted decay momentum k0 of 1/(1 + (q/k0)^2)."""
+        assert im.is_cuda and im.dtype == self.dtype and tuple(im.shape) == self.shape and im.is_contiguous()
+        e = lindhard_zone_envelope(self.handle, im.data_ptr(), omega_index, direction, q_scale, _stream_ptr(stream))
+        n = e.nseg
+        return {"k0": e.k0, "c_max": e.c_max, "X": np.array(e.X[:n]), "Y": np.array(e.Y[:n]),
+                "q": np.array(e.q[:n]), "y": np.array(e.y[:n])}
 
     def close(self):
         if getattr(self, "handle", None):
