@@ -272,6 +272,28 @@ def bench_extended(LH, W, torch, steps=5):
     return res
 
 
+def bench_multiband(LH, W, torch, steps=3):
+    """Two bands on the 2048^2 x 512 x 256 FP32 instance: the summed spectral
+    function of Eq. (4) (one correlation, the row pass once per band) and the
+    band-pair sum of Eq. (2) (four weighted pairs: forward passes once per
+    band, then window, column and row inverse passes per pair)."""
+    res = {}
+    for form, pairs in (("summed", False), ("pairs", True)):
+        cfg = W.config_multiband(pairs=pairs)
+        plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+        out = plan.empty()
+        plan.exec_timed(out)
+        ms = [sum(plan.exec_timed(out)) for _ in range(steps)]
+        pts = cfg["nkx"] * cfg["nky"] * len(cfg["omega"])
+        res[form] = {"ms_per_step": float(np.mean(ms)), "points_per_s": pts / (float(np.mean(ms)) * 1e-3),
+                     "bands": 2, "pairs": int(np.count_nonzero(cfg["pair_weight"])) if pairs else 0,
+                     "schedule": plan.info.schedule.decode()}
+        plan.close()
+        del out
+    res["workload"] = "two seeded bands, 2048^2 k, 512 energies, 256 omegas, FP32"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +314,8 @@ def main():
                     help="skip the RPA / structure-factor / peak epilogues on the extended-zone workload")
     ap.add_argument("--no-extended", action="store_true",
                     help="skip the extended-momentum instance (16x16 zones, momentum density weights)")
+    ap.add_argument("--no-multiband", action="store_true",
+                    help="skip the two-band instances (summed spectral function, band-pair sum)")
     ap.add_argument("--epilogues-only", action="store_true",
                     help="only time the extended-zone epilogues (for profiling them on their own)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -428,6 +452,11 @@ def main():
     ext = None if args.no_extended else bench_extended(LH, W, torch)
     if ext:
         print("bench: extended momentum %.3f ms/step" % ext["ms_per_step"], file=sys.stderr, flush=True)
+    mb = None if args.no_multiband else bench_multiband(LH, W, torch)
+    if mb:
+        print("bench: two bands summed %.3f ms, pairs %.3f ms" % (mb["summed"]["ms_per_step"],
+                                                                 mb["pairs"]["ms_per_step"]), file=sys.stderr,
+              flush=True)
     epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
     if epi:
         print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
@@ -443,7 +472,7 @@ def main():
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
-        "epilogues": epi, "extended_momentum": ext,
+        "epilogues": epi, "extended_momentum": ext, "multiband": mb,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }

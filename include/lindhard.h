@@ -70,8 +70,8 @@ typedef enum {
 
 typedef struct {
     double t, tp, tpp;          /* eV, tight-binding hoppings (ignored if eps_table) */
-    const double *eps_table;    /* optional host table eps[iy][ix] (x fastest), eV;
-                                   read only during lindhard_plan */
+    const double *eps_table;    /* optional host table eps[iy][ix] (x fastest), eV
+                                   (n_bands planes); read only during lindhard_plan */
     double mu;                  /* eV; NaN = solve from `filling` */
     double filling;             /* electrons per site, both spins (1 + x) */
     double gamma;               /* Lorentzian half width of Eq. (5), eV, > 0 */
@@ -100,7 +100,21 @@ typedef struct {
      * values (Im chi, and Re chi from the Kramers-Kronig pass); values at lags
      * 0 and >= neps are 0.  Omegas within 1e-9 d of the grid are on it. */
     int32_t omega_interp;
+    /* Several bands (Eqs. (2), (4)).  n_bands in 1 .. LINDHARD_MAX_BANDS (0
+     * = 1); with more than one, eps_table is required and holds n_bands planes
+     * [band][iy][ix], rho_table (if given) as many, and mu / filling count the
+     * electrons of every band.  pair_weight NULL: the spectral function of
+     * Eq. (4) sums the bands, A = sum_n rho_n A_n, and one correlation is
+     * taken.  Otherwise a host array [nu][mu] of band-pair weights |M|^2 >= 0
+     * (Eq. (2), not all zero; the same at every Q, the orbital form factor
+     * ff_kind multiplying every pair): Im chi = sum w[nu][mu] chi_{nu,mu},
+     * with band nu occupied and band mu empty in chi_{nu,mu}.  Tables are
+     * read only during lindhard_plan. */
+    int32_t n_bands;
+    const double *pair_weight;
 } lindhard_problem;
+
+#define LINDHARD_MAX_BANDS 8
 
 typedef struct lindhard_plan_s *lindhard_plan_t;
 

@@ -73,6 +73,10 @@ def _load():
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_long, _ip, _ip, _ip, _dp]
             lib.oracle_chi_pairs_w.restype = ctypes.c_int
+            lib.oracle_chi_grid_mb.argtypes = [_dp, _dp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_int, _ip, _ip, ctypes.c_int, _ip, _dp]
+            lib.oracle_chi_grid_mb.restype = ctypes.c_int
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
@@ -482,3 +486,45 @@ def zone_envelope(plane, nk: int, zx: int, zy: int, direction: int, q_scale: flo
     step = 2.0 * np.pi / W * (np.sqrt(2.0) if direction else 1.0)
     q = np.array(ss, dtype=np.float64) * step * q_scale
     return {"k0": envelope_fit(q, y), "c_max": cmax, "X": np.array(Xs), "Y": np.array(Ys), "q": q, "y": y}
+
+
+# --------------------------------------------------------------------------
+# Several bands, Eqs. (2) and (4)
+# --------------------------------------------------------------------------
+def mu_solve_bands(eps_bands: np.ndarray, gamma: float, fill: float) -> float:
+    """Common chemical potential of nb bands: electrons per site summed over
+    the bands.  ``filling`` normalises by the number of values it is given, so
+    on all nb planes at once it returns the per-site count divided by nb."""
+    e = np.ascontiguousarray(eps_bands, dtype=np.float64)
+    return mu_solve(e.reshape(-1), gamma, fill / e.shape[0])
+
+
+def chi_grid_mb(xi_bands: np.ndarray, neps: int, emin: float, emax: float, gamma: float, qx, qy, ms,
+                rho=None, pair_weight=None) -> np.ndarray:
+    """Im chi_1BZ of several bands, xi_bands [band][iy][ix]: with no pair
+    weights the spectral function sums the bands (Eq. (4), rho_n on band n);
+    with weights w[nu][mu], sum w chi_{nu,mu} (Eq. (2)), band nu occupied and
+    band mu empty.  Shape (nq, nm)."""
+    x = np.ascontiguousarray(xi_bands, dtype=np.float64)
+    nb, nky, nkx = x.shape
+    r = None if rho is None else np.ascontiguousarray(np.asarray(rho, dtype=np.float64).reshape(x.shape))
+    pw = None if pair_weight is None else np.ascontiguousarray(np.asarray(pair_weight, dtype=np.float64).reshape(nb, nb))
+    qx = np.ascontiguousarray(qx, dtype=np.int32)
+    qy = np.ascontiguousarray(qy, dtype=np.int32)
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    out = np.empty((qx.size, ms.size), dtype=np.float64)
+    rc = _load().oracle_chi_grid_mb(_d(x), _d(r) if r is not None else None, nb, _d(pw) if pw is not None else None,
+                                    nkx, nky, int(neps), float(emin), float(emax), float(gamma), qx.size, _i(qx),
+                                    _i(qy), ms.size, _i(ms), _d(out))
+    if rc != 0:
+        raise RuntimeError("oracle_chi_grid_mb failed: %d" % rc)
+    return out
+
+
+def chi_full_mb(xi_bands: np.ndarray, neps: int, emin: float, emax: float, gamma: float, ms, rho=None,
+                pair_weight=None) -> np.ndarray:
+    """``chi_grid_mb`` on the whole q-grid, natural q order: (nm, nky, nkx)."""
+    _, nky, nkx = np.asarray(xi_bands).shape
+    qy, qx = np.meshgrid(np.arange(nky), np.arange(nkx), indexing="ij")
+    g = chi_grid_mb(xi_bands, neps, emin, emax, gamma, qx.ravel(), qy.ravel(), ms, rho, pair_weight)
+    return np.moveaxis(g.reshape(nky, nkx, -1), -1, 0)

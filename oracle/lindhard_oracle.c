@@ -282,6 +282,103 @@ int oracle_chi_pairs_w(const double *xi, const double *rho, int nkx, int nky, in
     return bad ? -3 : 0;
 }
 
+/* Several bands (Eqs. (2), (4)).  xi and rho (NULL = 1) hold nb planes
+ * [band][iy][ix]; the spectral function of band n at k is
+ * rho_n(k) A(e - xi_n(k)).
+ *   pairw == NULL: Eq. (4) sums the bands, A(k, e) = sum_n rho_n(k) A_n(k, e),
+ *                  and acc[im] = sum_k sum_j A(k, j) A(k+q, j+m);
+ *   otherwise:     Eq. (2), acc[im] = sum_{nu,mu} pairw[nu nb + mu]
+ *                  sum_k sum_j A_nu(k, j) A_mu(k+q, j+m)
+ * with j occupied and j + m empty as in chi_one_q.  ar, br: nb * neps. */
+static void chi_one_q_mb(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
+                         int neps, double emin, double d, int j0, double gamma, int qx, int qy, int nm,
+                         const int *ms, double *acc, double *ar, double *br, nsum *sums)
+{
+    int mmax = 0;
+    for (int im = 0; im < nm; ++im) {
+        sums[im].s = 0.0;
+        sums[im].c = 0.0;
+        if (ms[im] > mmax) mmax = ms[im];
+    }
+    int alo = j0 - mmax > 0 ? j0 - mmax : 0;
+    int bhi = j0 + mmax < neps ? j0 + mmax : neps;
+    int qxm = ((qx % nkx) + nkx) % nkx, qym = ((qy % nky) + nky) % nky;
+    size_t nk = (size_t)nkx * nky;
+    for (int iy = 0; iy < nky; ++iy) {
+        int iy2 = (iy + qym) % nky;
+        for (int ix = 0; ix < nkx; ++ix) {
+            int ix2 = (ix + qxm) % nkx;
+            size_t k1 = (size_t)iy * nkx + ix, k2 = (size_t)iy2 * nkx + ix2;
+            for (int n = 0; n < nb; ++n) {
+                double ra = rho ? rho[n * nk + k1] : 1.0, rb = rho ? rho[n * nk + k2] : 1.0;
+                for (int j = alo; j < j0; ++j)
+                    ar[(size_t)n * neps + j] = ra * lorentz(emin + (j + 0.5) * d, xi[n * nk + k1], gamma);
+                for (int j = j0; j < bhi; ++j)
+                    br[(size_t)n * neps + j] = rb * lorentz(emin + (j + 0.5) * d, xi[n * nk + k2], gamma);
+            }
+            if (!pairw) {  /* the summed spectral function goes into band slot 0 */
+                for (int j = alo; j < j0; ++j)
+                    for (int n = 1; n < nb; ++n) ar[j] += ar[(size_t)n * neps + j];
+                for (int j = j0; j < bhi; ++j)
+                    for (int n = 1; n < nb; ++n) br[j] += br[(size_t)n * neps + j];
+            }
+            for (int im = 0; im < nm; ++im) {
+                int m = ms[im];
+                int jlo = j0 - m > 0 ? j0 - m : 0;
+                int jhi = neps - m < j0 ? neps - m : j0;
+                if (jlo >= jhi) continue;
+                int np = pairw ? nb : 1;
+                for (int nu = 0; nu < np; ++nu)
+                    for (int mu = 0; mu < np; ++mu) {
+                        double w = pairw ? pairw[nu * nb + mu] : 1.0;
+                        if (w == 0.0) continue;
+                        nsum p = {0.0, 0.0};
+                        for (int j = jlo; j < jhi; ++j)
+                            nsum_add(&p, ar[(size_t)nu * neps + j] * br[(size_t)mu * neps + j + m]);
+                        nsum_add(&sums[im], w * nsum_get(&p));
+                    }
+            }
+        }
+    }
+    for (int im = 0; im < nm; ++im)
+        acc[im] = nsum_get(&sums[im]);
+}
+
+int oracle_chi_grid_mb(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
+                       int neps, double emin, double emax, double gamma, int nq, const int *qx, const int *qy,
+                       int nm, const int *ms, double *out)
+{
+    if (nb < 1 || nkx <= 0 || nky <= 0 || neps <= 0 || !(emax > emin) || !(gamma > 0)) return -1;
+    double d = (emax - emin) / neps;
+    int j0 = oracle_j0(neps, emin, emax);
+    double scale = -d / ((double)nkx * (double)nky);
+    int bad = 0;
+#pragma omp parallel
+    {
+        double *ar = (double *)malloc(sizeof(double) * (size_t)nb * neps);
+        double *br = (double *)malloc(sizeof(double) * (size_t)nb * neps);
+        double *acc = (double *)malloc(sizeof(double) * (size_t)(nm > 0 ? nm : 1));
+        nsum *sums = (nsum *)malloc(sizeof(nsum) * (size_t)(nm > 0 ? nm : 1));
+        if (!ar || !br || !acc || !sums) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int iq = 0; iq < nq; ++iq) {
+                chi_one_q_mb(xi, rho, nb, pairw, nkx, nky, neps, emin, d, j0, gamma, qx[iq], qy[iq], nm, ms, acc,
+                             ar, br, sums);
+                for (int im = 0; im < nm; ++im)
+                    out[(size_t)iq * nm + im] = scale * acc[im];
+            }
+        }
+        free(ar);
+        free(br);
+        free(acc);
+        free(sums);
+    }
+    return bad ? -3 : 0;
+}
+
 /* Threads the OpenMP runtime will use (for reporting the baseline's cores). */
 int oracle_num_threads(void)
 {

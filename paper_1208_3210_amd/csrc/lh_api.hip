@@ -92,23 +92,40 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         return LINDHARD_EINVAL;
     }
     const long nk = (long)p->nkx * p->nky;
+    const int nbands = p->n_bands < 1 ? 1 : p->n_bands;
+    if (p->n_bands < 0 || p->n_bands > LINDHARD_MAX_BANDS) return LINDHARD_EINVAL;
+    if (nbands > 1 && !p->eps_table) return LINDHARD_EINVAL;
+    const long nall = nk * nbands;
     if (p->eps_table) {
-        for (long k = 0; k < nk; ++k)
+        for (long k = 0; k < nall; ++k)
             if (!std::isfinite(p->eps_table[k])) return LINDHARD_EINVAL;
     } else if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->tpp)) {
         return LINDHARD_EINVAL;
     }
     if (p->k_zones < 0 || p->k_zones > 64) return LINDHARD_EINVAL;
     if (p->rho_table)
-        for (long k = 0; k < nk; ++k)
+        for (long k = 0; k < nall; ++k)
             if (!std::isfinite(p->rho_table[k])) return LINDHARD_EINVAL;
+    if (p->pair_weight) {
+        bool any = false;
+        for (int i = 0; i < nbands * nbands; ++i) {
+            if (!std::isfinite(p->pair_weight[i]) || p->pair_weight[i] < 0.0) return LINDHARD_EINVAL;
+            any = any || p->pair_weight[i] > 0.0;
+        }
+        if (!any) return LINDHARD_EINVAL;
+    }
 
     pl.p = *p;
     pl.p.omega = nullptr;
     pl.p.eps_table = nullptr;
     pl.p.rho_table = nullptr;
+    pl.p.pair_weight = nullptr;
     pl.p.k_zones = std::max(1, p->k_zones);
+    pl.p.n_bands = nbands;
     pl.has_rho = p->rho_table != nullptr;
+    pl.nb = nbands;
+    pl.pairs = p->pair_weight != nullptr;
+    if (pl.pairs) pl.pairw.assign(p->pair_weight, p->pair_weight + nbands * nbands);
     pl.omega.assign(p->omega, p->omega + p->nomega);
     pl.deps = (p->emax - p->emin) / p->neps;
     Geo &g = pl.g;
@@ -261,8 +278,10 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
                 }
             return true;
         };
-        if (p->eps_table) sym = mirror(p->eps_table);
-        if (sym && p->rho_table) sym = mirror(p->rho_table);
+        for (int b = 0; b < nbands && sym; ++b) {
+            if (p->eps_table) sym = mirror(p->eps_table + b * nk);
+            if (sym && p->rho_table) sym = mirror(p->rho_table + b * nk);
+        }
         if (const char *ev = std::getenv("LINDHARD_SYMMETRY"))
             if (!std::strcmp(ev, "off")) sym = false;
         g.even = sym ? 1 : 0;
@@ -347,8 +366,10 @@ size_t plan_footprint(const Plan &pl)
     const size_t nk = (size_t)g.nkx * g.nky;
     size_t b = 0;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    b += al(nk * 8);
-    if (pl.has_rho) b += al(nk * es);
+    b += al(nk * 8 * pl.nb);
+    if (pl.has_rho) b += al(nk * es * pl.nb);
+    if (pl.pairs && g.nL > 0)
+        b += al((size_t)pl.nb * g.nS * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
     b += al(g.nkx * cs) + al(g.nky * cs) + al(((size_t)1 << g.logNE) * cs);
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += al(pl.p.nomega * sizeof(PlaneSrc)) + al(pl.p.nomega * sizeof(int)) + al(pl.p.nomega * sizeof(double));
@@ -453,7 +474,7 @@ void plan_free(Plan &pl)
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
-                     &pl.rho};
+                     &pl.rho,              &pl.bspec};
     for (void **p : ptrs) *p = nullptr;
 }
 
@@ -714,8 +735,10 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
         s = dalloc(pl, (void **)&(ptr), (bytes));            \
         if (s != LINDHARD_OK) return s;                      \
     } while (0)
-    LH_ALLOC(pl.xi, nk * 8);
-    if (pl.has_rho) LH_ALLOC(pl.rho, nk * es);
+    LH_ALLOC(pl.xi, nk * 8 * pl.nb);
+    if (pl.has_rho) LH_ALLOC(pl.rho, nk * es * pl.nb);
+    if (pl.pairs && g.nL > 0)
+        LH_ALLOC(pl.bspec, (size_t)pl.nb * g.nS * (g.even ? g.slice_e * es : g.slice_elems * cs));
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
     LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
@@ -774,11 +797,12 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     if (s != LINDHARD_OK) return s;
     const size_t nk = (size_t)pl.g.nkx * pl.g.nky;
     double band_lo = 0.0, band_hi = 0.0;
+    const size_t nall = nk * pl.nb;
     if (p->eps_table) {
         // the caller's table is read during planning only
-        LH_TRY(hipMemcpyAsync(pl.xi, p->eps_table, nk * sizeof(double), hipMemcpyHostToDevice, st));
-        band_lo = *std::min_element(p->eps_table, p->eps_table + nk);
-        band_hi = *std::max_element(p->eps_table, p->eps_table + nk);
+        LH_TRY(hipMemcpyAsync(pl.xi, p->eps_table, nall * sizeof(double), hipMemcpyHostToDevice, st));
+        band_lo = *std::min_element(p->eps_table, p->eps_table + nall);
+        band_hi = *std::max_element(p->eps_table, p->eps_table + nall);
     } else {
         LH_TRY(launch_band(pl, nullptr, st));
         const double bnd = 4.0 * (std::fabs(p->t) + std::fabs(p->tp) + std::fabs(p->tpp));
@@ -789,10 +813,10 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     if (p->rho_table) {
         // momentum-density weights, rounded once to the plan's precision
         if (pl.g.fp64) {
-            LH_TRY(hipMemcpyAsync(pl.rho, p->rho_table, nk * sizeof(double), hipMemcpyHostToDevice, st));
+            LH_TRY(hipMemcpyAsync(pl.rho, p->rho_table, nall * sizeof(double), hipMemcpyHostToDevice, st));
         } else {
-            rho32.assign(p->rho_table, p->rho_table + nk);
-            LH_TRY(hipMemcpyAsync(pl.rho, rho32.data(), nk * sizeof(float), hipMemcpyHostToDevice, st));
+            rho32.assign(p->rho_table, p->rho_table + nall);
+            LH_TRY(hipMemcpyAsync(pl.rho, rho32.data(), nall * sizeof(float), hipMemcpyHostToDevice, st));
         }
     }
     if (std::isnan(p->mu)) {

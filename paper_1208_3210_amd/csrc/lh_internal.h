@@ -93,12 +93,16 @@ struct Plan {
     int zx = 1, zy = 1, out_nx = 0, out_ny = 0;
     size_t out_elems = 0, elem_bytes = 4;
     // device memory (owned)
-    double *xi = nullptr;      // eps(k) - mu, FP64, [nky][nkx]
+    double *xi = nullptr;      // eps(k) - mu, FP64, [band][nky][nkx]
     void *twx = nullptr;       // cx<T>[nkx]
     void *twy = nullptr;       // cx<T>[nky]
     void *twe = nullptr;       // cx<T>[2^logNE] (energy-axis FFT)
     bool has_rho = false;
-    void *rho = nullptr;       // momentum-density weights rho[iy][ix] in T (or none)
+    void *rho = nullptr;       // momentum-density weights rho[band][iy][ix] in T (or none)
+    int nb = 1;                // bands (xi and rho hold nb planes)
+    bool pairs = false;        // band-pair sum with weights pairw[nu * nb + mu] (else one summed band)
+    std::vector<double> pairw;
+    void *bspec = nullptr;     // pair sum: forward-transformed spectra of every band, nb x nS slices
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
     double2 *ffy = nullptr;    // per extended row
     PlaneSrc *d_src = nullptr; // per omega: window slots and weights

@@ -13,6 +13,8 @@
 // RPA path (Sec. 4): P5 keeps every lag of the first zone, then the
 // Kramers-Kronig and chi / (1 - U chi) epilogues.
 #include "lh_fft.h"
+#include <type_traits>
+
 #include "lh_internal.h"
 #include "lh_regfft.h"
 
@@ -193,7 +195,7 @@ __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2
 template <typename T, int LOGL, bool W>
 __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx,
-                                                cx<T> *__restrict__ spec, const T *__restrict__ rho)
+                                                cx<T> *__restrict__ spec, const T *__restrict__ rho, int acc)
 {
     using F = RegFFT<T, LOGL, false>;
     constexpr int L = F::N, E = F::E, G = F::G;
@@ -256,7 +258,8 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
                 const cx<T> w = twx[k];
                 X = cadd(Ev, cmul(mk<T>(w.y, -w.x), D));
             }
-            dst[((size_t)tile * g.nky + ky0 + r) * C + c] = X;
+            cx<T> *o = dst + ((size_t)tile * g.nky + ky0 + r) * C + c;
+            *o = acc ? cadd(*o, X) : X;  // acc: add this band to the earlier ones
         }
         __syncthreads();
     }
@@ -507,7 +510,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                                                 const cx<T> *__restrict__ twx, const PlaneSrc *__restrict__ psrc,
                                                 double scale, int zx, int zy, int ff, double ffs,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
-                                                T *__restrict__ out, int out_nx, int out_ny)
+                                                T *__restrict__ out, int out_nx, int out_ny, int acc)
 {
     using F = RegFFT<T, LOGL, true>;
     constexpr int L = F::N, E = F::E, G = F::G;
@@ -524,6 +527,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int nkx = g.nkx, nky = g.nky;
 
     if (MODE == 0 && slot < 0) {
+        if (acc) return;  // adds zero
         for (int rz = 0; rz < R * zy; ++rz) {
             const int r = rz % R, zi = rz / R;
             const int Y = zi * nky + ((qy0 + r + zy * nky / 2) & (nky - 1));
@@ -597,7 +601,8 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                         a = (T)((double)a * form_factor_sq(ffx[X], fy, ffs));
                         b = (T)((double)b * form_factor_sq(ffx[X + 1], fy, ffs));
                     }
-                    *reinterpret_cast<cx<T> *>(orow + X) = mk<T>(a, b);
+                    cx<T> *o = reinterpret_cast<cx<T> *>(orow + X);
+                    *o = acc ? cadd(*o, mk<T>(a, b)) : mk<T>(a, b);
                 }
             }
         }
@@ -607,7 +612,9 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const int u = 2 * (gg + s * G);
-            *reinterpret_cast<cx<T> *>(orow + u) = mk<T>(v[s].x * sc, v[s].y * sc);
+            cx<T> *o = reinterpret_cast<cx<T> *>(orow + u);
+            const cx<T> x = mk<T>(v[s].x * sc, v[s].y * sc);
+            *o = acc ? cadd(*o, x) : x;
         }
     }
 }
@@ -623,7 +630,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 template <typename T, int LOGNX, bool W>
 __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
-                                                const T *__restrict__ rho)
+                                                const T *__restrict__ rho, int acc)
 {
     using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -696,7 +703,15 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
                 const cx<T> z = zl[min(rx, H)];
                 o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
             }
-            *reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.Hy + ky) * Ce + h * VEC) = __builtin_bit_cast(lh_u4, o);
+            lh_u4 *op = reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.Hy + ky) * Ce + h * VEC);
+            if (acc) {  // add this band to the earlier ones
+                const Vec16<T> old = __builtin_bit_cast(Vec16<T>, *op);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) o.v[i] += old.v[i];
+                *op = __builtin_bit_cast(lh_u4, o);
+            } else {
+                *op = __builtin_bit_cast(lh_u4, o);
+            }
         }
         __syncthreads();
     }
@@ -1299,7 +1314,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
                                                 const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
-                                                int out_ny)
+                                                int out_ny, int acc)
 {
     using F = RegFFT<T, LOGNX, true>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -1317,6 +1332,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
 
     if (MODE == 0 && slot < 0) {
+        if (acc) return;  // adds zero
         for (int rz = 0; rz < rows * 2 * zy; ++rz) {
             const int r = rz % rows, mir = (rz / rows) & 1, zi = rz / (2 * rows);
             const int qy0 = 2 * p0 + r;
@@ -1394,28 +1410,46 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
         for (int mir = 0; mir < 2; ++mir) {
             const int qy = mir ? (nky - qy0) & (nky - 1) : qy0;
             if (mir && qy == qy0) continue;
-            if (MODE == 0) {
-                for (int zi = 0; zi < zy; ++zi) {
-                    const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
-                    T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
-                    const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
-                    for (int zj = 0; zj < zx; ++zj) {
+            // the stores, plain or added to the output (a separate copy each,
+            // so that the plain form never reads the output)
+            auto store = [&](auto add) {
+                constexpr bool A = decltype(add)::value;
+                if (MODE == 0) {
+                    for (int zi = 0; zi < zy; ++zi) {
+                        const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
+                        T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
+                        const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
+                        for (int zj = 0; zj < zx; ++zj) {
 #pragma unroll
-                        for (int s = 0; s < E; ++s) {
-                            const int qx = gg + s * G;
-                            const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
-                            T val = (half ? v[s].y : v[s].x) * sc;
-                            if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
-                            orow[X] = val;
+                            for (int s = 0; s < E; ++s) {
+                                const int qx = gg + s * G;
+                                const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
+                                T val = (half ? v[s].y : v[s].x) * sc;
+                                if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
+                                if constexpr (A)
+                                    orow[X] += val;
+                                else
+                                    orow[X] = val;
+                            }
                         }
                     }
-                }
-            } else {
-                const int m = g.m_lo + slot;
-                T *orow = out + ((size_t)m * nky + qy) * nkx;
+                } else {
+                    const int m = g.m_lo + slot;
+                    T *orow = out + ((size_t)m * nky + qy) * nkx;
 #pragma unroll
-                for (int s = 0; s < E; ++s) orow[gg + s * G] = (half ? v[s].y : v[s].x) * sc;
-            }
+                    for (int s = 0; s < E; ++s) {
+                        const T val = (half ? v[s].y : v[s].x) * sc;
+                        if constexpr (A)
+                            orow[gg + s * G] += val;
+                        else
+                            orow[gg + s * G] = val;
+                    }
+                }
+            };
+            if (acc)
+                store(std::true_type{});
+            else
+                store(std::false_type{});
         }
     }
 }
@@ -1846,19 +1880,21 @@ hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st)
     return hipGetLastError();
 }
 
+// Occupation of every band (electrons per site: the sum runs over all bands,
+// the normalisation over the k points of one).
 hipError_t launch_occ(const Plan &pl, double mu, double *d_out2, hipStream_t st)
 {
-    const long nk = (long)pl.g.nkx * pl.g.nky;
-    const int nb = (int)std::min<long>(kOccBlocks, cdiv(nk, kThreads));
-    hipLaunchKernelGGL(k_occ_partial, dim3(nb), dim3(kThreads), 0, st, pl.xi, nk, mu, pl.p.gamma, pl.scratch);
+    const long nk = (long)pl.g.nkx * pl.g.nky, nall = nk * pl.nb;
+    const int nb = (int)std::min<long>(kOccBlocks, cdiv(nall, kThreads));
+    hipLaunchKernelGGL(k_occ_partial, dim3(nb), dim3(kThreads), 0, st, pl.xi, nall, mu, pl.p.gamma, pl.scratch);
     hipLaunchKernelGGL(k_occ_final, dim3(1), dim3(kThreads), 0, st, pl.scratch, nb, nk, d_out2);
     return hipGetLastError();
 }
 
 hipError_t launch_xi_shift(const Plan &pl, double mu, hipStream_t st)
 {
-    const long nk = (long)pl.g.nkx * pl.g.nky;
-    hipLaunchKernelGGL(k_xi_shift, dim3(cdiv(nk, kThreads)), dim3(kThreads), 0, st, pl.xi, nk, mu);
+    const long nall = (long)pl.g.nkx * pl.g.nky * pl.nb;
+    hipLaunchKernelGGL(k_xi_shift, dim3(cdiv(nall, kThreads)), dim3(kThreads), 0, st, pl.xi, nall, mu);
     return hipGetLastError();
 }
 
@@ -1892,18 +1928,20 @@ hipError_t launch_tables(const Plan &pl, hipStream_t st)
 
 // Launch helpers with the transform length as a template parameter.
 template <typename T, int LOGL>
-static void launch_p1(const Plan &pl, cx<T> *spec, hipStream_t st)
+static void launch_p1(const Plan &pl, cx<T> *spec, int band, int acc, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, false>;
     const dim3 grid(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc));
     const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>);
+    const size_t nk = (size_t)g.nkx * g.nky;
+    const double *xi = pl.xi + band * nk;
     if (pl.rho)
-        hipLaunchKernelGGL((k_p1<T, LOGL, true>), grid, dim3(g.p1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
-                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho);
+        hipLaunchKernelGGL((k_p1<T, LOGL, true>), grid, dim3(g.p1_R * F::G), lds, st, xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho + band * nk, acc);
     else
-        hipLaunchKernelGGL((k_p1<T, LOGL, false>), grid, dim3(g.p1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
-                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr);
+        hipLaunchKernelGGL((k_p1<T, LOGL, false>), grid, dim3(g.p1_R * F::G), lds, st, xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr, acc);
 }
 
 template <typename T, int LOGN, bool INV>
@@ -1927,30 +1965,33 @@ static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
 }
 
 template <typename T, int LOGL, int MODE>
-static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, double w, int acc,
+                      hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
                        (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
-                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
+                       pl.scale * w, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony, acc);
 }
 
 template <typename T, int LOGNX>
-static void launch_e1(const Plan &pl, T *spec, hipStream_t st)
+static void launch_e1(const Plan &pl, T *spec, int band, int acc, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
     const int np = (g.Hy + 1) / 2;
     const dim3 grid(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc));
     const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);
+    const size_t nk = (size_t)g.nkx * g.nky;
+    const double *xi = pl.xi + band * nk;
     if (pl.rho)
-        hipLaunchKernelGGL((k_e1<T, LOGNX, true>), grid, dim3(g.e1_R * F::G), lds, st, pl.xi, g, pl.p.emin, pl.deps,
-                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho);
+        hipLaunchKernelGGL((k_e1<T, LOGNX, true>), grid, dim3(g.e1_R * F::G), lds, st, xi, g, pl.p.emin, pl.deps,
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho + band * nk, acc);
     else
-        hipLaunchKernelGGL((k_e1<T, LOGNX, false>), grid, dim3(g.e1_R * F::G), lds, st, pl.xi, g, pl.p.emin,
-                           pl.deps, pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr);
+        hipLaunchKernelGGL((k_e1<T, LOGNX, false>), grid, dim3(g.e1_R * F::G), lds, st, xi, g, pl.p.emin,
+                           pl.deps, pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr, acc);
 }
 
 template <typename T, int LOGN, bool INV>
@@ -1965,15 +2006,17 @@ static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
 }
 
 template <typename T, int LOGNX, int MODE>
-static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, double w, int acc,
+                      hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGNX, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
-                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
-                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
+                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g,
+                       (const cx<T> *)pl.twx, pl.d_src, pl.scale * w, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out,
+                       onx, ony, acc);
 }
 
 #define LH_SWITCH_LOG(v, CALL)                   \
@@ -1992,110 +2035,148 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     default: return hipErrorInvalidValue;        \
     }
 
-template <typename T>
-static hipError_t window_t(const Plan &pl, hipStream_t st);
-
-// ev (optional, 6 events): recorded before P1 and after P1, P2, P3, P4, P5.
-template <typename T>
-static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
-{
-    const Geo &g = pl.g;
-    cx<T> *spec = (cx<T> *)pl.spec;
-    const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
-    auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
-    };
-    mark(0);
-    if (g.even) {
-        T *spr = (T *)pl.spec;
-        if (g.nL > 0) {
-#define LH_E1(LG) launch_e1<T, LG>(pl, spr, st)
-            LH_SWITCH_LOG(g.logNx, LH_E1)
-#undef LH_E1
-            mark(1);
-#define LH_E2(LG) launch_ecol<T, LG, false>(pl, spr, g.nS, st)
-            LH_SWITCH_LOG(g.logNy, LH_E2)
-#undef LH_E2
-            mark(2);
-            {
-                const hipError_t e3 = window_t<T>(pl, st);
-                if (e3 != hipSuccess) return e3;
-            }
-            mark(3);
-#define LH_E4(LG) launch_ecol<T, LG, true>(pl, spr, g.nL, st)
-            LH_SWITCH_LOG(g.logNy, LH_E4)
-#undef LH_E4
-            mark(4);
-        } else {
-            mark(1);
-            mark(2);
-            mark(3);
-            mark(4);
-        }
-        if (pl.p.want_rpa) {
-            if (g.nL > 0) {
-#define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
-                LH_SWITCH_LOG(g.logNx, LH_E5)
-#undef LH_E5
-            }
-            hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads),
-                               0, st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s,
-                               pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
-        } else {
-#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
-            LH_SWITCH_LOG(g.logNx, LH_E5)
-#undef LH_E5
-        }
-        mark(5);
-        return hipGetLastError();
-    }
-    if (g.nL > 0) {
-#define LH_P1(LG) launch_p1<T, LG>(pl, spec, st)
-        LH_SWITCH_LOG(g.logL, LH_P1)
-#undef LH_P1
-        mark(1);
-#define LH_P2(LG) launch_col<T, LG, false>(pl, spec, g.nS, st)
-        LH_SWITCH_LOG(g.logNy, LH_P2)
-#undef LH_P2
-        mark(2);
-        {
-            const hipError_t e3 = window_t<T>(pl, st);
-            if (e3 != hipSuccess) return e3;
-        }
-        mark(3);
-#define LH_P4(LG) launch_col<T, LG, true>(pl, spec, g.nL, st)
-        LH_SWITCH_LOG(g.logNy, LH_P4)
-#undef LH_P4
-        mark(4);
-    } else {
-        mark(1);
-        mark(2);
-        mark(3);
-        mark(4);
-    }
-    if (pl.p.want_rpa) {
-        if (g.nL > 0) {
-#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
-            LH_SWITCH_LOG(g.logL, LH_P5)
-#undef LH_P5
-        }
-        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
-                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx,
-                           pl.ffy, out, pl.out_nx, pl.out_ny);
-    } else {
-#define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
-        LH_SWITCH_LOG(g.logL, LH_P5)
-#undef LH_P5
-    }
-    mark(5);
-    return hipGetLastError();
-}
-
 #define LH_HIP_TRY(x)                     \
     do {                                  \
         const hipError_t e_ = (x);        \
         if (e_ != hipSuccess) return e_;  \
     } while (0)
+
+template <typename T>
+static hipError_t window_t(const Plan &pl, hipStream_t st);
+
+// ev (optional, 6 events): recorded before P1 and after P1, P2, P3, P4, P5
+// (with a band-pair sum, after the forward passes of every band, then at the
+// end of the pair loop, which holds P3, P4 and P5 of every pair).
+template <typename T>
+static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
+{
+    const Geo &g = pl.g;
+    const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    const size_t sb = g.even ? g.slice_e * sizeof(T) : g.slice_elems * sizeof(cx<T>);  // bytes per slice
+    // P1 of one band into dst (acc: added to what dst holds)
+    auto p1 = [&](void *dst, int band, int acc) -> hipError_t {
+        if (g.even) {
+#define LH_E1(LG) launch_e1<T, LG>(pl, (T *)dst, band, acc, st)
+            LH_SWITCH_LOG(g.logNx, LH_E1)
+#undef LH_E1
+        } else {
+#define LH_P1(LG) launch_p1<T, LG>(pl, (cx<T> *)dst, band, acc, st)
+            LH_SWITCH_LOG(g.logL, LH_P1)
+#undef LH_P1
+        }
+        return hipGetLastError();
+    };
+    // forward (P2) or inverse (P4) column pass over n slices of buf
+    auto col = [&](void *buf, int n, bool inv) -> hipError_t {
+        if (g.even) {
+            if (inv) {
+#define LH_E4(LG) launch_ecol<T, LG, true>(pl, (T *)buf, n, st)
+                LH_SWITCH_LOG(g.logNy, LH_E4)
+#undef LH_E4
+            } else {
+#define LH_E2(LG) launch_ecol<T, LG, false>(pl, (T *)buf, n, st)
+                LH_SWITCH_LOG(g.logNy, LH_E2)
+#undef LH_E2
+            }
+        } else {
+            if (inv) {
+#define LH_P4(LG) launch_col<T, LG, true>(pl, (cx<T> *)buf, n, st)
+                LH_SWITCH_LOG(g.logNy, LH_P4)
+#undef LH_P4
+            } else {
+#define LH_P2(LG) launch_col<T, LG, false>(pl, (cx<T> *)buf, n, st)
+                LH_SWITCH_LOG(g.logNy, LH_P2)
+#undef LH_P2
+            }
+        }
+        return hipGetLastError();
+    };
+    // P5 from pl.spec, weighted by w (acc: added to the output)
+    auto p5 = [&](double w, int acc) -> hipError_t {
+        const bool rpa = pl.p.want_rpa != 0;
+        if (g.even) {
+            T *spr = (T *)pl.spec;
+            if (rpa) {
+#define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, w, acc, st)
+                LH_SWITCH_LOG(g.logNx, LH_E5)
+#undef LH_E5
+            } else {
+#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, w, acc, st)
+                LH_SWITCH_LOG(g.logNx, LH_E5)
+#undef LH_E5
+            }
+        } else {
+            const cx<T> *spec = (const cx<T> *)pl.spec;
+            if (rpa) {
+#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, w, acc, st)
+                LH_SWITCH_LOG(g.logL, LH_P5)
+#undef LH_P5
+            } else {
+#define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, w, acc, st)
+                LH_SWITCH_LOG(g.logL, LH_P5)
+#undef LH_P5
+            }
+        }
+        return hipGetLastError();
+    };
+    mark(0);
+    if (g.nL > 0 && !pl.pairs) {
+        for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(p1(pl.spec, b, b > 0));
+        mark(1);
+        LH_HIP_TRY(col(pl.spec, g.nS, false));
+        mark(2);
+        LH_HIP_TRY(window_t<T>(pl, st));
+        mark(3);
+        LH_HIP_TRY(col(pl.spec, g.nL, true));
+        mark(4);
+        LH_HIP_TRY(p5(1.0, 0));
+    } else if (g.nL > 0) {
+        // Eq. (2): sum over band pairs (nu occupied, mu empty).  The window
+        // pairs occupied slices (energies below j0) with empty ones only, so
+        // the cross term of (nu, mu) is the window of the spliced spectrum:
+        // the occupied slices of band nu followed by the empty ones of band mu.
+        const size_t nocc = (size_t)(g.j0 - g.jA), nb = (size_t)pl.nb;
+        char *bs = (char *)pl.bspec;
+        for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(p1(bs + b * g.nS * sb, b, 0));
+        mark(1);
+        for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(col(bs + b * g.nS * sb, g.nS, false));
+        mark(2);
+        int done = 0;
+        for (size_t nu = 0; nu < nb; ++nu) {
+            for (size_t mu = 0; mu < nb; ++mu) {
+                const double w = pl.pairw[nu * nb + mu];
+                if (w == 0.0) continue;
+                char *sp = (char *)pl.spec;
+                if (nocc > 0)
+                    LH_HIP_TRY(hipMemcpyAsync(sp, bs + nu * g.nS * sb, nocc * sb, hipMemcpyDeviceToDevice, st));
+                if ((size_t)g.nS > nocc)
+                    LH_HIP_TRY(hipMemcpyAsync(sp + nocc * sb, bs + (mu * g.nS + nocc) * sb, (g.nS - nocc) * sb,
+                                              hipMemcpyDeviceToDevice, st));
+                LH_HIP_TRY(window_t<T>(pl, st));
+                LH_HIP_TRY(col(pl.spec, g.nL, true));
+                LH_HIP_TRY(p5(w, done++ > 0));
+            }
+        }
+        mark(3);
+        mark(4);
+    } else {
+        mark(1);
+        mark(2);
+        mark(3);
+        mark(4);
+        if (!pl.p.want_rpa) LH_HIP_TRY(p5(1.0, 0));  // every plane is zero
+    }
+    if (pl.p.want_rpa)
+        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
+                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx,
+                           pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
+    mark(5);
+    return hipGetLastError();
+}
+
 
 // Persistent launch of the matrix-core window: as many blocks as fit on the
 // device at once (a multiple of 8, one share per XCD), each walking tiles.

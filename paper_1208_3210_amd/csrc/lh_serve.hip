@@ -31,7 +31,7 @@ using Clock = std::chrono::steady_clock;
 struct Job {
     uint64_t id = 0;
     lindhard_problem p{};
-    std::vector<double> omega, table, rho;
+    std::vector<double> omega, table, rho, pairw;
     double U = NAN;
     void *im = nullptr, *re = nullptr, *imr = nullptr, *rer = nullptr;
     size_t footprint = 0, points = 0;
@@ -67,6 +67,7 @@ static lindhard_status run_job(Job &j, hipStream_t st)
     p.omega = j.omega.data();
     p.eps_table = j.table.empty() ? nullptr : j.table.data();
     p.rho_table = j.rho.empty() ? nullptr : j.rho.data();
+    p.pair_weight = j.pairw.empty() ? nullptr : j.pairw.data();
     lindhard_plan_t plan = nullptr;
     lindhard_status s = lindhard_plan(&p, &plan);
     if (s != LINDHARD_OK) return s;
@@ -174,11 +175,15 @@ lindhard_status lindhard_serve_submit(lindhard_server_t S, const lindhard_proble
         }
     }
     job->omega.assign(p->omega, p->omega + p->nomega);
-    if (p->eps_table) job->table.assign(p->eps_table, p->eps_table + (size_t)p->nkx * p->nky);
-    if (p->rho_table) job->rho.assign(p->rho_table, p->rho_table + (size_t)p->nkx * p->nky);
+    const size_t nb = (size_t)(p->n_bands > 1 ? p->n_bands : 1);
+    const size_t nall = (size_t)p->nkx * p->nky * nb;
+    if (p->eps_table) job->table.assign(p->eps_table, p->eps_table + nall);
+    if (p->rho_table) job->rho.assign(p->rho_table, p->rho_table + nall);
+    if (p->pair_weight) job->pairw.assign(p->pair_weight, p->pair_weight + nb * nb);
     job->p.omega = nullptr;
     job->p.eps_table = nullptr;
     job->p.rho_table = nullptr;
+    job->p.pair_weight = nullptr;
     job->U = U_or_nan;
     job->im = im_chi;
     job->re = re_chi;

@@ -59,6 +59,7 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32), ("want_rpa", ctypes.c_int32),
         ("k_zones", ctypes.c_int32), ("rho_table", ctypes.POINTER(ctypes.c_double)),
         ("omega_interp", ctypes.c_int32),
+        ("n_bands", ctypes.c_int32), ("pair_weight", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -87,6 +88,7 @@ class ServeStats(ctypes.Structure):
 
 
 ENVELOPE_MAX = 64
+LINDHARD_MAX_BANDS = 8
 
 
 class Envelope(ctypes.Structure):
@@ -169,10 +171,16 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
                  eps_table: Optional[np.ndarray] = None, mu: float = float("nan"), filling: float = 1.0,
                  zones: tuple = (1, 1), ff_kind: int = LINDHARD_FF_NONE, ff_width: float = 0.0,
                  precision: int = LINDHARD_FP32C, want_rpa: bool = False, k_zones: int = 1,
-                 rho_table: Optional[np.ndarray] = None, omega_interp: bool = False):
+                 rho_table: Optional[np.ndarray] = None, omega_interp: bool = False, n_bands: int = 1,
+                 pair_weight: Optional[np.ndarray] = None):
     """Fill a Problem; returns (problem, keepalive) -- keep `keepalive` until the call."""
     om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
     keep = [om]
+    nb = max(1, int(n_bands))
+    for name, tab, n in (("eps_table", eps_table, nb * nkx * nky), ("rho_table", rho_table, nb * nkx * nky),
+                         ("pair_weight", pair_weight, nb * nb)):
+        if tab is not None and np.asarray(tab).size != n:
+            raise ValueError("%s holds %d values, %d expected" % (name, np.asarray(tab).size, n))
     p = Problem()
     p.t, p.tp, p.tpp = float(t), float(tp), float(tpp)
     if eps_table is not None:
@@ -189,6 +197,11 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
     p.precision, p.want_rpa = int(precision), int(bool(want_rpa))
     p.k_zones = int(k_zones)
     p.omega_interp = int(bool(omega_interp))
+    p.n_bands = int(n_bands)
+    if pair_weight is not None:
+        pw = np.ascontiguousarray(np.asarray(pair_weight, dtype=np.float64))
+        keep.append(pw)
+        p.pair_weight = pw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if rho_table is not None:
         rt = np.ascontiguousarray(np.asarray(rho_table, dtype=np.float64))
         keep.append(rt)

@@ -73,6 +73,47 @@ def momentum_density_dx2y2(nkx: int, nky: int, k_zones: int, w: float) -> np.nda
     return rho / rho.max()
 
 
+def multiband_tables(nk: int, nb: int = 2, seed: int = 20121208, k_zones: int = 1):
+    """Seeded synthetic bands for the multi-band forms: band n is
+    offset_n + sum_{a,b <= 2} c_nab cos(a px) cos(b py) with c_nab uniform in
+    [-0.25, 0.25] eV and offsets spread over [-0.3, 0.6] eV, on
+    p = 2 pi k_zones (ix, iy)/nk taken with folded indices (exactly mirror
+    symmetric).  Returns eps [nb][nk][nk]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    i = np.minimum(np.arange(nk), nk - np.arange(nk))
+    p = 2.0 * np.pi * k_zones * i / nk
+    eps = np.empty((nb, nk, nk))
+    for n in range(nb):
+        c = rng.uniform(-0.25, 0.25, size=(3, 3))
+        off = -0.3 + 0.9 * n / max(1, nb - 1)
+        cx = np.stack([np.cos(a * p) for a in range(3)])  # [a][ix]
+        eps[n] = off + np.einsum("ab,by,ax->yx", c, cx, cx)
+    return eps
+
+
+def density_s(nkx: int, nky: int, k_zones: int, w: float) -> np.ndarray:
+    """Momentum density of an s-like Gaussian orbital exp(-r^2/(2 w^2)):
+    exp(-w^2 |p|^2) on folded indices (exactly mirror symmetric), peak 1."""
+    ix = np.minimum(np.arange(nkx), nkx - np.arange(nkx))
+    iy = np.minimum(np.arange(nky), nky - np.arange(nky))
+    PX, PY = np.meshgrid(2.0 * np.pi * k_zones * ix / nkx, 2.0 * np.pi * k_zones * iy / nky)
+    return np.exp(-w * w * (PX * PX + PY * PY))
+
+
+def config_multiband(nk: int = 2048, neps: int = 512, pairs: bool = True) -> dict:
+    """Two-band instance (2048^2 k, 512 energies on [-2, 2] eV, G = 0.01 eV,
+    256 omegas, filling 1.15 over both bands): seeded bands of
+    ``multiband_tables``; with ``pairs`` the band-pair sum of Eq. (2) with
+    weights [[1, 0.5], [0.5, 1]], else the summed spectral function of Eq. (4)."""
+    emin, emax = -2.0, 2.0
+    cfg = dict(eps_table=multiband_tables(nk, 2), n_bands=2, filling=1.15, nkx=nk, nky=nk, neps=neps, emin=emin,
+               emax=emax, gamma=0.01, omega=lag_omegas(neps, emin, emax, range(1, neps // 2 + 1)), zones=(1, 1),
+               ff_kind=0, ff_width=0.0)
+    if pairs:
+        cfg["pair_weight"] = np.array([[1.0, 0.5], [0.5, 1.0]])
+    return cfg
+
+
 def config_extended(nk: int = 2048, k_zones: int = 16, neps: int = 512) -> dict:
     """Extended-momentum instance (the form the paper computes for its
     extended-zone maps): a 2048^2 momentum grid spanning 16 x 16 Brillouin
