@@ -294,6 +294,24 @@ def bench_multiband(LH, W, torch, steps=3):
     return res
 
 
+def bench_3d(LH, W, torch, steps=3):
+    """Three-dimensional k-grid with as many points as the main instance:
+    256 x 256 x 64 k, 512 energies, 256 omegas, FP32 (general complex path
+    with the kz transform pass)."""
+    cfg = W.config_3d()
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    out = plan.empty()
+    plan.exec_timed(out)
+    runs = [plan.exec_timed(out) for _ in range(steps)]
+    ms = float(np.mean([sum(r) for r in runs]))
+    pts = cfg["nkx"] * cfg["nky"] * cfg["nkz"] * len(cfg["omega"])
+    res = {"workload": "256x256x64 k (3D), 512 energies, 256 omegas, FP32", "ms_per_step": ms,
+           "points_per_s": pts / (ms * 1e-3), "passes_ms": [float(np.mean([r[i] for r in runs])) for i in range(5)],
+           "schedule": plan.info.schedule.decode()}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +332,7 @@ def main():
                     help="skip the RPA / structure-factor / peak epilogues on the extended-zone workload")
     ap.add_argument("--no-extended", action="store_true",
                     help="skip the extended-momentum instance (16x16 zones, momentum density weights)")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional k-grid instance")
     ap.add_argument("--no-multiband", action="store_true",
                     help="skip the two-band instances (summed spectral function, band-pair sum)")
     ap.add_argument("--epilogues-only", action="store_true",
@@ -457,6 +476,9 @@ def main():
         print("bench: two bands summed %.3f ms, pairs %.3f ms" % (mb["summed"]["ms_per_step"],
                                                                  mb["pairs"]["ms_per_step"]), file=sys.stderr,
               flush=True)
+    k3 = None if args.no_3d else bench_3d(LH, W, torch)
+    if k3:
+        print("bench: 3d %.3f ms/step" % k3["ms_per_step"], file=sys.stderr, flush=True)
     epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
     if epi:
         print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
@@ -472,7 +494,7 @@ def main():
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
-        "epilogues": epi, "extended_momentum": ext, "multiband": mb,
+        "epilogues": epi, "extended_momentum": ext, "multiband": mb, "k3d": k3,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }

@@ -112,6 +112,13 @@ typedef struct {
      * read only during lindhard_plan. */
     int32_t n_bands;
     const double *pair_weight;
+    /* Three-dimensional k-grids (the d^3p of Eq. (9)): nkz > 1 (a power of two
+     * up to 256; 0 or 1 = two dimensions) adds a third periodic axis.  It
+     * needs eps_table with nkz planes [band][iz][iy][ix] (rho_table alike), one
+     * zone (zones 1 x 1, k_zones <= 1), no orbital form factor and no RPA.
+     * The output planes are [omega][Z][Y][X] with Z = (qz + nkz/2) mod nkz,
+     * reported as out_ny = nkz * nky rows of out_nx = nkx. */
+    int32_t nkz;
 } lindhard_problem;
 
 #define LINDHARD_MAX_BANDS 8

@@ -77,6 +77,11 @@ def _load():
                                                ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                ctypes.c_int, _ip, _ip, ctypes.c_int, _ip, _dp]
             lib.oracle_chi_grid_mb.restype = ctypes.c_int
+            lib.oracle_chi_grid_3d.argtypes = [_dp, _dp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, _ip, _ip, _ip, ctypes.c_int, _ip,
+                                               _dp]
+            lib.oracle_chi_grid_3d.restype = ctypes.c_int
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = ctypes.c_int
             _lib = lib
@@ -528,3 +533,43 @@ def chi_full_mb(xi_bands: np.ndarray, neps: int, emin: float, emax: float, gamma
     qy, qx = np.meshgrid(np.arange(nky), np.arange(nkx), indexing="ij")
     g = chi_grid_mb(xi_bands, neps, emin, emax, gamma, qx.ravel(), qy.ravel(), ms, rho, pair_weight)
     return np.moveaxis(g.reshape(nky, nkx, -1), -1, 0)
+
+
+# --------------------------------------------------------------------------
+# Three-dimensional k-grids (the d^3p of Eq. (9))
+# --------------------------------------------------------------------------
+def chi_grid_3d(xi3: np.ndarray, neps: int, emin: float, emax: float, gamma: float, qx, qy, qz, ms,
+                rho=None, pair_weight=None) -> np.ndarray:
+    """Im chi on a 3D periodic k-grid, xi3 [band][iz][iy][ix] (or [iz][iy][ix]
+    for one band), bands as in ``chi_grid_mb``; shape (nq, nm)."""
+    x = np.asarray(xi3, dtype=np.float64)
+    if x.ndim == 3:
+        x = x[None]
+    x = np.ascontiguousarray(x)
+    nb, nkz, nky, nkx = x.shape
+    r = None if rho is None else np.ascontiguousarray(np.asarray(rho, dtype=np.float64).reshape(x.shape))
+    pw = None if pair_weight is None else np.ascontiguousarray(np.asarray(pair_weight, dtype=np.float64).reshape(nb, nb))
+    qx, qy, qz = (np.ascontiguousarray(a, dtype=np.int32) for a in (qx, qy, qz))
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    out = np.empty((qx.size, ms.size), dtype=np.float64)
+    rc = _load().oracle_chi_grid_3d(_d(x), _d(r) if r is not None else None, nb, _d(pw) if pw is not None else None,
+                                    nkx, nky, nkz, int(neps), float(emin), float(emax), float(gamma), qx.size,
+                                    _i(qx), _i(qy), _i(qz), ms.size, _i(ms), _d(out))
+    if rc != 0:
+        raise RuntimeError("oracle_chi_grid_3d failed: %d" % rc)
+    return out
+
+
+def chi_full_3d(xi3: np.ndarray, neps: int, emin: float, emax: float, gamma: float, ms, rho=None,
+                pair_weight=None) -> np.ndarray:
+    """``chi_grid_3d`` on the whole q-grid, natural order: (nm, nkz, nky, nkx)."""
+    sh = np.asarray(xi3).shape[-3:]
+    qz, qy, qx = np.meshgrid(*(np.arange(n) for n in sh), indexing="ij")
+    g = chi_grid_3d(xi3, neps, emin, emax, gamma, qx.ravel(), qy.ravel(), qz.ravel(), ms, rho, pair_weight)
+    return np.moveaxis(g.reshape(sh + (-1,)), -1, 0)
+
+
+def centre_3d(full: np.ndarray) -> np.ndarray:
+    """Natural q order -> the output order of the maps: index (q + n/2) mod n
+    on each of the last three axes."""
+    return np.roll(full, [n // 2 for n in full.shape[-3:]], axis=(-3, -2, -1))

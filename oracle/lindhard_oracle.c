@@ -291,8 +291,8 @@ int oracle_chi_pairs_w(const double *xi, const double *rho, int nkx, int nky, in
  *                  sum_k sum_j A_nu(k, j) A_mu(k+q, j+m)
  * with j occupied and j + m empty as in chi_one_q.  ar, br: nb * neps. */
 static void chi_one_q_mb(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
-                         int neps, double emin, double d, int j0, double gamma, int qx, int qy, int nm,
-                         const int *ms, double *acc, double *ar, double *br, nsum *sums)
+                         int nkz, int neps, double emin, double d, int j0, double gamma, int qx, int qy, int qz,
+                         int nm, const int *ms, double *acc, double *ar, double *br, nsum *sums)
 {
     int mmax = 0;
     for (int im = 0; im < nm; ++im) {
@@ -302,13 +302,14 @@ static void chi_one_q_mb(const double *xi, const double *rho, int nb, const doub
     }
     int alo = j0 - mmax > 0 ? j0 - mmax : 0;
     int bhi = j0 + mmax < neps ? j0 + mmax : neps;
-    int qxm = ((qx % nkx) + nkx) % nkx, qym = ((qy % nky) + nky) % nky;
-    size_t nk = (size_t)nkx * nky;
-    for (int iy = 0; iy < nky; ++iy) {
-        int iy2 = (iy + qym) % nky;
+    int qxm = ((qx % nkx) + nkx) % nkx, qym = ((qy % nky) + nky) % nky, qzm = ((qz % nkz) + nkz) % nkz;
+    size_t nk = (size_t)nkx * nky * nkz;
+    for (int izy = 0; izy < nkz * nky; ++izy) {  /* k = (iz, iy, ix), the kz planes one after another */
+        int iz = izy / nky, iy = izy % nky;
+        int iz2 = (iz + qzm) % nkz, iy2 = (iy + qym) % nky;
         for (int ix = 0; ix < nkx; ++ix) {
             int ix2 = (ix + qxm) % nkx;
-            size_t k1 = (size_t)iy * nkx + ix, k2 = (size_t)iy2 * nkx + ix2;
+            size_t k1 = ((size_t)iz * nky + iy) * nkx + ix, k2 = ((size_t)iz2 * nky + iy2) * nkx + ix2;
             for (int n = 0; n < nb; ++n) {
                 double ra = rho ? rho[n * nk + k1] : 1.0, rb = rho ? rho[n * nk + k2] : 1.0;
                 for (int j = alo; j < j0; ++j)
@@ -344,14 +345,16 @@ static void chi_one_q_mb(const double *xi, const double *rho, int nb, const doub
         acc[im] = nsum_get(&sums[im]);
 }
 
-int oracle_chi_grid_mb(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
-                       int neps, double emin, double emax, double gamma, int nq, const int *qx, const int *qy,
-                       int nm, const int *ms, double *out)
+/* Three-dimensional k-grid [iz][iy][ix] (the d^3p of Eq. (9)) with several
+ * bands as above; q = (qx, qy, qz); per-site normalisation over nkx nky nkz. */
+int oracle_chi_grid_3d(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
+                       int nkz, int neps, double emin, double emax, double gamma, int nq, const int *qx,
+                       const int *qy, const int *qz, int nm, const int *ms, double *out)
 {
-    if (nb < 1 || nkx <= 0 || nky <= 0 || neps <= 0 || !(emax > emin) || !(gamma > 0)) return -1;
+    if (nb < 1 || nkx <= 0 || nky <= 0 || nkz <= 0 || neps <= 0 || !(emax > emin) || !(gamma > 0)) return -1;
     double d = (emax - emin) / neps;
     int j0 = oracle_j0(neps, emin, emax);
-    double scale = -d / ((double)nkx * (double)nky);
+    double scale = -d / ((double)nkx * (double)nky * (double)nkz);
     int bad = 0;
 #pragma omp parallel
     {
@@ -365,8 +368,8 @@ int oracle_chi_grid_mb(const double *xi, const double *rho, int nb, const double
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int iq = 0; iq < nq; ++iq) {
-                chi_one_q_mb(xi, rho, nb, pairw, nkx, nky, neps, emin, d, j0, gamma, qx[iq], qy[iq], nm, ms, acc,
-                             ar, br, sums);
+                chi_one_q_mb(xi, rho, nb, pairw, nkx, nky, nkz, neps, emin, d, j0, gamma, qx[iq], qy[iq],
+                             qz ? qz[iq] : 0, nm, ms, acc, ar, br, sums);
                 for (int im = 0; im < nm; ++im)
                     out[(size_t)iq * nm + im] = scale * acc[im];
             }
@@ -377,6 +380,14 @@ int oracle_chi_grid_mb(const double *xi, const double *rho, int nb, const double
         free(sums);
     }
     return bad ? -3 : 0;
+}
+
+int oracle_chi_grid_mb(const double *xi, const double *rho, int nb, const double *pairw, int nkx, int nky,
+                       int neps, double emin, double emax, double gamma, int nq, const int *qx, const int *qy,
+                       int nm, const int *ms, double *out)
+{
+    return oracle_chi_grid_3d(xi, rho, nb, pairw, nkx, nky, 1, neps, emin, emax, gamma, nq, qx, qy, NULL, nm, ms,
+                              out);
 }
 
 /* Threads the OpenMP runtime will use (for reporting the baseline's cores). */

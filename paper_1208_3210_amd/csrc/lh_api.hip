@@ -91,7 +91,12 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     } else if (!std::isfinite(p->mu)) {
         return LINDHARD_EINVAL;
     }
-    const long nk = (long)p->nkx * p->nky;
+    const int nkz = p->nkz < 1 ? 1 : p->nkz;
+    if (p->nkz < 0 || p->nkz > 256 || !is_pow2(nkz)) return LINDHARD_EINVAL;
+    if (nkz > 1 && (!p->eps_table || p->zones_x != 1 || p->zones_y != 1 || p->k_zones > 1 ||
+                    p->ff_kind != LINDHARD_FF_NONE || p->want_rpa))
+        return LINDHARD_EINVAL;
+    const long nk = (long)p->nkx * p->nky * nkz;
     const int nbands = p->n_bands < 1 ? 1 : p->n_bands;
     if (p->n_bands < 0 || p->n_bands > LINDHARD_MAX_BANDS) return LINDHARD_EINVAL;
     if (nbands > 1 && !p->eps_table) return LINDHARD_EINVAL;
@@ -122,6 +127,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.p.pair_weight = nullptr;
     pl.p.k_zones = std::max(1, p->k_zones);
     pl.p.n_bands = nbands;
+    pl.p.nkz = nkz;
     pl.has_rho = p->rho_table != nullptr;
     pl.nb = nbands;
     pl.pairs = p->pair_weight != nullptr;
@@ -188,7 +194,10 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.jA = g.jB = g.nS = 0;
     }
     g.nslots = std::max(g.nS, g.nL);
-    g.slice_elems = (size_t)g.NT * g.nky * g.C;
+    g.nkz = nkz;
+    g.logNz = ilog2(nkz);
+    g.plane_elems = (size_t)g.NT * g.nky * g.C;
+    g.slice_elems = g.plane_elems * nkz;
     pl.src.resize(p->nomega);
     for (int w = 0; w < p->nomega; ++w) {
         auto slot_of = [&](int m) { return (g.nL > 0 && m >= g.m_lo && m <= g.m_hi) ? m - g.m_lo : -1; };
@@ -278,6 +287,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
                 }
             return true;
         };
+        if (nkz > 1) sym = false;  // the real even form is two-dimensional
         for (int b = 0; b < nbands && sym; ++b) {
             if (p->eps_table) sym = mirror(p->eps_table + b * nk);
             if (sym && p->rho_table) sym = mirror(p->rho_table + b * nk);
@@ -343,7 +353,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.zx = p->zones_x;
     pl.zy = p->zones_y;
     pl.out_nx = p->zones_x * p->nkx;
-    pl.out_ny = p->zones_y * p->nky;
+    pl.out_ny = p->zones_y * p->nky * nkz;  // three dimensions: nkz blocks of nky rows
     pl.out_elems = (size_t)p->nomega * pl.out_nx * pl.out_ny;
     pl.elem_bytes = g.fp64 ? 8 : 4;
     pl.scale = -pl.deps / ((double)nk * (double)nk);
@@ -363,14 +373,14 @@ size_t plan_footprint(const Plan &pl)
 {
     const Geo &g = pl.g;
     const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
-    const size_t nk = (size_t)g.nkx * g.nky;
+    const size_t nk = (size_t)g.nkx * g.nky * g.nkz;
     size_t b = 0;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     b += al(nk * 8 * pl.nb);
     if (pl.has_rho) b += al(nk * es * pl.nb);
     if (pl.pairs && g.nL > 0)
         b += al((size_t)pl.nb * g.nS * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
-    b += al(g.nkx * cs) + al(g.nky * cs) + al(((size_t)1 << g.logNE) * cs);
+    b += al(g.nkx * cs) + al(g.nky * cs) + al(g.nkz * cs) + al(((size_t)1 << g.logNE) * cs);
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += al(pl.p.nomega * sizeof(PlaneSrc)) + al(pl.p.nomega * sizeof(int)) + al(pl.p.nomega * sizeof(double));
     b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
@@ -471,7 +481,7 @@ void plan_free(Plan &pl)
 {
     for (auto &a : pl.allocs) pool_free(a.first, a.second, pl.device);
     pl.allocs.clear();
-    void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twe, (void **)&pl.ffx,
+    void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twz, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
                      &pl.rho,              &pl.bspec};
@@ -525,8 +535,8 @@ std::string tune_key(const Geo &g)
         for (int TR = 32; TR >= 4 && !maxfit_m; TR >>= 1)
             if (even_mfma_lds(g, TR) <= 65536) maxfit_m = TR;
     const char *ev = g.even ? std::getenv("LINDHARD_EVEN_WINDOW") : nullptr;
-    std::snprintf(b, sizeof b, "w4 %d %d %d %d %d %d %d %d %d %d %s", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0,
-                  g.m_lo, (g.m_hi + 31) / 32, maxfit, maxfit_m, ev ? ev : "auto");
+    std::snprintf(b, sizeof b, "w4 %d %d %d %d %d %d %d %d %d %d %s z%d", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0,
+                  g.m_lo, (g.m_hi + 31) / 32, maxfit, maxfit_m, ev ? ev : "auto", g.nkz);
     return b;
 }
 
@@ -728,7 +738,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
 {
     const Geo &g = pl.g;
     const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
-    const size_t nk = (size_t)g.nkx * g.nky;
+    const size_t nk = (size_t)g.nkx * g.nky * g.nkz;
     lindhard_status s;
 #define LH_ALLOC(ptr, bytes)                                 \
     do {                                                     \
@@ -741,6 +751,7 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
         LH_ALLOC(pl.bspec, (size_t)pl.nb * g.nS * (g.even ? g.slice_e * es : g.slice_elems * cs));
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
+    LH_ALLOC(pl.twz, g.nkz * cs);
     LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
     LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
     LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
@@ -795,7 +806,7 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     hipStream_t st = o->setup;
     s = plan_build(pl, st);
     if (s != LINDHARD_OK) return s;
-    const size_t nk = (size_t)pl.g.nkx * pl.g.nky;
+    const size_t nk = (size_t)pl.g.nkx * pl.g.nky * pl.g.nkz;
     double band_lo = 0.0, band_hi = 0.0;
     const size_t nall = nk * pl.nb;
     if (p->eps_table) {
@@ -1020,7 +1031,7 @@ lindhard_status lindhard_high_symmetry_path(lindhard_plan_t plan, int32_t *X, in
     if (!plan || !X || !Y || !npts) return LINDHARD_EINVAL;
     const Plan &pl = plan->pl;
     const int kz = std::max(1, pl.p.k_zones);
-    if (pl.g.nkx != pl.g.nky || pl.g.nkx % (2 * kz)) return LINDHARD_EINVAL;
+    if (pl.g.nkz > 1 || pl.g.nkx != pl.g.nky || pl.g.nkx % (2 * kz)) return LINDHARD_EINVAL;
     const int h = pl.g.nkx / kz / 2, Xc = pl.out_nx / 2, Yc = pl.out_ny / 2;
     const int n = 3 * h + 1;
     *npts = n;
@@ -1045,6 +1056,7 @@ lindhard_status lindhard_zone_envelope(lindhard_plan_t plan, const void *im, int
     if (omega_index < 0 || omega_index >= pl.p.nomega || (direction != 0 && direction != 1)) return LINDHARD_EINVAL;
     if (!(q_scale > 0.0) || !std::isfinite(q_scale)) return LINDHARD_EINVAL;
     if (direction == 1 && pl.g.nkx != pl.g.nky) return LINDHARD_EINVAL;
+    if (pl.g.nkz > 1) return LINDHARD_EINVAL;
     // zone width W grid steps: the whole k-grid, or 1/k_zones of it
     const int kz = std::max(1, pl.p.k_zones);
     if (pl.g.nkx % (2 * kz)) return LINDHARD_EINVAL;

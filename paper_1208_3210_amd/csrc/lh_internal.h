@@ -33,13 +33,15 @@ struct Geo {
     int nkx, nky, logNx, logNy;
     int L, logL;        // row transform length nkx / 2
     int C, logC, NT;    // tile width (complex values) and tile count
+    int nkz, logNz;     // third axis (1, 0 in two dimensions)
+    size_t plane_elems; // NT * nky * C: one kz plane of a slice (general path)
     int neps;
     int jA, jB;         // slices that can enter the window: [jA, jB)
     int nS;             // jB - jA
     int j0;             // occupied points (global index)
     int m_lo, m_hi, nL; // lag range of the window pass; nL = 0: nothing to do
     int nslots;         // slices allocated in the spectral array
-    size_t slice_elems; // NT * nky * C
+    size_t slice_elems; // NT * nky * C * nkz
     // launch shapes
     int p1_R, p1_logR, p1_jc;
     int p3_RY, p3_logRY, p3_TR, p3_logTR;
@@ -96,6 +98,7 @@ struct Plan {
     double *xi = nullptr;      // eps(k) - mu, FP64, [band][nky][nkx]
     void *twx = nullptr;       // cx<T>[nkx]
     void *twy = nullptr;       // cx<T>[nky]
+    void *twz = nullptr;       // cx<T>[nkz] (three dimensions)
     void *twe = nullptr;       // cx<T>[2^logNE] (energy-axis FFT)
     bool has_rho = false;
     void *rho = nullptr;       // momentum-density weights rho[band][iy][ix] in T (or none)

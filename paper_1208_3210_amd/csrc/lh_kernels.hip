@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, co
     const int tid = threadIdx.x;
     const int line = tid % NL, gg = tid / NL;
     const int tb = line / C, c = line % C;
-    const int tile = blockIdx.x * TPB + tb;
-    const bool active = tile < g.NT;
+    const int tile = blockIdx.x * TPB + tb;  // tiles of every kz plane (three dimensions)
+    const bool active = tile < g.NT * g.nkz;
     cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)(active ? tile : 0) * N * C;
     cx<T> v[E];
 #pragma unroll
@@ -294,6 +294,35 @@ __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, co
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) base[(gg + s * G) * C + c] = v[s];
+    }
+}
+
+// Third-axis pass (three-dimensional grids): each line runs along kz through
+// the planes of one slice (stride plane_elems); the lines are the (tile, ky,
+// c) positions of a plane, C consecutive c per group so that the loads of a
+// wave cover whole 32-byte tile rows.  Transformed in place.
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(512) k_zcol(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twz)
+{
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int N = F::N, E = F::E, G = F::G;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
+    constexpr int NL = TPB * C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int line = tid % NL, gg = tid / NL;
+    const int grp = blockIdx.x * TPB + line / C, c = line % C;
+    const bool active = grp < g.NT * g.nky;
+    cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)(active ? grp : 0) * C + c;
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) v[s] = active ? base[(size_t)(gg + s * G) * g.plane_elems] : mk<T>((T)0, (T)0);
+    F::run(v, lds + line * N, twz, 0, gg, lds_xor_interleaved<T, N>(line, NL));
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) base[(size_t)(gg + s * G) * g.plane_elems] = v[s];
     }
 }
 
@@ -1884,7 +1913,7 @@ hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st)
 // the normalisation over the k points of one).
 hipError_t launch_occ(const Plan &pl, double mu, double *d_out2, hipStream_t st)
 {
-    const long nk = (long)pl.g.nkx * pl.g.nky, nall = nk * pl.nb;
+    const long nk = (long)pl.g.nkx * pl.g.nky * pl.g.nkz, nall = nk * pl.nb;
     const int nb = (int)std::min<long>(kOccBlocks, cdiv(nall, kThreads));
     hipLaunchKernelGGL(k_occ_partial, dim3(nb), dim3(kThreads), 0, st, pl.xi, nall, mu, pl.p.gamma, pl.scratch);
     hipLaunchKernelGGL(k_occ_final, dim3(1), dim3(kThreads), 0, st, pl.scratch, nb, nk, d_out2);
@@ -1893,7 +1922,7 @@ hipError_t launch_occ(const Plan &pl, double mu, double *d_out2, hipStream_t st)
 
 hipError_t launch_xi_shift(const Plan &pl, double mu, hipStream_t st)
 {
-    const long nall = (long)pl.g.nkx * pl.g.nky * pl.nb;
+    const long nall = (long)pl.g.nkx * pl.g.nky * pl.g.nkz * pl.nb;
     hipLaunchKernelGGL(k_xi_shift, dim3(cdiv(nall, kThreads)), dim3(kThreads), 0, st, pl.xi, nall, mu);
     return hipGetLastError();
 }
@@ -1904,6 +1933,7 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
     const Geo &g = pl.g;
     hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(g.nkx, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twx, g.nkx);
     hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(g.nky, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twy, g.nky);
+    hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(g.nkz, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twz, g.nkz);
     hipLaunchKernelGGL(k_twiddle<T>, dim3(cdiv(1 << g.logNE, kThreads)), dim3(kThreads), 0, st, (cx<T> *)pl.twe,
                        1 << g.logNE);
     if (pl.p.ff_kind != LINDHARD_FF_NONE) {
@@ -1928,17 +1958,18 @@ hipError_t launch_tables(const Plan &pl, hipStream_t st)
 
 // Launch helpers with the transform length as a template parameter.
 template <typename T, int LOGL>
-static void launch_p1(const Plan &pl, cx<T> *spec, int band, int acc, hipStream_t st)
+static void launch_p1(const Plan &pl, cx<T> *spec, int band, int z, int acc, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, false>;
     const dim3 grid(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc));
     const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>);
-    const size_t nk = (size_t)g.nkx * g.nky;
-    const double *xi = pl.xi + band * nk;
+    // band `band`, kz plane z of the table; the plane's spectrum at spec
+    const size_t nk = (size_t)g.nkx * g.nky * g.nkz, off = band * nk + (size_t)z * g.nkx * g.nky;
+    const double *xi = pl.xi + off;
     if (pl.rho)
         hipLaunchKernelGGL((k_p1<T, LOGL, true>), grid, dim3(g.p1_R * F::G), lds, st, xi, g, pl.p.emin, pl.deps,
-                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho + band * nk, acc);
+                           pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)pl.rho + off, acc);
     else
         hipLaunchKernelGGL((k_p1<T, LOGL, false>), grid, dim3(g.p1_R * F::G), lds, st, xi, g, pl.p.emin, pl.deps,
                            pl.p.gamma, (const cx<T> *)pl.twx, spec, (const T *)nullptr, acc);
@@ -1951,8 +1982,19 @@ static void launch_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st)
     using F = RegFFT<T, LOGN, INV>;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
-    hipLaunchKernelGGL((k_col<T, LOGN, INV>), dim3(cdiv(g.NT, TPB), nslices), dim3(F::G * TPB * C),
+    hipLaunchKernelGGL((k_col<T, LOGN, INV>), dim3(cdiv(g.NT * g.nkz, TPB), nslices), dim3(F::G * TPB * C),
                        (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twy);
+}
+
+template <typename T, int LOGN, bool INV>
+static void launch_zcol(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGN, INV>;
+    constexpr int C = sizeof(T) == 4 ? 4 : 2;
+    constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
+    hipLaunchKernelGGL((k_zcol<T, LOGN, INV>), dim3(cdiv((long)g.NT * g.nky, TPB), nslices), dim3(F::G * TPB * C),
+                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twz);
 }
 
 template <typename T, int LOGN>
@@ -1960,7 +2002,7 @@ static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGN, false>;
-    hipLaunchKernelGGL((k_p3f<T, LOGN>), dim3(g.NT, g.nky / (g.p3f_TR >> g.logC)), dim3(g.p3f_TR * F::G),
+    hipLaunchKernelGGL((k_p3f<T, LOGN>), dim3(g.NT * g.nkz, g.nky / (g.p3f_TR >> g.logC)), dim3(g.p3f_TR * F::G),
                        (size_t)g.p3f_TR * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twe);
 }
 
@@ -2063,9 +2105,12 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
             LH_SWITCH_LOG(g.logNx, LH_E1)
 #undef LH_E1
         } else {
-#define LH_P1(LG) launch_p1<T, LG>(pl, (cx<T> *)dst, band, acc, st)
-            LH_SWITCH_LOG(g.logL, LH_P1)
+            for (int z = 0; z < g.nkz; ++z) {
+                cx<T> *pz = (cx<T> *)dst + (size_t)z * g.plane_elems;
+#define LH_P1(LG) launch_p1<T, LG>(pl, pz, band, z, acc, st)
+                LH_SWITCH_LOG(g.logL, LH_P1)
 #undef LH_P1
+            }
         }
         return hipGetLastError();
     };
@@ -2083,6 +2128,11 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
             }
         } else {
             if (inv) {
+                if (g.nkz > 1) {
+#define LH_PZ(LG) launch_zcol<T, LG, true>(pl, (cx<T> *)buf, n, st)
+                    LH_SWITCH_LOG(g.logNz, LH_PZ)
+#undef LH_PZ
+                }
 #define LH_P4(LG) launch_col<T, LG, true>(pl, (cx<T> *)buf, n, st)
                 LH_SWITCH_LOG(g.logNy, LH_P4)
 #undef LH_P4
@@ -2090,6 +2140,11 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 #define LH_P2(LG) launch_col<T, LG, false>(pl, (cx<T> *)buf, n, st)
                 LH_SWITCH_LOG(g.logNy, LH_P2)
 #undef LH_P2
+                if (g.nkz > 1) {
+#define LH_PZ(LG) launch_zcol<T, LG, false>(pl, (cx<T> *)buf, n, st)
+                    LH_SWITCH_LOG(g.logNz, LH_PZ)
+#undef LH_PZ
+                }
             }
         }
         return hipGetLastError();
@@ -2115,9 +2170,14 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
                 LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
             } else {
-#define LH_P5(LG) launch_p5<T, LG, 0>(pl, spec, pl.p.nomega, out, pl.out_nx, pl.out_ny, w, acc, st)
-                LH_SWITCH_LOG(g.logL, LH_P5)
+                // kz plane z of the spectrum -> output rows of Z = (z + nkz/2) mod nkz
+                for (int z = 0; z < g.nkz; ++z) {
+                    const cx<T> *sz = spec + (size_t)z * g.plane_elems;
+                    T *oz = out + (size_t)((z + g.nkz / 2) & (g.nkz - 1)) * g.nky * pl.out_nx;
+#define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, w, acc, st)
+                    LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
+                }
             }
         }
         return hipGetLastError();
@@ -2255,10 +2315,10 @@ static hipError_t window_t(const Plan &pl, hipStream_t st)
         LH_SWITCH_LOG(g.logNE, LH_P3F)
 #undef LH_P3F
     } else if (g.fp64) {
-        hipLaunchKernelGGL((k_p3<T, false>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
+        hipLaunchKernelGGL((k_p3<T, false>), dim3(g.NT * g.nkz, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
                            st, spec, g);
     } else {
-        hipLaunchKernelGGL((k_p3<T, true>), dim3(g.NT, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
+        hipLaunchKernelGGL((k_p3<T, true>), dim3(g.NT * g.nkz, g.nky / g.p3_RY), dim3(kThreads), (size_t)g.nS * g.p3_TR * cs,
                            st, spec, g);
     }
     return hipGetLastError();

@@ -176,7 +176,7 @@ lindhard_status lindhard_serve_submit(lindhard_server_t S, const lindhard_proble
     }
     job->omega.assign(p->omega, p->omega + p->nomega);
     const size_t nb = (size_t)(p->n_bands > 1 ? p->n_bands : 1);
-    const size_t nall = (size_t)p->nkx * p->nky * nb;
+    const size_t nall = (size_t)p->nkx * p->nky * (size_t)(p->nkz > 1 ? p->nkz : 1) * nb;
     if (p->eps_table) job->table.assign(p->eps_table, p->eps_table + nall);
     if (p->rho_table) job->rho.assign(p->rho_table, p->rho_table + nall);
     if (p->pair_weight) job->pairw.assign(p->pair_weight, p->pair_weight + nb * nb);

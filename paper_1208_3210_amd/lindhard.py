@@ -60,6 +60,7 @@ class Problem(ctypes.Structure):
         ("k_zones", ctypes.c_int32), ("rho_table", ctypes.POINTER(ctypes.c_double)),
         ("omega_interp", ctypes.c_int32),
         ("n_bands", ctypes.c_int32), ("pair_weight", ctypes.POINTER(ctypes.c_double)),
+        ("nkz", ctypes.c_int32),
     ]
 
 
@@ -172,12 +173,13 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
                  zones: tuple = (1, 1), ff_kind: int = LINDHARD_FF_NONE, ff_width: float = 0.0,
                  precision: int = LINDHARD_FP32C, want_rpa: bool = False, k_zones: int = 1,
                  rho_table: Optional[np.ndarray] = None, omega_interp: bool = False, n_bands: int = 1,
-                 pair_weight: Optional[np.ndarray] = None):
+                 pair_weight: Optional[np.ndarray] = None, nkz: int = 1):
     """Fill a Problem; returns (problem, keepalive) -- keep `keepalive` until the call."""
     om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
     keep = [om]
     nb = max(1, int(n_bands))
-    for name, tab, n in (("eps_table", eps_table, nb * nkx * nky), ("rho_table", rho_table, nb * nkx * nky),
+    nk3 = nkx * nky * max(1, int(nkz))
+    for name, tab, n in (("eps_table", eps_table, nb * nk3), ("rho_table", rho_table, nb * nk3),
                          ("pair_weight", pair_weight, nb * nb)):
         if tab is not None and np.asarray(tab).size != n:
             raise ValueError("%s holds %d values, %d expected" % (name, np.asarray(tab).size, n))
@@ -198,6 +200,7 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
     p.k_zones = int(k_zones)
     p.omega_interp = int(bool(omega_interp))
     p.n_bands = int(n_bands)
+    p.nkz = int(nkz)
     if pair_weight is not None:
         pw = np.ascontiguousarray(np.asarray(pair_weight, dtype=np.float64))
         keep.append(pw)

@@ -114,6 +114,33 @@ def config_multiband(nk: int = 2048, neps: int = 512, pairs: bool = True) -> dic
     return cfg
 
 
+def band3d_table(nkx: int, nky: int, nkz: int, seed: int = 1208, tz: float = 0.08) -> np.ndarray:
+    """Seeded synthetic three-dimensional band [iz][iy][ix] (eV): an in-plane
+    cosine series sum_{a,b <= 2} c_ab cos(a kx) cos(b ky), c_ab uniform in
+    [-0.3, 0.3], plus an interlayer term -2 tz cos(kz), and a seeded
+    perturbation of 0.02 eV so that no symmetry is exact."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(-0.3, 0.3, size=(3, 3))
+    kx = 2.0 * np.pi * np.arange(nkx) / nkx
+    ky = 2.0 * np.pi * np.arange(nky) / nky
+    kz = 2.0 * np.pi * np.arange(nkz) / nkz
+    cx = np.stack([np.cos(a * kx) for a in range(3)])
+    cy = np.stack([np.cos(b * ky) for b in range(3)])
+    plane = np.einsum("ab,by,ax->yx", c, cy, cx)
+    eps = plane[None, :, :] - 2.0 * tz * np.cos(kz)[:, None, None]
+    return eps + rng.uniform(-0.02, 0.02, size=eps.shape)
+
+
+def config_3d(nkx: int = 256, nky: int = 256, nkz: int = 64, neps: int = 512) -> dict:
+    """Three-dimensional instance with as many k points as the 2048^2 one:
+    256 x 256 x 64 k (``band3d_table``), 512 energies on [-2, 2] eV,
+    G = 0.01 eV, 256 omegas, filling 1.15."""
+    emin, emax = -2.0, 2.0
+    return dict(eps_table=band3d_table(nkx, nky, nkz), nkz=nkz, filling=1.15, nkx=nkx, nky=nky, neps=neps,
+                emin=emin, emax=emax, gamma=0.01, omega=lag_omegas(neps, emin, emax, range(1, neps // 2 + 1)),
+                zones=(1, 1), ff_kind=0, ff_width=0.0)
+
+
 def config_extended(nk: int = 2048, k_zones: int = 16, neps: int = 512) -> dict:
     """Extended-momentum instance (the form the paper computes for its
     extended-zone maps): a 2048^2 momentum grid spanning 16 x 16 Brillouin
