@@ -312,6 +312,26 @@ def bench_3d(LH, W, torch, steps=3):
     return res
 
 
+def bench_grid_2049(LH, W, torch, steps=2):
+    """The paper's own grid size: 2049 x 2049 momenta spanning 16 x 16 zones
+    (128 points per zone plus the closing point) with the d(x2-y2) momentum
+    density, 512 energies, 256 omegas, FP32 -- a size that is not a power of
+    two, so every transform runs as a Bluestein convolution of length 8192."""
+    cfg = W.config_extended(nk=2049)
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    out = plan.empty()
+    plan.exec_timed(out)
+    runs = [plan.exec_timed(out) for _ in range(steps)]
+    ms = float(np.mean([sum(r) for r in runs]))
+    pts = cfg["nkx"] * cfg["nky"] * len(cfg["omega"])
+    res = {"workload": "2049^2 momentum grid over 16x16 zones, d(x2-y2) density, 512 energies, 256 omegas, FP32",
+           "ms_per_step": ms, "points_per_s": pts / (ms * 1e-3),
+           "passes_ms": [float(np.mean([r[i] for r in runs])) for i in range(5)],
+           "schedule": plan.info.schedule.decode()}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +353,7 @@ def main():
     ap.add_argument("--no-extended", action="store_true",
                     help="skip the extended-momentum instance (16x16 zones, momentum density weights)")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional k-grid instance")
+    ap.add_argument("--no-2049", action="store_true", help="skip the 2049^2 (not a power of two) instance")
     ap.add_argument("--no-multiband", action="store_true",
                     help="skip the two-band instances (summed spectral function, band-pair sum)")
     ap.add_argument("--epilogues-only", action="store_true",
@@ -479,6 +500,9 @@ def main():
     k3 = None if args.no_3d else bench_3d(LH, W, torch)
     if k3:
         print("bench: 3d %.3f ms/step" % k3["ms_per_step"], file=sys.stderr, flush=True)
+    g2049 = None if args.no_2049 else bench_grid_2049(LH, W, torch)
+    if g2049:
+        print("bench: 2049^2 grid %.3f ms/step" % g2049["ms_per_step"], file=sys.stderr, flush=True)
     epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
     if epi:
         print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
@@ -494,7 +518,7 @@ def main():
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
-        "epilogues": epi, "extended_momentum": ext, "multiband": mb, "k3d": k3,
+        "epilogues": epi, "extended_momentum": ext, "multiband": mb, "k3d": k3, "grid_2049": g2049,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -74,8 +75,18 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
 {
     if (!p) return LINDHARD_EINVAL;
     if (p->precision != LINDHARD_FP32C && p->precision != LINDHARD_FP64) return LINDHARD_EINVAL;
-    if (!is_pow2(p->nkx) || !is_pow2(p->nky) || p->nkx < 4 || p->nky < 4 || p->nkx > 2048 || p->nky > 2048)
-        return LINDHARD_EINVAL;
+    // powers of two up to 2048; other sizes (Bluestein transforms) up to 4096
+    // in FP32 and 2048 in FP64, one zone, one band, no form factor, no RPA
+    const bool any_size = !is_pow2(p->nkx) || !is_pow2(p->nky);
+    if (p->nkx < 4 || p->nky < 4) return LINDHARD_EINVAL;
+    if (!any_size && (p->nkx > 2048 || p->nky > 2048)) return LINDHARD_EINVAL;
+    if (any_size) {
+        const int lim = p->precision == LINDHARD_FP64 ? 2048 : 4096;
+        if (p->nkx > lim || p->nky > lim) return LINDHARD_EINVAL;
+        if (p->zones_x != 1 || p->zones_y != 1 || p->ff_kind != LINDHARD_FF_NONE || p->want_rpa || p->nkz > 1 ||
+            p->n_bands > 1 || p->pair_weight)
+            return LINDHARD_EINVAL;
+    }
     if (!is_pow2(p->neps) || p->neps < 4 || p->neps > 2048) return LINDHARD_EINVAL;
     if (!std::isfinite(p->emin) || !std::isfinite(p->emax) || !(p->emin < 0.0) || !(p->emax > 0.0))
         return LINDHARD_EINVAL;
@@ -146,6 +157,27 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     g.C = g.fp64 ? 2 : 4;
     g.logC = ilog2(g.C);
     g.NT = g.L / g.C + 1;
+    g.bs = any_size ? 1 : 0;
+    if (g.bs) {
+        // every kx column is kept (complex transforms of the full length)
+        g.NT = (p->nkx + g.C - 1) / g.C;
+        auto clog2 = [](int v) {
+            int l = 0;
+            while ((1 << l) < v) ++l;
+            return l;
+        };
+        g.logMx = clog2(2 * p->nkx - 1);
+        g.logMy = clog2(2 * p->nky - 1);
+        const size_t cs = g.fp64 ? 16 : 8;
+        auto lines = [&](int logM, int cap) {
+            const int M = 1 << logM, E = std::min(16, M), G = M / E;
+            int R = 1;
+            while (R * 2 <= cap && R * 2 * G <= 256 && (size_t)(R * 2) * M * cs <= 65536) R *= 2;
+            return R;
+        };
+        g.bs_Rr = lines(g.logMx, p->nky);
+        g.bs_Rc = lines(g.logMy, g.NT * g.C);
+    }
     g.neps = p->neps;
     g.j0 = count_occupied(p->neps, p->emin, p->emax);
 
@@ -264,6 +296,15 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             if (!std::strcmp(ev, "fft")) g.p3_variant = 1;
         }
     }
+    if (g.bs) {
+        // rows of any count: one row of C points per window block
+        g.p3_TR = g.C;
+        g.p3_logTR = g.logC;
+        g.p3_RY = 1;
+        g.p3_logRY = 0;
+        g.p3f_TR = g.C;
+        g.p3f_logTR = g.logC;
+    }
     {
         // P5: R rows of (L + 1) complex values in LDS (<= 64 KiB), <= 256 threads
         const int E = std::min(16, g.L), G = g.L / E;
@@ -287,7 +328,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
                 }
             return true;
         };
-        if (nkz > 1) sym = false;  // the real even form is two-dimensional
+        if (nkz > 1 || g.bs) sym = false;  // the real even form: two dimensions, powers of two
         for (int b = 0; b < nbands && sym; ++b) {
             if (p->eps_table) sym = mirror(p->eps_table + b * nk);
             if (sym && p->rho_table) sym = mirror(p->rho_table + b * nk);
@@ -381,6 +422,8 @@ size_t plan_footprint(const Plan &pl)
     if (pl.pairs && g.nL > 0)
         b += al((size_t)pl.nb * g.nS * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
     b += al(g.nkx * cs) + al(g.nky * cs) + al(g.nkz * cs) + al(((size_t)1 << g.logNE) * cs);
+    if (g.bs)
+        b += al(g.nkx * cs) + al(g.nky * cs) + 3 * (al(((size_t)1 << g.logMx) * cs) + al(((size_t)1 << g.logMy) * cs));
     b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
     b += al(pl.p.nomega * sizeof(PlaneSrc)) + al(pl.p.nomega * sizeof(int)) + al(pl.p.nomega * sizeof(double));
     b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
@@ -484,7 +527,8 @@ void plan_free(Plan &pl)
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twz, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
-                     &pl.rho,              &pl.bspec};
+                     &pl.rho,              &pl.bspec,         &pl.bsx[0], &pl.bsx[1], &pl.bsx[2], &pl.bsx[3],
+                     &pl.bsy[0],           &pl.bsy[1],        &pl.bsy[2], &pl.bsy[3]};
     for (void **p : ptrs) *p = nullptr;
 }
 
@@ -752,6 +796,14 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
     LH_ALLOC(pl.twz, g.nkz * cs);
+    if (g.bs) {
+        LH_ALLOC(pl.bsx[0], g.nkx * cs);
+        LH_ALLOC(pl.bsy[0], g.nky * cs);
+        for (int i = 1; i < 4; ++i) {
+            LH_ALLOC(pl.bsx[i], ((size_t)1 << g.logMx) * cs);
+            LH_ALLOC(pl.bsy[i], ((size_t)1 << g.logMy) * cs);
+        }
+    }
     LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
     LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
     LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
@@ -792,6 +844,81 @@ static hipStream_t thread_setup_stream(int device)
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
     streams.push_back({device, st});
     return st;
+}
+
+// In-place FFT of a power-of-two length in FP64 (host; plan tables only).
+static void fft_host(std::vector<std::complex<double>> &a)
+{
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        for (size_t k = 0; k < len / 2; ++k) {
+            const double ang = -2.0 * M_PI * (double)k / (double)len;
+            const std::complex<double> w(std::cos(ang), std::sin(ang));
+            for (size_t i = 0; i < n; i += len) {
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
+// Bluestein tables of one axis of length n (a grid of any size): chirp
+// b_k = exp(i pi (k^2 mod 2n) / n), the spectra FFT_M(B) / M and FFT_M(conj B) / M
+// of the chirp sequence B (B_m = b_m = B_(M-m) for m < n, zero between), and
+// the FFT twiddles exp(-2 pi i s / M); FP64, rounded once to the precision.
+// `keep` holds the host arrays until the copies have run.
+static hipError_t bs_tables(const Plan &pl, int n, int logM, void *const *dst, hipStream_t st,
+                            std::vector<std::vector<double>> &keep)
+{
+    const size_t M = (size_t)1 << logM;
+    std::vector<std::complex<double>> b(n), B(M, 0.0), Bc(M, 0.0), tw(M);
+    for (int k = 0; k < n; ++k) {
+        const double ang = M_PI * (double)(((long)k * k) % (2L * n)) / (double)n;
+        b[k] = std::complex<double>(std::cos(ang), std::sin(ang));
+    }
+    for (int m = 0; m < n; ++m) {
+        B[m] = b[m];
+        if (m > 0) B[M - m] = b[m];
+    }
+    for (size_t m = 0; m < M; ++m) Bc[m] = std::conj(B[m]);
+    fft_host(B);
+    fft_host(Bc);
+    for (size_t s = 0; s < M; ++s) {
+        const double ang = -2.0 * M_PI * (double)s / (double)M;
+        tw[s] = std::complex<double>(std::cos(ang), std::sin(ang));
+    }
+    const std::vector<std::complex<double>> *src[4] = {&b, &B, &Bc, &tw};
+    const double sc[4] = {1.0, 1.0 / (double)M, 1.0 / (double)M, 1.0};
+    for (int i = 0; i < 4; ++i) {
+        const auto &v = *src[i];
+        const size_t nv = 2 * v.size();  // interleaved (re, im)
+        // one host array per table, in the plan's precision (FP32 pairs are
+        // packed into the storage of nv / 2 doubles)
+        keep.emplace_back(pl.g.fp64 ? nv : nv / 2);
+        double *hd = keep.back().data();
+        float *hf = reinterpret_cast<float *>(hd);
+        for (size_t k = 0; k < v.size(); ++k) {
+            const double re = v[k].real() * sc[i], im = v[k].imag() * sc[i];
+            if (pl.g.fp64) {
+                hd[2 * k] = re;
+                hd[2 * k + 1] = im;
+            } else {
+                hf[2 * k] = (float)re;
+                hf[2 * k + 1] = (float)im;
+            }
+        }
+        const hipError_t e = hipMemcpyAsync(dst[i], hd, nv * (pl.g.fp64 ? sizeof(double) : sizeof(float)),
+                                            hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_plan_s *o)
@@ -842,6 +969,11 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     LH_TRY(hipMemcpyAsync(pl.d_frac, pl.frac.data(), pl.frac.size() * sizeof(double), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_lag, pl.lag.data(), pl.lag.size() * sizeof(int), hipMemcpyHostToDevice, st));
     LH_TRY(launch_tables(pl, st));
+    std::vector<std::vector<double>> keep;
+    if (pl.g.bs) {
+        LH_TRY(bs_tables(pl, pl.g.nkx, pl.g.logMx, pl.bsx, st, keep));
+        LH_TRY(bs_tables(pl, pl.g.nky, pl.g.logMy, pl.bsy, st, keep));
+    }
     if (pl.p.want_rpa)
         LH_TRY(hipMemsetAsync(pl.im1, 0, (size_t)pl.g.neps * nk * pl.elem_bytes, st));
     LH_TRY(hipStreamSynchronize(st));

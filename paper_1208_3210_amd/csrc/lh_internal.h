@@ -70,6 +70,10 @@ struct Geo {
     int logNE;                // FFT length along energy for variant 1
     int p3f_TR, p3f_logTR;    // real-space points per block for variant 1
     int tuned;                // 1: window schedule chosen by timing, 2: from the tuning cache
+    // grids of any size (bs = 1): Bluestein transforms of length 2^logMx,
+    // 2^logMy; bs_Rr rows per block in the row passes, bs_Rc columns per
+    // block in the column passes
+    int bs, logMx, logMy, bs_Rr, bs_Rc;
 };
 
 // Elements per thread of the register FFTs in the even builder pass (the
@@ -99,6 +103,9 @@ struct Plan {
     void *twx = nullptr;       // cx<T>[nkx]
     void *twy = nullptr;       // cx<T>[nky]
     void *twz = nullptr;       // cx<T>[nkz] (three dimensions)
+    // grids of any size: per axis chirp b, chirp spectra hf / hi, FFT twiddles of length M
+    void *bsx[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *bsy[4] = {nullptr, nullptr, nullptr, nullptr};
     void *twe = nullptr;       // cx<T>[2^logNE] (energy-axis FFT)
     bool has_rho = false;
     void *rho = nullptr;       // momentum-density weights rho[band][iy][ix] in T (or none)

@@ -34,8 +34,10 @@ __global__ void __launch_bounds__(kThreads) k_band_tb(double *__restrict__ eps, 
     const long k = (long)blockIdx.x * kThreads + threadIdx.x;
     if (k >= nk) return;
     // folded indices make eps(kx, ky) = eps(-kx, ky) = eps(kx, -ky) bit for bit
-    const int ix = min((int)(k & (nkx - 1)), nkx - (int)(k & (nkx - 1)));
-    const int iy = min((int)(k >> logNx), nky - (int)(k >> logNx));
+    // (any grid size: the row index by division)
+    const int kx0 = (int)(k % nkx), ky0 = (int)(k / nkx);
+    const int ix = min(kx0, nkx - kx0);
+    const int iy = min(ky0, nky - ky0);
     // k_zones kz: the grid spans kz zones, k = 2 pi kz (ix / nkx, iy / nky)
     const double cx = cospi(2.0 * kz * ix / nkx), cy = cospi(2.0 * kz * iy / nky);
     const double c2x = cospi(4.0 * kz * ix / nkx), c2y = cospi(4.0 * kz * iy / nky);
@@ -1896,6 +1898,179 @@ __global__ void __launch_bounds__(kThreads) k_envelope(const T *__restrict__ im,
     }
 }
 
+// ====================================================== grids of any size
+// A transform of length N that is not a power of two runs as Bluestein's
+// chirp convolution: with b_n = exp(i pi n^2 / N), the forward transform is
+// X_k = conj(b_k) sum_n (x_n conj(b_n)) b_(k-n), a circular convolution of
+// length M = 2^logM >= 2N - 1 done with two register FFTs of length M.  The
+// tables of one axis (built in FP64 on the host, rounded once): chirp b_n
+// (n < N) and the spectra hf = FFT_M(B) / M, hi = FFT_M(conj B) / M of the
+// chirp sequence B (B_m = b_m, B_(M-m) = b_m, zero between) for the forward
+// and the inverse transform.
+struct BsTab {
+    const void *b, *hf, *hi, *tw;  // cx<T>[N], cx<T>[M], cx<T>[M], cx<T>[M] (FFT twiddles of length M)
+    int n;
+};
+
+// v[s] = x[g + s G] (zero for n >= N) -> the DFT of length N (INV: inverse,
+// no 1/N) in the same places.  Every thread of the block calls it.
+template <typename T, int LOGM, bool INV>
+__device__ __forceinline__ void bs_line(cx<T> *v, cx<T> *buf, const BsTab &t, int g, int lx)
+{
+    using F = RegFFT<T, LOGM, false>;
+    using Fi = RegFFT<T, LOGM, true>;
+    constexpr int E = F::E, G = F::G;
+    const cx<T> *b = (const cx<T> *)t.b, *h = (const cx<T> *)(INV ? t.hi : t.hf), *tw = (const cx<T> *)t.tw;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int n = g + s * G;
+        v[s] = n < t.n ? cmul(v[s], INV ? b[n] : cconj(b[n])) : mk<T>((T)0, (T)0);
+    }
+    F::run(v, buf, tw, 0, g, lx);
+#pragma unroll
+    for (int s = 0; s < E; ++s) v[s] = cmul(v[s], h[g + s * G]);
+    __syncthreads();
+    Fi::run(v, buf, tw, 0, g, lx);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int k = g + s * G;
+        if (k < t.n) v[s] = cmul(v[s], INV ? b[k] : cconj(b[k]));
+    }
+}
+
+// P1, any size: R rows (ky) of one energy slice; the spectral function of
+// each row is built, transformed along kx with bs_line, and written to the
+// column-tiled array (every kx column, NT = ceil(nkx / C) tiles).
+template <typename T, int LOGM, bool W>
+__global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, Geo g, double emin, double deps,
+                                               double gamma, BsTab tx, cx<T> *__restrict__ spec,
+                                               const T *__restrict__ rho)
+{
+    using F = RegFFT<T, LOGM, false>;
+    constexpr int M = F::N, E = F::E, G = F::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int R = g.bs_Rr;
+    const int tid = threadIdx.x, line = tid / G, gg = tid % G;
+    const int ky = min(blockIdx.x * R + line, g.nky - 1);
+    const int j = g.jA + blockIdx.y;
+    const int nkx = g.nkx;
+    const double ej = emin + (j + 0.5) * deps;
+    const T gp = (T)(gamma / kPi), g2 = (T)(gamma * gamma);
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int n = gg + s * G;
+        T a = (T)0;
+        if (n < nkx) {
+            a = lorentz((T)(ej - xi[(size_t)ky * nkx + n]), gp, g2);
+            if constexpr (W) a *= rho[(size_t)ky * nkx + n];
+        }
+        v[s] = mk<T>(a, (T)0);
+    }
+    bs_line<T, LOGM, false>(v, lds + line * M, tx, gg, lds_xor_gfast<M, G>(line));
+    if (blockIdx.x * R + line < g.nky) {
+        cx<T> *dst = spec + (size_t)blockIdx.y * g.slice_elems;
+        const int C = g.C, logC = g.logC;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {  // every column of the tiles; the padding ones get 0
+            const int k = gg + s * G;
+            if (k < g.NT * C)
+                dst[((size_t)(k >> logC) * g.nky + ky) * C + (k & (C - 1))] = k < nkx ? v[s] : mk<T>((T)0, (T)0);
+        }
+    }
+}
+
+// Column pass, any size: lines along ky (stride C in a tile), one per
+// column (tile, c); R lines per block, lane-interleaved so that a wave's
+// loads cover neighbouring columns.  Transformed in place.
+template <typename T, int LOGM, bool INV>
+__global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g, BsTab ty)
+{
+    using F = RegFFT<T, LOGM, false>;
+    constexpr int M = F::N, E = F::E, G = F::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int R = g.bs_Rc;
+    const int tid = threadIdx.x, line = tid % R, gg = tid / R;
+    const int col = blockIdx.x * R + line;  // tile * C + c
+    const int ncol = g.NT * g.C;
+    const bool active = col < ncol;
+    const int tile = (active ? col : 0) >> g.logC, c = (active ? col : 0) & (g.C - 1);
+    cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)tile * g.nky * g.C + c;
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int n = gg + s * G;
+        v[s] = (active && n < g.nky) ? base[(size_t)n * g.C] : mk<T>((T)0, (T)0);
+    }
+    bs_line<T, LOGM, INV>(v, lds + line * M, ty, gg, lds_xor_interleaved<T, M>(line, R));
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int k = gg + s * G;
+            if (k < g.nky) base[(size_t)k * g.C] = v[s];
+        }
+    }
+}
+
+// P5, any size: the inverse transform along kx of R rows (qy) of one output
+// plane (wa S[a] + wb S[b] for an omega between two lags), the real part
+// scaled and written Gamma-centred: out[plane][(qy + nky/2) mod nky][(qx +
+// nkx/2) mod nkx] (one zone, no form factor).
+template <typename T, int LOGM>
+__global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, Geo g, BsTab tx,
+                                              const PlaneSrc *__restrict__ psrc, double scale,
+                                              T *__restrict__ out)
+{
+    using F = RegFFT<T, LOGM, false>;
+    constexpr int M = F::N, E = F::E, G = F::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+    const int R = g.bs_Rr;
+    const int tid = threadIdx.x, line = tid / G, gg = tid % G;
+    const int plane = blockIdx.y;
+    const int qy = min(blockIdx.x * R + line, g.nky - 1);
+    const bool rowok = blockIdx.x * R + line < g.nky;
+    const int nkx = g.nkx, nky = g.nky;
+    const PlaneSrc ps = psrc[plane];
+    T *orow = out + ((size_t)plane * nky + (qy + nky / 2) % nky) * nkx;
+    if (ps.a < 0) {  // the plane is zero (block-uniform)
+        if (rowok)
+            for (int k = gg; k < nkx; k += G) orow[k] = (T)0;
+        return;
+    }
+    const cx<T> *src = spec + (size_t)ps.a * g.slice_elems;
+    const cx<T> *src2 = spec + (size_t)(ps.b >= 0 ? ps.b : ps.a) * g.slice_elems;
+    const bool blend = ps.b >= 0 || ps.wa != 1.0;
+    const T wa = (T)ps.wa, wb = (T)ps.wb;
+    const int C = g.C, logC = g.logC;
+    cx<T> v[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        const int k = gg + s * G;
+        cx<T> x = mk<T>((T)0, (T)0);
+        if (k < nkx) {
+            const size_t o = ((size_t)(k >> logC) * nky + qy) * C + (k & (C - 1));
+            x = src[o];
+            if (blend) {
+                const cx<T> y = src2[o];
+                x = mk<T>(wa * x.x + wb * y.x, wa * x.y + wb * y.y);
+            }
+        }
+        v[s] = x;
+    }
+    bs_line<T, LOGM, true>(v, lds + line * M, tx, gg, lds_xor_gfast<M, G>(line));
+    if (rowok) {
+        const T sc = (T)scale;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int k = gg + s * G;
+            if (k < nkx) orow[(k + nkx / 2) % nkx] = v[s].x * sc;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
@@ -2086,6 +2261,101 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
 template <typename T>
 static hipError_t window_t(const Plan &pl, hipStream_t st);
 
+#define LH_SWITCH_LOGM(v, CALL)                  \
+    switch (v) {                                 \
+    case 3: CALL(3); break;                      \
+    case 4: CALL(4); break;                      \
+    case 5: CALL(5); break;                      \
+    case 6: CALL(6); break;                      \
+    case 7: CALL(7); break;                      \
+    case 8: CALL(8); break;                      \
+    case 9: CALL(9); break;                      \
+    case 10: CALL(10); break;                    \
+    case 11: CALL(11); break;                    \
+    case 12: CALL(12); break;                    \
+    case 13: CALL(13); break;                    \
+    default: return hipErrorInvalidValue;        \
+    }
+
+static BsTab bs_tab(const Plan &pl, bool y)
+{
+    void *const *t = y ? pl.bsy : pl.bsx;
+    return BsTab{t[0], t[1], t[2], t[3], y ? pl.g.nky : pl.g.nkx};
+}
+
+template <typename T, int LOGM>
+static void launch_bs_row(const Plan &pl, cx<T> *spec, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGM, false>;
+    const dim3 grid(cdiv(g.nky, g.bs_Rr), g.nS);
+    const size_t lds = (size_t)g.bs_Rr * F::N * sizeof(cx<T>);
+    if (pl.rho)
+        hipLaunchKernelGGL((k_bs_row<T, LOGM, true>), grid, dim3(g.bs_Rr * F::G), lds, st, pl.xi, g, pl.p.emin,
+                           pl.deps, pl.p.gamma, bs_tab(pl, false), spec, (const T *)pl.rho);
+    else
+        hipLaunchKernelGGL((k_bs_row<T, LOGM, false>), grid, dim3(g.bs_Rr * F::G), lds, st, pl.xi, g, pl.p.emin,
+                           pl.deps, pl.p.gamma, bs_tab(pl, false), spec, (const T *)nullptr);
+}
+
+template <typename T, int LOGM, bool INV>
+static void launch_bs_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGM, false>;
+    const dim3 grid(cdiv((long)g.NT * g.C, g.bs_Rc), nslices);
+    hipLaunchKernelGGL((k_bs_col<T, LOGM, INV>), grid, dim3(g.bs_Rc * F::G), (size_t)g.bs_Rc * F::N * sizeof(cx<T>),
+                       st, spec, g, bs_tab(pl, true));
+}
+
+template <typename T, int LOGM>
+static void launch_bs_p5(const Plan &pl, const cx<T> *spec, T *out, hipStream_t st)
+{
+    const Geo &g = pl.g;
+    using F = RegFFT<T, LOGM, false>;
+    const dim3 grid(cdiv(g.nky, g.bs_Rr), pl.p.nomega);
+    hipLaunchKernelGGL((k_bs_p5<T, LOGM>), grid, dim3(g.bs_Rr * F::G), (size_t)g.bs_Rr * F::N * sizeof(cx<T>), st,
+                       spec, g, bs_tab(pl, false), pl.d_src, pl.scale, out);
+}
+
+// Grids of any size: Bluestein row and column passes around the same window.
+template <typename T>
+static hipError_t exec_bs(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
+{
+    const Geo &g = pl.g;
+    cx<T> *spec = (cx<T> *)pl.spec;
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    if (g.nL > 0) {
+#define LH_B1(LG) launch_bs_row<T, LG>(pl, spec, st)
+        LH_SWITCH_LOGM(g.logMx, LH_B1)
+#undef LH_B1
+        mark(1);
+#define LH_B2(LG) launch_bs_col<T, LG, false>(pl, spec, g.nS, st)
+        LH_SWITCH_LOGM(g.logMy, LH_B2)
+#undef LH_B2
+        mark(2);
+        LH_HIP_TRY(window_t<T>(pl, st));
+        mark(3);
+#define LH_B4(LG) launch_bs_col<T, LG, true>(pl, spec, g.nL, st)
+        LH_SWITCH_LOGM(g.logMy, LH_B4)
+#undef LH_B4
+        mark(4);
+    } else {
+        mark(1);
+        mark(2);
+        mark(3);
+        mark(4);
+    }
+#define LH_B5(LG) launch_bs_p5<T, LG>(pl, spec, out, st)
+    LH_SWITCH_LOGM(g.logMx, LH_B5)
+#undef LH_B5
+    mark(5);
+    return hipGetLastError();
+}
+
 // ev (optional, 6 events): recorded before P1 and after P1, P2, P3, P4, P5
 // (with a band-pair sum, after the forward passes of every band, then at the
 // end of the pair loop, which holds P3, P4 and P5 of every pair).
@@ -2093,6 +2363,7 @@ template <typename T>
 static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 {
     const Geo &g = pl.g;
+    if (g.bs) return exec_bs<T>(pl, out, st, ev);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);

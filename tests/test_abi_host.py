@@ -47,7 +47,8 @@ def _base(**over):
 
 
 @pytest.mark.parametrize("over,status", [
-    (dict(nkx=48), -1), (dict(nky=2), -1), (dict(nkx=4096), -1), (dict(neps=100), -1), (dict(neps=2), -1),
+    (dict(nkx=48, zones=(3, 1)), -1), (dict(nkx=2049), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
+    (dict(nkx=4096), -1), (dict(nkx=48, want_rpa=True), -1), (dict(neps=100), -1), (dict(neps=2), -1),
     (dict(emin=0.1), -1), (dict(emax=-0.1), -1), (dict(gamma=0.0), -1), (dict(gamma=math.nan), -1),
     (dict(precision=3), -1), (dict(zones=(2, 1)), -1), (dict(zones=(1, 0)), -1), (dict(ff_kind=7), -1),
     (dict(ff_kind=1, ff_width=0.0), -1), (dict(filling=2.5), -1), (dict(mu=math.inf), -1),
