@@ -506,7 +506,7 @@ def main():
     epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
     if epi:
         print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
-                                               if isinstance(v, dict)), file=sys.stderr, flush=True)
+                                               if isinstance(v, dict) and "ms" in v), file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
     res = {
         "metric": "chi(q,w) points/s at 2048^2 k x 512 eps, FP32 vs FP64 at <=1e-5 rel",
