@@ -159,8 +159,8 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     g.NT = g.L / g.C + 1;
     g.bs = any_size ? 1 : 0;
     if (g.bs) {
-        // every kx column is kept (complex transforms of the full length)
-        g.NT = (p->nkx + g.C - 1) / g.C;
+        // real rows: the columns kx <= nkx / 2 hold the whole spectrum
+        g.NT = (p->nkx / 2 + 1 + g.C - 1) / g.C;
         auto clog2 = [](int v) {
             int l = 0;
             while ((1 << l) < v) ++l;
@@ -175,7 +175,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             while (R * 2 <= cap && R * 2 * G <= 256 && (size_t)(R * 2) * M * cs <= 65536) R *= 2;
             return R;
         };
-        g.bs_Rr = lines(g.logMx, p->nky);
+        g.bs_Rr = lines(g.logMx, (p->nky + 1) / 2);
         g.bs_Rc = lines(g.logMy, g.NT * g.C);
     }
     g.neps = p->neps;
@@ -420,7 +420,7 @@ size_t plan_footprint(const Plan &pl)
     b += al(nk * 8 * pl.nb);
     if (pl.has_rho) b += al(nk * es * pl.nb);
     if (pl.pairs && g.nL > 0)
-        b += al((size_t)pl.nb * g.nS * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
+        b += al((size_t)(pl.nb * g.nS + g.nL) * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
     b += al(g.nkx * cs) + al(g.nky * cs) + al(g.nkz * cs) + al(((size_t)1 << g.logNE) * cs);
     if (g.bs)
         b += al(g.nkx * cs) + al(g.nky * cs) + 3 * (al(((size_t)1 << g.logMx) * cs) + al(((size_t)1 << g.logMy) * cs));
@@ -527,7 +527,7 @@ void plan_free(Plan &pl)
     void **ptrs[] = {(void **)&pl.xi,     (void **)&pl.twx,  (void **)&pl.twy, &pl.twz, &pl.twe, (void **)&pl.ffx,
                      (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
-                     &pl.rho,              &pl.bspec,         &pl.bsx[0], &pl.bsx[1], &pl.bsx[2], &pl.bsx[3],
+                     &pl.rho,              &pl.bspec,         &pl.sacc,         &pl.bsx[0], &pl.bsx[1], &pl.bsx[2], &pl.bsx[3],
                      &pl.bsy[0],           &pl.bsy[1],        &pl.bsy[2], &pl.bsy[3]};
     for (void **p : ptrs) *p = nullptr;
 }
@@ -791,8 +791,10 @@ lindhard_status plan_build(Plan &pl, hipStream_t st)
     } while (0)
     LH_ALLOC(pl.xi, nk * 8 * pl.nb);
     if (pl.has_rho) LH_ALLOC(pl.rho, nk * es * pl.nb);
-    if (pl.pairs && g.nL > 0)
+    if (pl.pairs && g.nL > 0) {
         LH_ALLOC(pl.bspec, (size_t)pl.nb * g.nS * (g.even ? g.slice_e * es : g.slice_elems * cs));
+        LH_ALLOC(pl.sacc, (size_t)g.nL * (g.even ? g.slice_e * es : g.slice_elems * cs));
+    }
     LH_ALLOC(pl.twx, g.nkx * cs);
     LH_ALLOC(pl.twy, g.nky * cs);
     LH_ALLOC(pl.twz, g.nkz * cs);

@@ -113,6 +113,7 @@ struct Plan {
     bool pairs = false;        // band-pair sum with weights pairw[nu * nb + mu] (else one summed band)
     std::vector<double> pairw;
     void *bspec = nullptr;     // pair sum: forward-transformed spectra of every band, nb x nS slices
+    void *sacc = nullptr;      // pair sum: the summed window outputs, nL slices
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column
     double2 *ffy = nullptr;    // per extended row
     PlaneSrc *d_src = nullptr; // per omega: window slots and weights

@@ -13,8 +13,6 @@
 // RPA path (Sec. 4): P5 keeps every lag of the first zone, then the
 // Kramers-Kronig and chi / (1 - U chi) epilogues.
 #include "lh_fft.h"
-#include <type_traits>
-
 #include "lh_internal.h"
 #include "lh_regfft.h"
 
@@ -541,7 +539,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                                                 const cx<T> *__restrict__ twx, const PlaneSrc *__restrict__ psrc,
                                                 double scale, int zx, int zy, int ff, double ffs,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
-                                                T *__restrict__ out, int out_nx, int out_ny, int acc)
+                                                T *__restrict__ out, int out_nx, int out_ny)
 {
     using F = RegFFT<T, LOGL, true>;
     constexpr int L = F::N, E = F::E, G = F::G;
@@ -558,7 +556,6 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int nkx = g.nkx, nky = g.nky;
 
     if (MODE == 0 && slot < 0) {
-        if (acc) return;  // adds zero
         for (int rz = 0; rz < R * zy; ++rz) {
             const int r = rz % R, zi = rz / R;
             const int Y = zi * nky + ((qy0 + r + zy * nky / 2) & (nky - 1));
@@ -632,8 +629,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                         a = (T)((double)a * form_factor_sq(ffx[X], fy, ffs));
                         b = (T)((double)b * form_factor_sq(ffx[X + 1], fy, ffs));
                     }
-                    cx<T> *o = reinterpret_cast<cx<T> *>(orow + X);
-                    *o = acc ? cadd(*o, mk<T>(a, b)) : mk<T>(a, b);
+                    *reinterpret_cast<cx<T> *>(orow + X) = mk<T>(a, b);
                 }
             }
         }
@@ -643,9 +639,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const int u = 2 * (gg + s * G);
-            cx<T> *o = reinterpret_cast<cx<T> *>(orow + u);
-            const cx<T> x = mk<T>(v[s].x * sc, v[s].y * sc);
-            *o = acc ? cadd(*o, x) : x;
+            *reinterpret_cast<cx<T> *>(orow + u) = mk<T>(v[s].x * sc, v[s].y * sc);
         }
     }
 }
@@ -1345,7 +1339,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
                                                 const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
-                                                int out_ny, int acc)
+                                                int out_ny)
 {
     using F = RegFFT<T, LOGNX, true>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -1363,7 +1357,6 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
 
     if (MODE == 0 && slot < 0) {
-        if (acc) return;  // adds zero
         for (int rz = 0; rz < rows * 2 * zy; ++rz) {
             const int r = rz % rows, mir = (rz / rows) & 1, zi = rz / (2 * rows);
             const int qy0 = 2 * p0 + r;
@@ -1441,46 +1434,28 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
         for (int mir = 0; mir < 2; ++mir) {
             const int qy = mir ? (nky - qy0) & (nky - 1) : qy0;
             if (mir && qy == qy0) continue;
-            // the stores, plain or added to the output (a separate copy each,
-            // so that the plain form never reads the output)
-            auto store = [&](auto add) {
-                constexpr bool A = decltype(add)::value;
-                if (MODE == 0) {
-                    for (int zi = 0; zi < zy; ++zi) {
-                        const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
-                        T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
-                        const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
-                        for (int zj = 0; zj < zx; ++zj) {
+            if (MODE == 0) {
+                for (int zi = 0; zi < zy; ++zi) {
+                    const int Y = zi * nky + ((qy + zy * nky / 2) & (nky - 1));
+                    T *orow = out + ((size_t)plane * out_ny + Y) * out_nx;
+                    const double2 fy = ff ? ffy[Y] : make_double2(1.0, 0.0);
+                    for (int zj = 0; zj < zx; ++zj) {
 #pragma unroll
-                            for (int s = 0; s < E; ++s) {
-                                const int qx = gg + s * G;
-                                const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
-                                T val = (half ? v[s].y : v[s].x) * sc;
-                                if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
-                                if constexpr (A)
-                                    orow[X] += val;
-                                else
-                                    orow[X] = val;
-                            }
+                        for (int s = 0; s < E; ++s) {
+                            const int qx = gg + s * G;
+                            const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
+                            T val = (half ? v[s].y : v[s].x) * sc;
+                            if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
+                            orow[X] = val;
                         }
                     }
-                } else {
-                    const int m = g.m_lo + slot;
-                    T *orow = out + ((size_t)m * nky + qy) * nkx;
-#pragma unroll
-                    for (int s = 0; s < E; ++s) {
-                        const T val = (half ? v[s].y : v[s].x) * sc;
-                        if constexpr (A)
-                            orow[gg + s * G] += val;
-                        else
-                            orow[gg + s * G] = val;
-                    }
                 }
-            };
-            if (acc)
-                store(std::true_type{});
-            else
-                store(std::false_type{});
+            } else {
+                const int m = g.m_lo + slot;
+                T *orow = out + ((size_t)m * nky + qy) * nkx;
+#pragma unroll
+                for (int s = 0; s < E; ++s) orow[gg + s * G] = (half ? v[s].y : v[s].x) * sc;
+            }
         }
     }
 }
@@ -1938,9 +1913,12 @@ __device__ __forceinline__ void bs_line(cx<T> *v, cx<T> *buf, const BsTab &t, in
     }
 }
 
-// P1, any size: R rows (ky) of one energy slice; the spectral function of
-// each row is built, transformed along kx with bs_line, and written to the
-// column-tiled array (every kx column, NT = ceil(nkx / C) tiles).
+// P1, any size: R lines of one energy slice, each line two rows (ky = 2p,
+// 2p + 1) packed as z = A(2p) + i A(2p + 1).  After bs_line the two spectra
+// separate through the line's LDS buffer, X(2p)_k = (Z_k + conj Z_(N-k)) / 2,
+// X(2p+1)_k = (Z_k - conj Z_(N-k)) / 2i; the rows are real, so only the
+// columns kx <= nkx / 2 are kept (the others are conjugates), written to the
+// column-tiled array (NT = ceil((nkx / 2 + 1) / C) tiles, padding columns 0).
 template <typename T, int LOGM, bool W>
 __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                double gamma, BsTab tx, cx<T> *__restrict__ spec,
@@ -1952,7 +1930,9 @@ __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, G
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
     const int R = g.bs_Rr;
     const int tid = threadIdx.x, line = tid / G, gg = tid % G;
-    const int ky = min(blockIdx.x * R + line, g.nky - 1);
+    const int p = blockIdx.x * R + line;          // row pair
+    const int ka = min(2 * p, g.nky - 1), kb = min(2 * p + 1, g.nky - 1);
+    const bool hasa = 2 * p < g.nky, hasb = 2 * p + 1 < g.nky;
     const int j = g.jA + blockIdx.y;
     const int nkx = g.nkx;
     const double ej = emin + (j + 0.5) * deps;
@@ -1961,23 +1941,38 @@ __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, G
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int n = gg + s * G;
-        T a = (T)0;
+        T a = (T)0, b = (T)0;
         if (n < nkx) {
-            a = lorentz((T)(ej - xi[(size_t)ky * nkx + n]), gp, g2);
-            if constexpr (W) a *= rho[(size_t)ky * nkx + n];
+            a = lorentz((T)(ej - xi[(size_t)ka * nkx + n]), gp, g2);
+            b = lorentz((T)(ej - xi[(size_t)kb * nkx + n]), gp, g2);
+            if constexpr (W) {
+                a *= rho[(size_t)ka * nkx + n];
+                b *= rho[(size_t)kb * nkx + n];
+            }
         }
-        v[s] = mk<T>(a, (T)0);
+        v[s] = mk<T>(hasa ? a : (T)0, hasb ? b : (T)0);
     }
-    bs_line<T, LOGM, false>(v, lds + line * M, tx, gg, lds_xor_gfast<M, G>(line));
-    if (blockIdx.x * R + line < g.nky) {
-        cx<T> *dst = spec + (size_t)blockIdx.y * g.slice_elems;
-        const int C = g.C, logC = g.logC;
+    cx<T> *buf = lds + line * M;
+    bs_line<T, LOGM, false>(v, buf, tx, gg, lds_xor_gfast<M, G>(line));
 #pragma unroll
-        for (int s = 0; s < E; ++s) {  // every column of the tiles; the padding ones get 0
-            const int k = gg + s * G;
-            if (k < g.NT * C)
-                dst[((size_t)(k >> logC) * g.nky + ky) * C + (k & (C - 1))] = k < nkx ? v[s] : mk<T>((T)0, (T)0);
+    for (int s = 0; s < E; ++s) {
+        const int k = gg + s * G;
+        if (k < nkx) buf[k] = v[s];
+    }
+    __syncthreads();
+    cx<T> *dst = spec + (size_t)blockIdx.y * g.slice_elems;
+    const int C = g.C, logC = g.logC, H = nkx / 2, ncol = g.NT * C;
+    for (int k = gg; k < ncol; k += G) {
+        cx<T> xa = mk<T>((T)0, (T)0), xb = xa;
+        if (k <= H) {
+            const cx<T> zk = buf[k], zn = cconj(buf[k == 0 ? 0 : nkx - k]);
+            xa = cscale(cadd(zk, zn), (T)0.5);
+            const cx<T> dd = csub(zk, zn);
+            xb = mk<T>((T)0.5 * dd.y, (T)-0.5 * dd.x);  // (zk - zn) / 2i
         }
+        const size_t o = ((size_t)(k >> logC) * g.nky) * C + (k & (C - 1));
+        if (hasa) dst[o + (size_t)ka * C] = xa;
+        if (hasb) dst[o + (size_t)kb * C] = xb;
     }
 }
 
@@ -2014,10 +2009,13 @@ __global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g,
     }
 }
 
-// P5, any size: the inverse transform along kx of R rows (qy) of one output
-// plane (wa S[a] + wb S[b] for an omega between two lags), the real part
-// scaled and written Gamma-centred: out[plane][(qy + nky/2) mod nky][(qx +
-// nkx/2) mod nkx] (one zone, no form factor).
+// P5, any size: the inverse transform along kx of R lines of one output
+// plane (wa S[a] + wb S[b] for an omega between two lags), each line the rows
+// qy = 2p, 2p + 1 packed as z = S(2p) + i S(2p + 1): both rows have real
+// transforms, so the real and imaginary parts of the result are the two
+// output rows.  Columns rx > nkx / 2 are rebuilt as conj S(nkx - rx).  The
+// rows are scaled and written Gamma-centred: out[plane][(qy + nky/2) mod
+// nky][(qx + nkx/2) mod nkx] (one zone, no form factor).
 template <typename T, int LOGM>
 __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, Geo g, BsTab tx,
                                               const PlaneSrc *__restrict__ psrc, double scale,
@@ -2030,14 +2028,18 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
     const int R = g.bs_Rr;
     const int tid = threadIdx.x, line = tid / G, gg = tid % G;
     const int plane = blockIdx.y;
-    const int qy = min(blockIdx.x * R + line, g.nky - 1);
-    const bool rowok = blockIdx.x * R + line < g.nky;
-    const int nkx = g.nkx, nky = g.nky;
+    const int p = blockIdx.x * R + line;
+    const int qa = min(2 * p, g.nky - 1), qb = min(2 * p + 1, g.nky - 1);
+    const bool hasa = 2 * p < g.nky, hasb = 2 * p + 1 < g.nky;
+    const int nkx = g.nkx, nky = g.nky, H = nkx / 2;
     const PlaneSrc ps = psrc[plane];
-    T *orow = out + ((size_t)plane * nky + (qy + nky / 2) % nky) * nkx;
+    T *ra = out + ((size_t)plane * nky + (qa + nky / 2) % nky) * nkx;
+    T *rb = out + ((size_t)plane * nky + (qb + nky / 2) % nky) * nkx;
     if (ps.a < 0) {  // the plane is zero (block-uniform)
-        if (rowok)
-            for (int k = gg; k < nkx; k += G) orow[k] = (T)0;
+        for (int k = gg; k < nkx; k += G) {
+            if (hasa) ra[k] = (T)0;
+            if (hasb) rb[k] = (T)0;
+        }
         return;
     }
     const cx<T> *src = spec + (size_t)ps.a * g.slice_elems;
@@ -2045,28 +2047,42 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
     const bool blend = ps.b >= 0 || ps.wa != 1.0;
     const T wa = (T)ps.wa, wb = (T)ps.wb;
     const int C = g.C, logC = g.logC;
+    auto at = [&](int row, int k) {  // S(k, row) for k <= nkx / 2
+        const size_t o = ((size_t)(k >> logC) * nky + row) * C + (k & (C - 1));
+        cx<T> x = src[o];
+        if (blend) {
+            const cx<T> y = src2[o];
+            x = mk<T>(wa * x.x + wb * y.x, wa * x.y + wb * y.y);
+        }
+        return x;
+    };
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int k = gg + s * G;
-        cx<T> x = mk<T>((T)0, (T)0);
+        cx<T> z = mk<T>((T)0, (T)0);
         if (k < nkx) {
-            const size_t o = ((size_t)(k >> logC) * nky + qy) * C + (k & (C - 1));
-            x = src[o];
-            if (blend) {
-                const cx<T> y = src2[o];
-                x = mk<T>(wa * x.x + wb * y.x, wa * x.y + wb * y.y);
+            const bool lo = k <= H;
+            const int kk = lo ? k : nkx - k;
+            cx<T> sa = at(qa, kk), sb = at(qb, kk);
+            if (!lo) {
+                sa = cconj(sa);
+                sb = cconj(sb);
             }
+            if (!hasb) sb = mk<T>((T)0, (T)0);
+            z = mk<T>(sa.x - sb.y, sa.y + sb.x);  // sa + i sb
         }
-        v[s] = x;
+        v[s] = z;
     }
     bs_line<T, LOGM, true>(v, lds + line * M, tx, gg, lds_xor_gfast<M, G>(line));
-    if (rowok) {
-        const T sc = (T)scale;
+    const T sc = (T)scale;
 #pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int k = gg + s * G;
-            if (k < nkx) orow[(k + nkx / 2) % nkx] = v[s].x * sc;
+    for (int s = 0; s < E; ++s) {
+        const int k = gg + s * G;
+        if (k < nkx) {
+            const int X = (k + nkx / 2) % nkx;
+            if (hasa) ra[X] = v[s].x * sc;
+            if (hasb) rb[X] = v[s].y * sc;
         }
     }
 }
@@ -2182,15 +2198,14 @@ static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
 }
 
 template <typename T, int LOGL, int MODE>
-static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, double w, int acc,
-                      hipStream_t st)
+static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
                        (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
-                       pl.scale * w, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony, acc);
+                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
 }
 
 template <typename T, int LOGNX>
@@ -2223,8 +2238,7 @@ static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
 }
 
 template <typename T, int LOGNX, int MODE>
-static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, double w, int acc,
-                      hipStream_t st)
+static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGNX, true>;
@@ -2232,8 +2246,8 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     const int np = (g.Hy + 1) / 2;
     hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
                        (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g,
-                       (const cx<T> *)pl.twx, pl.d_src, pl.scale * w, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out,
-                       onx, ony, acc);
+                       (const cx<T> *)pl.twx, pl.d_src, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out,
+                       onx, ony);
 }
 
 #define LH_SWITCH_LOG(v, CALL)                   \
@@ -2277,6 +2291,24 @@ static hipError_t window_t(const Plan &pl, hipStream_t st);
     default: return hipErrorInvalidValue;        \
     }
 
+// dst = a src (overwrite) or dst += a src, n values of T, the arithmetic in T.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_lin(T *__restrict__ dst, const T *__restrict__ src, T a, int overwrite,
+                                                 size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+        dst[i] = overwrite ? a * src[i] : dst[i] + a * src[i];
+}
+
+template <typename T>
+static hipError_t launch_lin(T *dst, const T *src, double a, bool overwrite, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + kThreads - 1) / kThreads, 8192);
+    hipLaunchKernelGGL(k_lin<T>, dim3(blocks), dim3(kThreads), 0, st, dst, src, (T)a, overwrite ? 1 : 0, n);
+    return hipGetLastError();
+}
+
 static BsTab bs_tab(const Plan &pl, bool y)
 {
     void *const *t = y ? pl.bsy : pl.bsx;
@@ -2288,7 +2320,7 @@ static void launch_bs_row(const Plan &pl, cx<T> *spec, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(cdiv(g.nky, g.bs_Rr), g.nS);
+    const dim3 grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.nS);
     const size_t lds = (size_t)g.bs_Rr * F::N * sizeof(cx<T>);
     if (pl.rho)
         hipLaunchKernelGGL((k_bs_row<T, LOGM, true>), grid, dim3(g.bs_Rr * F::G), lds, st, pl.xi, g, pl.p.emin,
@@ -2313,7 +2345,7 @@ static void launch_bs_p5(const Plan &pl, const cx<T> *spec, T *out, hipStream_t 
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(cdiv(g.nky, g.bs_Rr), pl.p.nomega);
+    const dim3 grid(cdiv((g.nky + 1) / 2, g.bs_Rr), pl.p.nomega);
     hipLaunchKernelGGL((k_bs_p5<T, LOGM>), grid, dim3(g.bs_Rr * F::G), (size_t)g.bs_Rr * F::N * sizeof(cx<T>), st,
                        spec, g, bs_tab(pl, false), pl.d_src, pl.scale, out);
 }
@@ -2420,24 +2452,24 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         }
         return hipGetLastError();
     };
-    // P5 from pl.spec, weighted by w (acc: added to the output)
-    auto p5 = [&](double w, int acc) -> hipError_t {
+    // P5 from the window output in buf
+    auto p5 = [&](void *buf) -> hipError_t {
         const bool rpa = pl.p.want_rpa != 0;
         if (g.even) {
-            T *spr = (T *)pl.spec;
+            T *spr = (T *)buf;
             if (rpa) {
-#define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, w, acc, st)
+#define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
                 LH_SWITCH_LOG(g.logNx, LH_E5)
 #undef LH_E5
             } else {
-#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, w, acc, st)
+#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
                 LH_SWITCH_LOG(g.logNx, LH_E5)
 #undef LH_E5
             }
         } else {
-            const cx<T> *spec = (const cx<T> *)pl.spec;
+            const cx<T> *spec = (const cx<T> *)buf;
             if (rpa) {
-#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, w, acc, st)
+#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
                 LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
             } else {
@@ -2445,7 +2477,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
                 for (int z = 0; z < g.nkz; ++z) {
                     const cx<T> *sz = spec + (size_t)z * g.plane_elems;
                     T *oz = out + (size_t)((z + g.nkz / 2) & (g.nkz - 1)) * g.nky * pl.out_nx;
-#define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, w, acc, st)
+#define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, st)
                     LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
                 }
@@ -2463,42 +2495,48 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         mark(3);
         LH_HIP_TRY(col(pl.spec, g.nL, true));
         mark(4);
-        LH_HIP_TRY(p5(1.0, 0));
+        LH_HIP_TRY(p5(pl.spec));
     } else if (g.nL > 0) {
         // Eq. (2): sum over band pairs (nu occupied, mu empty).  The window
-        // pairs occupied slices (energies below j0) with empty ones only, so
-        // the cross term of (nu, mu) is the window of the spliced spectrum:
-        // the occupied slices of band nu followed by the empty ones of band mu.
+        // pairs occupied slices (energies below j0) with empty ones only and
+        // is bilinear in them, so sum_{nu,mu} w S(P_nu, H_mu) =
+        // sum_nu S(P_nu, sum_mu w H_mu): for every nu one window of a spliced
+        // spectrum -- the occupied slices of band nu followed by the weighted
+        // sum of the bands' empty slices -- and the window outputs summed
+        // (linear, so one pair of inverse passes serves them all).
         const size_t nocc = (size_t)(g.j0 - g.jA), nb = (size_t)pl.nb;
+        const size_t per = sb / sizeof(T);  // T values per slice
         char *bs = (char *)pl.bspec;
         for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(p1(bs + b * g.nS * sb, b, 0));
         mark(1);
         for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(col(bs + b * g.nS * sb, g.nS, false));
         mark(2);
+        char *sp = (char *)pl.spec;
+        const size_t nemp = (size_t)g.nS - nocc;
         int done = 0;
         for (size_t nu = 0; nu < nb; ++nu) {
+            int terms = 0;
             for (size_t mu = 0; mu < nb; ++mu) {
                 const double w = pl.pairw[nu * nb + mu];
-                if (w == 0.0) continue;
-                char *sp = (char *)pl.spec;
-                if (nocc > 0)
-                    LH_HIP_TRY(hipMemcpyAsync(sp, bs + nu * g.nS * sb, nocc * sb, hipMemcpyDeviceToDevice, st));
-                if ((size_t)g.nS > nocc)
-                    LH_HIP_TRY(hipMemcpyAsync(sp + nocc * sb, bs + (mu * g.nS + nocc) * sb, (g.nS - nocc) * sb,
-                                              hipMemcpyDeviceToDevice, st));
-                LH_HIP_TRY(window_t<T>(pl, st));
-                LH_HIP_TRY(col(pl.spec, g.nL, true));
-                LH_HIP_TRY(p5(w, done++ > 0));
+                if (w == 0.0 || nemp == 0) continue;
+                LH_HIP_TRY(launch_lin<T>((T *)(sp + nocc * sb), (const T *)(bs + (mu * g.nS + nocc) * sb), w,
+                                         terms++ == 0, nemp * per, st));
             }
+            if (terms == 0) continue;  // no empty band pairs with nu
+            if (nocc > 0) LH_HIP_TRY(hipMemcpyAsync(sp, bs + nu * g.nS * sb, nocc * sb, hipMemcpyDeviceToDevice, st));
+            LH_HIP_TRY(window_t<T>(pl, st));
+            LH_HIP_TRY(launch_lin<T>((T *)pl.sacc, (const T *)pl.spec, 1.0, done++ == 0, (size_t)g.nL * per, st));
         }
         mark(3);
+        LH_HIP_TRY(col(pl.sacc, g.nL, true));
         mark(4);
+        LH_HIP_TRY(p5(pl.sacc));
     } else {
         mark(1);
         mark(2);
         mark(3);
         mark(4);
-        if (!pl.p.want_rpa) LH_HIP_TRY(p5(1.0, 0));  // every plane is zero
+        if (!pl.p.want_rpa) LH_HIP_TRY(p5(pl.spec));  // every plane is zero
     }
     if (pl.p.want_rpa)
         hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
