@@ -149,6 +149,13 @@ lindhard_status lindhard_plan(const lindhard_problem *p, lindhard_plan_t *out);
 /* Copy the plan's derived quantities into *info.  EINVAL on NULL. */
 lindhard_status lindhard_plan_info(lindhard_plan_t plan, lindhard_info *info);
 
+/* Shape of the output arrays a problem would have (host only, no device
+ * work): nomega planes of out_ny rows of out_nx elements of elem_bytes bytes
+ * each (the buffers lindhard_serve_submit writes must have this shape).
+ * Errors: as lindhard_plan's validation (EINVAL, EOFFGRID). */
+lindhard_status lindhard_problem_shape(const lindhard_problem *p, int32_t *nomega, int32_t *out_ny, int32_t *out_nx,
+                                       int32_t *elem_bytes);
+
 /* Enqueue the whole hot path on `stream`: spectral builder + row FFT, column
  * FFT, energy-window product, inverse column FFT, inverse row FFT + scale +
  * form factor + zone writes into `im_chi` (device, out_elems elements of the

@@ -1006,6 +1006,20 @@ lindhard_status lindhard_plan(const lindhard_problem *p, lindhard_plan_t *out)
     return LINDHARD_OK;
 }
 
+lindhard_status lindhard_problem_shape(const lindhard_problem *p, int32_t *nomega, int32_t *out_ny, int32_t *out_nx,
+                                       int32_t *elem_bytes)
+{
+    if (!p || !nomega || !out_ny || !out_nx || !elem_bytes) return LINDHARD_EINVAL;
+    Plan pl;
+    const lindhard_status s = plan_describe(p, pl);
+    if (s != LINDHARD_OK) return s;
+    *nomega = pl.p.nomega;
+    *out_ny = pl.out_ny;
+    *out_nx = pl.out_nx;
+    *elem_bytes = (int32_t)pl.elem_bytes;
+    return LINDHARD_OK;
+}
+
 lindhard_status lindhard_plan_info(lindhard_plan_t plan, lindhard_info *info)
 {
     if (!plan || !info) return LINDHARD_EINVAL;

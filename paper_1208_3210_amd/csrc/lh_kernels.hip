@@ -1014,59 +1014,47 @@ __device__ __forceinline__ V vshift(V x)
     return x;
 }
 
-// Horner chains over a group of up to four e: the products of the group are
-// summed in the precision of the MFMA (64 products per FP32 partial sum) and
-// each group is folded once into the FP64 accumulator.  For e >= 0 the chain
-// runs from the largest e down with one-column right shifts in between and a
-// final right shift by the smallest e; for e < 0 it runs upwards with left
-// shifts.  Every shift of a chain moves the same way, so what leaves the
-// 16-column row has left the lag block for good.
-template <typename T, int E, int E0, bool CHECK>
-__device__ __forceinline__ void e3m_chain_r(const T *hb, const T (&b)[4], int e_lo, int e_hi,
-                                            typename MfmaVec<T>::V &x)
+// Horner chains over groups of four e: the products of a group are summed in
+// the precision of the MFMA (64 products per FP32 partial sum) and each group
+// is folded once into the FP64 accumulator.  A chain runs from the largest e
+// of its group down, with one-column right shifts in between and a final
+// right shift by the smallest e; every shift moves the same way, so what
+// leaves the 16-column row has left the lag block for good.
+// Four Horner chains at once (e from EA, EA + 4, EA + 8 and EA + 12 downwards,
+// N steps each), their products interleaved so that the matrix ops of one
+// chain run while the others wait for their results to be shifted.
+template <typename T, int EA>
+__device__ __forceinline__ void e3m_prod4(const T *hb, const T (&b)[4], typename MfmaVec<T>::V (&x)[4])
 {
-    if (!CHECK || (E >= e_lo && E <= e_hi)) x = e3m_prod<T, E>(hb, b, x);
-    if constexpr (E > E0) {
-        x = vshift<1>(x);
-        e3m_chain_r<T, E - 1, E0, CHECK>(hb, b, e_lo, e_hi, x);
-    }
-}
-template <typename T, int E, int E1, bool CHECK>
-__device__ __forceinline__ void e3m_chain_l(const T *hb, const T (&b)[4], int e_lo, int e_hi,
-                                            typename MfmaVec<T>::V &x)
-{
-    if (!CHECK || (E >= e_lo && E <= e_hi)) x = e3m_prod<T, E>(hb, b, x);
-    if constexpr (E < E1) {
-        x = vshift<-1>(x);
-        e3m_chain_l<T, E + 1, E1, CHECK>(hb, b, e_lo, e_hi, x);
-    }
-}
-
-// Group [E0, E1] (both >= 0, or both < 0).
-template <typename T, int E0, int E1, bool CHECK>
-__device__ __forceinline__ void e3m_group(const T *hb, const T (&b)[4], int e_lo, int e_hi, double (&acc)[4])
-{
-    if (CHECK && (e_hi < E0 || e_lo > E1)) return;  // wave-uniform
-    typename MfmaVec<T>::V x = {0, 0, 0, 0};
-    if constexpr (E0 >= 0) {
-        e3m_chain_r<T, E1, E0, CHECK>(hb, b, e_lo, e_hi, x);
-        x = vshift<E0>(x);
-    } else {
-        e3m_chain_l<T, E0, E1, CHECK>(hb, b, e_lo, e_hi, x);
-        x = vshift<E1>(x);
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] += (double)x[r];
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = mfma16x16x4(hb[16 * (EA + 4 * c) - 4 * s], b[s], x[c]);
+}
+template <typename T, int EA, int N>
+__device__ __forceinline__ void e3m_chain4(const T *hb, const T (&b)[4], typename MfmaVec<T>::V (&x)[4])
+{
+    e3m_prod4<T, EA>(hb, b, x);
+    if constexpr (N > 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = vshift<1>(x[c]);
+        e3m_chain4<T, EA - 1, N - 1>(hb, b, x);
+    }
 }
 
-// Every e in [0, 15] (the whole range is known to be needed).
+// Every e in [0, 15] (the whole range is known to be needed): the groups
+// [0, 3], [4, 7], [8, 11], [12, 15] as four interleaved chains, each group's
+// FP32 (or FP64) partial sum folded once into the FP64 accumulator.
 template <typename T>
 __device__ __forceinline__ void e3m_all(const T *hb, const T (&b)[4], double (&acc)[4])
 {
-    e3m_group<T, 0, 3, false>(hb, b, 0, 15, acc);
-    e3m_group<T, 4, 7, false>(hb, b, 0, 15, acc);
-    e3m_group<T, 8, 11, false>(hb, b, 0, 15, acc);
-    e3m_group<T, 12, 15, false>(hb, b, 0, 15, acc);
+    typename MfmaVec<T>::V x[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    e3m_chain4<T, 3, 4>(hb, b, x);
+    x[1] = vshift<4>(x[1]);
+    x[2] = vshift<8>(x[2]);
+    x[3] = vshift<12>(x[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += ((double)x[0][r] + (double)x[1][r]) + ((double)x[2][r] + (double)x[3][r]);
 }
 
 // One e alone, folded at once (the general ranges of e3m_some).

@@ -104,6 +104,7 @@ EXPORTS = [
     "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa",
     "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_q_average", "lindhard_peak_index",
     "lindhard_cut", "lindhard_high_symmetry_path", "lindhard_zone_envelope", "lindhard_exec_batch",
+    "lindhard_problem_shape",
     "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
     "lindhard_serve_wait", "lindhard_serve_cancel", "lindhard_serve_stats_get", "lindhard_serve_destroy",
     "lindhard_strerror",
@@ -133,6 +134,7 @@ def lib() -> ctypes.CDLL:
             L.lindhard_structure_factor.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp]
             L.lindhard_peak_index.argtypes = [_vp, _vp, _vp, _vp]
             L.lindhard_q_average.argtypes = [_vp, _vp, _vp, _vp]
+            L.lindhard_problem_shape.argtypes = [ctypes.POINTER(Problem)] + [ctypes.POINTER(ctypes.c_int32)] * 4
             _i32p = ctypes.POINTER(ctypes.c_int32)
             L.lindhard_cut.argtypes = [_vp, _vp, _i32p, _i32p, ctypes.c_int32, _vp, _vp]
             L.lindhard_high_symmetry_path.argtypes = [_vp, _i32p, _i32p, ctypes.c_int32, _i32p]
@@ -432,7 +434,12 @@ class Server:
         if math.isfinite(U):
             kw["want_rpa"] = True
         p, keep = make_problem(**kw)
-        info_probe = _probe_shape(kw)
+        try:
+            info_probe = problem_shape(p)
+        except LindhardError:
+            # an invalid problem: the server refuses it itself (and counts the
+            # refusal) before it touches the output, so a placeholder will do
+            info_probe = (1,)
         dtype = _dtype(p.precision)
         outs = {"im_chi": torch.empty(info_probe, dtype=dtype, device="cuda")}
         if math.isfinite(U):
@@ -479,6 +486,8 @@ class Server:
             pass
 
 
-def _probe_shape(kw) -> tuple:
-    zx, zy = kw.get("zones", (1, 1))
-    return (len(np.atleast_1d(kw["omega"])), zy * int(kw["nky"]), zx * int(kw["nkx"]))
+def problem_shape(problem: Problem) -> tuple:
+    """(nomega, out_ny, out_nx) of the output arrays of a problem (the library's own answer)."""
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    _check(lib().lindhard_problem_shape(ctypes.byref(problem), *[ctypes.byref(x) for x in v]), "lindhard_problem_shape")
+    return (v[0].value, v[1].value, v[2].value)

@@ -92,3 +92,20 @@ def test_null_handles_are_rejected():
     assert L.lindhard_plan_info(None, None) == -1
     assert L.lindhard_serve_create(None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.lindhard_serve_destroy(None) == -1
+
+
+def test_problem_shape_is_host_only():
+    """The output shape of a problem comes from the library without a device:
+    extended zones, a 3D grid (nkz blocks of rows), a grid of any size."""
+    from paper_1208_3210_amd import lindhard as LH
+
+    p, keep = LH.make_problem(**_base(zones=(3, 5)))
+    assert LH.problem_shape(p) == (32, 5 * 32, 3 * 32)
+    tab = np.zeros((4, 8, 16))
+    p, keep = LH.make_problem(**_base(nkx=16, nky=8, nkz=4, eps_table=tab))
+    assert LH.problem_shape(p) == (32, 4 * 8, 16)
+    p, keep = LH.make_problem(**_base(nkx=33, nky=17, eps_table=np.zeros((17, 33))))
+    assert LH.problem_shape(p) == (32, 17, 33)
+    p, keep = LH.make_problem(**_base(zones=(2, 1)))
+    with pytest.raises(LH.LindhardError):
+        LH.problem_shape(p)

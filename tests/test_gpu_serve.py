@@ -143,3 +143,31 @@ def test_exec_batch_equals_individual_runs():
             assert torch.equal(again, alone[rep % len(group)])
     for p in plans:
         p.close()
+
+
+def test_served_extended_forms_equal_alone():
+    """Jobs using the wider problem fields (several bands with pair weights,
+    a 3D grid, a grid that is not a power of two, omegas between lags) are
+    copied whole at submission: served results equal the same problems run
+    alone, bit for bit."""
+    d = 3.0 / 64
+    base = dict(neps=64, emin=-1.5, emax=1.5, gamma=0.08, filling=1.1, precision=LH.LINDHARD_FP32C)
+    jobs = [
+        dict(base, eps_table=W.multiband_tables(32, 2, seed=4), n_bands=2, nkx=32, nky=32,
+             pair_weight=np.array([[1.0, 0.3], [0.7, 0.2]]), omega=np.arange(1, 30, 4) * d),
+        dict(base, eps_table=W.band3d_table(16, 8, 4), nkz=4, nkx=16, nky=8, omega=np.arange(1, 30, 4) * d),
+        dict(base, eps_table=np.random.Generator(np.random.PCG64(2)).uniform(-1.2, 1.5, size=(17, 33)), nkx=33,
+             nky=17, omega=np.arange(1, 30, 4) * d),
+        dict(base, t=0.4, tp=-0.1, tpp=0.05, nkx=32, nky=32, omega_interp=True, omega=[2.5 * d, 7.25 * d, 30.9 * d]),
+    ]
+    srv = LH.Server(hbm_budget_bytes=4 << 30, max_inflight=4, max_queue=16)
+    tickets = [srv.submit(float("nan"), **j) for j in jobs]
+    for t, _ in tickets:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    for j, (t, outs) in zip(jobs, tickets):
+        plan = LH.Plan(**j)
+        alone = plan.exec()
+        torch.cuda.synchronize()
+        assert torch.equal(outs["im_chi"], alone), t
+        plan.close()
+    srv.close()
