@@ -341,7 +341,9 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         g.logCe = ilog2(g.Ce);
         g.NTe = (g.L + 1 + g.Ce - 1) / g.Ce;
         g.Hy = p->nky / 2 + 1;
-        g.slice_e = (size_t)g.NTe * g.Hy * g.Ce;
+        // groups of four rows (the rows of a row-pair block) start on 128-byte lines
+        g.HyS = (g.Hy + 3) & ~3;
+        g.slice_e = (size_t)g.NTe * g.HyS * g.Ce;
         const int np = (g.Hy + 1) / 2;
         // row pairs per block for register FFTs of E elements per thread
         auto rows_per_block = [&](int E) {
@@ -978,6 +980,14 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     }
     if (pl.p.want_rpa)
         LH_TRY(hipMemsetAsync(pl.im1, 0, (size_t)pl.g.neps * nk * pl.elem_bytes, st));
+    if (pl.g.even) {
+        // the padding rows of the tiles (ry >= Hy) are carried through the
+        // window but never read back; keep them zero rather than stale
+        const size_t sl = pl.g.slice_e * pl.elem_bytes;
+        LH_TRY(hipMemsetAsync(pl.spec, 0, (size_t)pl.g.nslots * sl, st));
+        if (pl.bspec) LH_TRY(hipMemsetAsync(pl.bspec, 0, (size_t)pl.nb * pl.g.nS * sl, st));
+        if (pl.sacc) LH_TRY(hipMemsetAsync(pl.sacc, 0, (size_t)pl.g.nL * sl, st));
+    }
     LH_TRY(hipStreamSynchronize(st));
     s = autotune_window(pl, st);
     if (s != LINDHARD_OK) return s;

@@ -49,10 +49,11 @@ struct Geo {
     // mirror-symmetric band (eps(kx,ky) = eps(-kx,ky) = eps(kx,-ky)): every
     // real-space function is real and even, so the slices hold real values on
     // the quarter rx in [0, nkx/2], ry in [0, nky/2]:
-    //   element (s, rx, ry) at ((s * NTe + rx / Ce) * Hy + ry) * Ce + rx % Ce,
+    //   element (s, rx, ry) at ((s * NTe + rx / Ce) * HyS + ry) * Ce + rx % Ce,
     // Ce = 32 bytes of reals, NTe = ceil((nkx/2 + 1) / Ce), Hy = nky/2 + 1.
     int even;
     int Ce, logCe, NTe, Hy;
+    int HyS;                  // row stride of a tile: Hy rounded up to 4 rows (128 bytes)
     size_t slice_e;
     int e1_R, e1_jc;          // row pairs per block, slices per block
     int e3_TR, e3_logTR;      // real-space points per block, even window

@@ -728,7 +728,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
                 const cx<T> z = zl[min(rx, H)];
                 o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
             }
-            lh_u4 *op = reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.Hy + ky) * Ce + h * VEC);
+            lh_u4 *op = reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.HyS + ky) * Ce + h * VEC);
             if (acc) {  // add this band to the earlier ones
                 const Vec16<T> old = __builtin_bit_cast(Vec16<T>, *op);
 #pragma unroll
@@ -762,7 +762,7 @@ __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const
     const bool active = tile < g.NTe;
     const int Hy = g.Hy;
     cx<T> *base = reinterpret_cast<cx<T> *>(spec + (size_t)blockIdx.y * g.slice_e +
-                                            (size_t)(active ? tile : 0) * Hy * (2 * C));
+                                            (size_t)(active ? tile : 0) * g.HyS * (2 * C));
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -1382,7 +1382,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
             const int tile = (it >> logHV) >> logRows;
             const int qy = 2 * p0 + r;
             const bool ok = it < nvec && qy < Hy;
-            const size_t o = ok ? ((size_t)tile * Hy + qy) * Ce + h * VEC : 0;
+            const size_t o = ok ? ((size_t)tile * g.HyS + qy) * Ce + h * VEC : 0;
             v[k] = __builtin_bit_cast(Vec16<T>, *reinterpret_cast<const lh_u4 *>(src + o));
             if (blend) {
                 const Vec16<T> y = __builtin_bit_cast(Vec16<T>, *reinterpret_cast<const lh_u4 *>(src2 + o));
