@@ -88,6 +88,11 @@ def test_null_handles_are_rejected():
     assert L.lindhard_structure_factor(None, 0.01, None, None, None) == -1
     assert L.lindhard_peak_index(None, None, None, None) == -1
     assert L.lindhard_q_average(None, None, None, None) == -1
+    assert L.lindhard_cut(None, None, None, None, 1, None, None) == -1
+    n = ctypes.c_int32(0)
+    assert L.lindhard_high_symmetry_path(None, None, None, 0, ctypes.byref(n)) == -1
+    assert L.lindhard_zone_envelope(None, None, 0, 0, 1.0, None, None) == -1
+    assert L.lindhard_problem_shape(None, None, None, None, None) == -1
     assert L.lindhard_plan_destroy(None) == -1
     assert L.lindhard_plan_info(None, None) == -1
     assert L.lindhard_serve_create(None, ctypes.byref(ctypes.c_void_p())) == -1
@@ -109,3 +114,34 @@ def test_problem_shape_is_host_only():
     p, keep = LH.make_problem(**_base(zones=(2, 1)))
     with pytest.raises(LH.LindhardError):
         LH.problem_shape(p)
+
+
+@pytest.mark.parametrize("over", [
+    dict(n_bands=2),                                                   # several bands need a table
+    dict(n_bands=2, eps_table=np.zeros((2, 32, 32)), pair_weight=np.zeros((2, 2))),
+    dict(n_bands=2, eps_table=np.zeros((2, 32, 32)), pair_weight=-np.ones((2, 2))),
+    dict(n_bands=9, eps_table=np.zeros((9, 32, 32))),
+    dict(nkz=3, eps_table=np.zeros((3, 32, 32))),                      # kz count not a power of two
+    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), zones=(3, 1)),        # 3D takes one zone
+    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), want_rpa=True),
+    dict(nkx=33, eps_table=np.zeros((32, 33)), ff_kind=1, ff_width=0.6),  # any size: no form factor
+    dict(nkx=2049, eps_table=np.zeros((32, 2049))),                    # FP64 any size up to 2048
+    dict(omega=[1.5 / 32.0], omega_interp=False),
+    dict(omega=[-1.0 / 32.0], omega_interp=True),
+])
+def test_widened_forms_validated_on_the_host(over):
+    """The several-band, 3D, any-size and off-grid rules are checked before any
+    device work (the output-shape query runs the same validation)."""
+    from paper_1208_3210_amd import lindhard as LH
+
+    p, keep = LH.make_problem(**_base(**over))
+    with pytest.raises(LH.LindhardError) as ei:
+        LH.problem_shape(p)
+    assert ei.value.status in (-1, -2)
+
+
+def test_offgrid_omega_accepted_with_interp_on_the_host():
+    from paper_1208_3210_amd import lindhard as LH
+
+    p, keep = LH.make_problem(**_base(omega=[1.5 / 32.0, 2.0 / 32.0], omega_interp=True))
+    assert LH.problem_shape(p) == (2, 32, 32)
