@@ -75,13 +75,13 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
 {
     if (!p) return LINDHARD_EINVAL;
     if (p->precision != LINDHARD_FP32C && p->precision != LINDHARD_FP64) return LINDHARD_EINVAL;
-    // powers of two up to 2048; other sizes (Bluestein transforms) up to 4096
-    // in FP32 and 2048 in FP64, one zone, one band, no form factor, no RPA
+    // powers of two up to 2048; other sizes (Bluestein transforms) up to 4097
+    // in FP32 and 2049 in FP64, one zone, one band, no form factor, no RPA
     const bool any_size = !is_pow2(p->nkx) || !is_pow2(p->nky);
     if (p->nkx < 4 || p->nky < 4) return LINDHARD_EINVAL;
     if (!any_size && (p->nkx > 2048 || p->nky > 2048)) return LINDHARD_EINVAL;
     if (any_size) {
-        const int lim = p->precision == LINDHARD_FP64 ? 2048 : 4096;
+        const int lim = p->precision == LINDHARD_FP64 ? 2049 : 4097;
         if (p->nkx > lim || p->nky > lim) return LINDHARD_EINVAL;
         if (p->zones_x != 1 || p->zones_y != 1 || p->ff_kind != LINDHARD_FF_NONE || p->want_rpa || p->nkz > 1 ||
             p->n_bands > 1 || p->pair_weight)
@@ -166,8 +166,10 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             while ((1 << l) < v) ++l;
             return l;
         };
-        g.logMx = clog2(2 * p->nkx - 1);
-        g.logMy = clog2(2 * p->nky - 1);
+        // the chirp is even (b_-m = b_m), so the lags -(N-1) and N-1 may share
+        // one place: a circular convolution of length 2N - 2 suffices
+        g.logMx = clog2(2 * p->nkx - 2);
+        g.logMy = clog2(2 * p->nky - 2);
         const size_t cs = g.fp64 ? 16 : 8;
         auto lines = [&](int logM, int cap) {
             const int M = 1 << logM, E = std::min(16, M), G = M / E;
@@ -875,7 +877,8 @@ static void fft_host(std::vector<std::complex<double>> &a)
 
 // Bluestein tables of one axis of length n (a grid of any size): chirp
 // b_k = exp(i pi (k^2 mod 2n) / n), the spectra FFT_M(B) / M and FFT_M(conj B) / M
-// of the chirp sequence B (B_m = b_m = B_(M-m) for m < n, zero between), and
+// of the chirp sequence B (B_m = b_m = B_(M-m) for m < n, zero between; with
+// M = 2n - 2 the place n - 1 serves both m = n - 1 and m = -(n - 1)), and
 // the FFT twiddles exp(-2 pi i s / M); FP64, rounded once to the precision.
 // `keep` holds the host arrays until the copies have run.
 static hipError_t bs_tables(const Plan &pl, int n, int logM, void *const *dst, hipStream_t st,

@@ -1865,7 +1865,8 @@ __global__ void __launch_bounds__(kThreads) k_envelope(const T *__restrict__ im,
 // A transform of length N that is not a power of two runs as Bluestein's
 // chirp convolution: with b_n = exp(i pi n^2 / N), the forward transform is
 // X_k = conj(b_k) sum_n (x_n conj(b_n)) b_(k-n), a circular convolution of
-// length M = 2^logM >= 2N - 1 done with two register FFTs of length M.  The
+// length M = 2^logM >= 2N - 2 done with two register FFTs of length M (the
+// chirp is even in k - n, so the lags -(N-1) and N-1 may share one place).  The
 // tables of one axis (built in FP64 on the host, rounded once): chirp b_n
 // (n < N) and the spectra hf = FFT_M(B) / M, hi = FFT_M(conj B) / M of the
 // chirp sequence B (B_m = b_m, B_(M-m) = b_m, zero between) for the forward

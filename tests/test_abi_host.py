@@ -47,7 +47,7 @@ def _base(**over):
 
 
 @pytest.mark.parametrize("over,status", [
-    (dict(nkx=48, zones=(3, 1)), -1), (dict(nkx=2049), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
+    (dict(nkx=48, zones=(3, 1)), -1), (dict(nkx=2050), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
     (dict(nkx=4096), -1), (dict(nkx=48, want_rpa=True), -1), (dict(neps=100), -1), (dict(neps=2), -1),
     (dict(emin=0.1), -1), (dict(emax=-0.1), -1), (dict(gamma=0.0), -1), (dict(gamma=math.nan), -1),
     (dict(precision=3), -1), (dict(zones=(2, 1)), -1), (dict(zones=(1, 0)), -1), (dict(ff_kind=7), -1),
@@ -125,7 +125,7 @@ def test_problem_shape_is_host_only():
     dict(nkz=4, eps_table=np.zeros((4, 32, 32)), zones=(3, 1)),        # 3D takes one zone
     dict(nkz=4, eps_table=np.zeros((4, 32, 32)), want_rpa=True),
     dict(nkx=33, eps_table=np.zeros((32, 33)), ff_kind=1, ff_width=0.6),  # any size: no form factor
-    dict(nkx=2049, eps_table=np.zeros((32, 2049))),                    # FP64 any size up to 2048
+    dict(nkx=2050, eps_table=np.zeros((32, 2050))),                    # FP64 any size up to 2049
     dict(omega=[1.5 / 32.0], omega_interp=False),
     dict(omega=[-1.0 / 32.0], omega_interp=True),
 ])

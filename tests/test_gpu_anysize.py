@@ -92,9 +92,10 @@ def test_extended_momentum_closed_style_grid(prec):
 
 
 @pytest.mark.parametrize("prec,nkx,nky", [(LH.LINDHARD_FP32C, 2049, 6), (LH.LINDHARD_FP64, 1000, 6),
-                                          (LH.LINDHARD_FP32C, 6, 2049)])
+                                          (LH.LINDHARD_FP32C, 6, 2049), (LH.LINDHARD_FP64, 2049, 4),
+                                          (LH.LINDHARD_FP32C, 4097, 4)])
 def test_long_axes_sampled(prec, nkx, nky):
-    """The longest transforms (2049 points: Bluestein length 8192), checked on
+    """Long transforms (2049 points: Bluestein length 4096), checked on
     sampled (q, omega) points the oracle computes one by one."""
     rng = np.random.Generator(np.random.PCG64(5))
     tab = rng.uniform(-1.2, 1.5, size=(nky, nkx))
@@ -126,7 +127,7 @@ def test_any_size_argument_errors():
         with pytest.raises(LH.LindhardError) as ei:
             LH.Plan(precision=LH.LINDHARD_FP32C, **dict(base, **bad))
         assert ei.value.status == LH.LINDHARD_EINVAL
-    for prec, n in ((LH.LINDHARD_FP32C, 4097), (LH.LINDHARD_FP64, 2049)):
+    for prec, n in ((LH.LINDHARD_FP32C, 4098), (LH.LINDHARD_FP64, 2050)):
         with pytest.raises(LH.LindhardError) as ei:
             LH.Plan(precision=prec, **dict(base, nkx=n, nky=4, eps_table=np.zeros((4, n))))
         assert ei.value.status == LH.LINDHARD_EINVAL
