@@ -179,6 +179,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         };
         g.bs_Rr = lines(g.logMx, (p->nky + 1) / 2);
         g.bs_Rc = lines(g.logMy, g.NT * g.C);
+        g.bs_SJ = 8;
     }
     g.neps = p->neps;
     g.j0 = count_occupied(p->neps, p->emin, p->emax);

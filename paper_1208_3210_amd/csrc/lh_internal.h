@@ -73,8 +73,9 @@ struct Geo {
     int tuned;                // 1: window schedule chosen by timing, 2: from the tuning cache
     // grids of any size (bs = 1): Bluestein transforms of length 2^logMx,
     // 2^logMy; bs_Rr rows per block in the row passes, bs_Rc columns per
-    // block in the column passes
-    int bs, logMx, logMy, bs_Rr, bs_Rc;
+    // block in the column passes, bs_SJ energy slices (or lags) per block in
+    // the column passes
+    int bs, logMx, logMy, bs_Rr, bs_Rc, bs_SJ;
 };
 
 // Elements per thread of the register FFTs in the even builder pass (the

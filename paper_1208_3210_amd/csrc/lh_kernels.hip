@@ -1876,6 +1876,49 @@ struct BsTab {
     int n;
 };
 
+// Launch index -> work index such that grp consecutive work items (which
+// share cache lines) run on one XCD: blocks are dispatched round-robin over the
+// 8 XCDs, launch index b on XCD b mod 8.  The grid is padded to a multiple of
+// 8 grp blocks; the caller skips work indices past its range.
+__device__ __forceinline__ int xcd_group(int b, int grp)
+{
+    const int xcd = b & 7, i = b >> 3;
+    return ((i / grp) * 8 + xcd) * grp + i % grp;
+}
+
+// A zero the optimiser cannot see through.  Added to a thread's position in
+// a loop body it keeps the loads and LDS addresses that depend on it inside
+// the loop, rather than hoisted out and held in registers across it.
+__device__ __forceinline__ int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+// FP32 up to M = 4096: the FFT twiddles of an axis copied into LDS after the
+// block's R line buffers (M values), so that every pass reads them from LDS
+// rather than waiting on the cache.  FP64 and longer lines keep them in
+// global memory (the table would take the block past 64 KB of LDS).
+template <typename T, int LOGM>
+__host__ __device__ constexpr bool bs_tw_lds()
+{
+    return sizeof(T) == 4 && LOGM <= 12;
+}
+// Every thread of the block calls it.
+template <typename T, int M>
+__device__ __forceinline__ BsTab bs_lds_twiddles(BsTab t, cx<T> *lds, int R, int tid, int nthr)
+{
+    if constexpr (bs_tw_lds<T, ilog2_c(M)>()) {
+        cx<T> *twl = lds + R * M;
+        const cx<T> *tw = (const cx<T> *)t.tw;
+        for (int i = tid; i < M; i += nthr) twl[i] = tw[i];
+        __syncthreads();
+        t.tw = twl;
+    }
+    return t;
+}
+
 // v[s] = x[g + s G] (zero for n >= N) -> the DFT of length N (INV: inverse,
 // no 1/N) in the same places.  Every thread of the block calls it.
 template <typename T, int LOGM, bool INV>
@@ -1908,6 +1951,10 @@ __device__ __forceinline__ void bs_line(cx<T> *v, cx<T> *buf, const BsTab &t, in
 // X(2p+1)_k = (Z_k - conj Z_(N-k)) / 2i; the rows are real, so only the
 // columns kx <= nkx / 2 are kept (the others are conjugates), written to the
 // column-tiled array (NT = ceil((nkx / 2 + 1) / C) tiles, padding columns 0).
+// Two row pairs fill the 128-byte lines of a tile, so with one line per
+// block the two blocks of a pair run on one XCD.  The twiddles stay in global
+// memory here: this pass is bound by how many lines a CU holds, and a table in
+// LDS would cost a third of them.
 template <typename T, int LOGM, bool W>
 __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                double gamma, BsTab tx, cx<T> *__restrict__ spec,
@@ -1919,7 +1966,9 @@ __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, G
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
     const int R = g.bs_Rr;
     const int tid = threadIdx.x, line = tid / G, gg = tid % G;
-    const int p = blockIdx.x * R + line;          // row pair
+    const int w = xcd_group(blockIdx.x, R >= 2 ? 1 : 2);
+    if (w * R >= (g.nky + 1) / 2) return;  // padding block (block-uniform)
+    const int p = w * R + line;              // row pair
     const int ka = min(2 * p, g.nky - 1), kb = min(2 * p + 1, g.nky - 1);
     const bool hasa = 2 * p < g.nky, hasb = 2 * p + 1 < g.nky;
     const int j = g.jA + blockIdx.y;
@@ -1966,10 +2015,12 @@ __global__ void __launch_bounds__(512) k_bs_row(const double *__restrict__ xi, G
 }
 
 // Column pass, any size: lines along ky (stride C in a tile), one per
-// column (tile, c); R lines per block, lane-interleaved so that a wave's
-// loads cover neighbouring columns.  Transformed in place.
+// column (tile, c), for bs_SJ slices; R lines per block, lane-interleaved so
+// that a wave's loads cover neighbouring columns.  In FP32 the next slice's
+// column is loaded while the current one is transformed.  When R < C the C / R blocks of one tile (whose 32-byte
+// rows share 128-byte lines) run on one XCD.  Transformed in place.
 template <typename T, int LOGM, bool INV>
-__global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g, BsTab ty)
+__global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g, BsTab ty, int nslices)
 {
     using F = RegFFT<T, LOGM, false>;
     constexpr int M = F::N, E = F::E, G = F::G;
@@ -1977,23 +2028,42 @@ __global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g,
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
     const int R = g.bs_Rc;
     const int tid = threadIdx.x, line = tid % R, gg = tid / R;
-    const int col = blockIdx.x * R + line;  // tile * C + c
     const int ncol = g.NT * g.C;
+    const int w = xcd_group(blockIdx.x, R >= g.C ? 1 : g.C / R);
+    if (w * R >= ncol) return;  // padding block (block-uniform)
+    const int col = w * R + line;  // tile * C + c
     const bool active = col < ncol;
     const int tile = (active ? col : 0) >> g.logC, c = (active ? col : 0) & (g.C - 1);
-    cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)tile * g.nky * g.C + c;
-    cx<T> v[E];
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-        const int n = gg + s * G;
-        v[s] = (active && n < g.nky) ? base[(size_t)n * g.C] : mk<T>((T)0, (T)0);
-    }
-    bs_line<T, LOGM, INV>(v, lds + line * M, ty, gg, lds_xor_interleaved<T, M>(line, R));
-    if (active) {
+    cx<T> *base0 = spec + (size_t)tile * g.nky * g.C + c;
+    const int lx = lds_xor_interleaved<T, M>(line, R);
+    const int j0 = blockIdx.y * g.bs_SJ, j1 = min(nslices, j0 + g.bs_SJ);
+    const BsTab tl = bs_lds_twiddles<T, M>(ty, lds, R, tid, R * G);
+    constexpr bool PF = sizeof(T) == 4;  // FP64 has no registers to spare for the prefetch
+    cx<T> nx[E];
+    auto load = [&](int j, int go) {
+        const cx<T> *base = base0 + (size_t)j * g.slice_elems;
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            const int k = gg + s * G;
-            if (k < g.nky) base[(size_t)k * g.C] = v[s];
+            const int n = go + s * G;
+            nx[s] = (active && n < g.nky) ? base[(size_t)n * g.C] : mk<T>((T)0, (T)0);
+        }
+    };
+    if (PF) load(j0, gg);
+    for (int j = j0; j < j1; ++j) {
+        const int go = gg + opaque_zero();
+        if (!PF) load(j, go);
+        cx<T> v[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = nx[s];
+        if (PF && j + 1 < j1) load(j + 1, go);
+        bs_line<T, LOGM, INV>(v, lds + line * M, tl, go, lx);
+        if (active) {
+            cx<T> *base = base0 + (size_t)j * g.slice_elems;
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int k = go + s * G;
+                if (k < g.nky) base[(size_t)k * g.C] = v[s];
+            }
         }
     }
 }
@@ -2017,7 +2087,9 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
     const int R = g.bs_Rr;
     const int tid = threadIdx.x, line = tid / G, gg = tid % G;
     const int plane = blockIdx.y;
-    const int p = blockIdx.x * R + line;
+    const int w = xcd_group(blockIdx.x, R >= 2 ? 1 : 2);  // as in k_bs_row
+    if (w * R >= (g.nky + 1) / 2) return;                  // padding block (block-uniform)
+    const int p = w * R + line;
     const int qa = min(2 * p, g.nky - 1), qb = min(2 * p + 1, g.nky - 1);
     const bool hasa = 2 * p < g.nky, hasb = 2 * p + 1 < g.nky;
     const int nkx = g.nkx, nky = g.nky, H = nkx / 2;
@@ -2031,6 +2103,7 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
         }
         return;
     }
+    const BsTab tl = bs_lds_twiddles<T, M>(tx, lds, R, tid, R * G);
     const cx<T> *src = spec + (size_t)ps.a * g.slice_elems;
     const cx<T> *src2 = spec + (size_t)(ps.b >= 0 ? ps.b : ps.a) * g.slice_elems;
     const bool blend = ps.b >= 0 || ps.wa != 1.0;
@@ -2063,7 +2136,7 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
         }
         v[s] = z;
     }
-    bs_line<T, LOGM, true>(v, lds + line * M, tx, gg, lds_xor_gfast<M, G>(line));
+    bs_line<T, LOGM, true>(v, lds + line * M, tl, gg, lds_xor_gfast<M, G>(line));
     const T sc = (T)scale;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -2078,6 +2151,8 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
 
 // ---------------------------------------------------------------- launchers
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+// n blocks padded for xcd_group with groups of grp
+static inline unsigned xcd_grid(unsigned n, int grp) { return cdiv(n, 8L * grp) * 8u * (unsigned)grp; }
 
 hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st)
 {
@@ -2309,7 +2384,7 @@ static void launch_bs_row(const Plan &pl, cx<T> *spec, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.nS);
+    const dim3 grid(xcd_grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.bs_Rr >= 2 ? 1 : 2), g.nS);
     const size_t lds = (size_t)g.bs_Rr * F::N * sizeof(cx<T>);
     if (pl.rho)
         hipLaunchKernelGGL((k_bs_row<T, LOGM, true>), grid, dim3(g.bs_Rr * F::G), lds, st, pl.xi, g, pl.p.emin,
@@ -2324,9 +2399,11 @@ static void launch_bs_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t 
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(cdiv((long)g.NT * g.C, g.bs_Rc), nslices);
-    hipLaunchKernelGGL((k_bs_col<T, LOGM, INV>), grid, dim3(g.bs_Rc * F::G), (size_t)g.bs_Rc * F::N * sizeof(cx<T>),
-                       st, spec, g, bs_tab(pl, true));
+    const dim3 grid(xcd_grid(cdiv((long)g.NT * g.C, g.bs_Rc), g.bs_Rc >= g.C ? 1 : g.C / g.bs_Rc),
+                    cdiv(nslices, g.bs_SJ));
+    const size_t lds = (size_t)(g.bs_Rc + (bs_tw_lds<T, LOGM>() ? 1 : 0)) * F::N * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_bs_col<T, LOGM, INV>), grid, dim3(g.bs_Rc * F::G), lds, st, spec, g, bs_tab(pl, true),
+                       nslices);
 }
 
 template <typename T, int LOGM>
@@ -2334,9 +2411,10 @@ static void launch_bs_p5(const Plan &pl, const cx<T> *spec, T *out, hipStream_t 
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(cdiv((g.nky + 1) / 2, g.bs_Rr), pl.p.nomega);
-    hipLaunchKernelGGL((k_bs_p5<T, LOGM>), grid, dim3(g.bs_Rr * F::G), (size_t)g.bs_Rr * F::N * sizeof(cx<T>), st,
-                       spec, g, bs_tab(pl, false), pl.d_src, pl.scale, out);
+    const dim3 grid(xcd_grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.bs_Rr >= 2 ? 1 : 2), pl.p.nomega);
+    const size_t lds = (size_t)(g.bs_Rr + (bs_tw_lds<T, LOGM>() ? 1 : 0)) * F::N * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_bs_p5<T, LOGM>), grid, dim3(g.bs_Rr * F::G), lds, st, spec, g, bs_tab(pl, false), pl.d_src,
+                       pl.scale, out);
 }
 
 // Grids of any size: Bluestein row and column passes around the same window.
