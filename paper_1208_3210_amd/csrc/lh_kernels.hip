@@ -185,6 +185,29 @@ __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2
     return F * F;
 }
 
+// FP32: an FFT twiddle table of n values copied into LDS at dst, so that the
+// transform passes read it there rather than waiting on the cache for every
+// pass; returns the table to use.  FP64 keeps the global table (it would
+// double the LDS of the blocks that use it).  Every thread of the block calls
+// it (it ends with a barrier when it copies).
+template <typename T>
+__device__ __forceinline__ const cx<T> *tw_to_lds(const cx<T> *tw, cx<T> *dst, int n, int tid, int nthr)
+{
+    if constexpr (sizeof(T) == 4) {
+        for (int i = tid; i < n; i += nthr) dst[i] = tw[i];
+        __syncthreads();
+        return dst;
+    } else {
+        return tw;
+    }
+}
+// LDS bytes of such a table
+template <typename T>
+constexpr size_t tw_lds_bytes(int n)
+{
+    return sizeof(T) == 4 ? (size_t)n * sizeof(cx<T>) : 0;
+}
+
 // ---------------------------------------------------------------- P1
 // One block: R rows (ky) of the spectral function for jc consecutive energy
 // slices; G = L/E threads per row.  Row kx of length nkx is packed as
@@ -208,6 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
     const int jbeg = g.jA + blockIdx.y * g.p1_jc;
     const int jend = min(g.jB, jbeg + g.p1_jc);
     cx<T> *buf = lds + row * L;
+    const cx<T> *tw = tw_to_lds<T>(twx, lds + R * L, 2 * L, tid, R * G);
 
     double xa[E], xb[E];
     T ra[W ? E : 1], rb[W ? E : 1];  // momentum-density weights (W)
@@ -239,7 +263,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
             else
                 v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
-        F::run(v, buf, twx, 1, gg, lds_xor_gfast<L, G>(row));
+        F::run(v, buf, tw, 1, gg, lds_xor_gfast<L, G>(row));
 #pragma unroll
         for (int s = 0; s < E; ++s) buf[swz(gg + s * G)] = v[s];
         __syncthreads();
@@ -255,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
                 const cx<T> ZL = cconj(lds[r * L + swz((L - k) & (L - 1))]);
                 const cx<T> Ev = cscale(cadd(Zk, ZL), (T)0.5);
                 const cx<T> D = cscale(csub(Zk, ZL), (T)0.5);
-                const cx<T> w = twx[k];
+                const cx<T> w = tw[k];
                 X = cadd(Ev, cmul(mk<T>(w.y, -w.x), D));
             }
             cx<T> *o = dst + ((size_t)tile * g.nky + ky0 + r) * C + c;
@@ -286,11 +310,12 @@ __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, co
     const int tb = line / C, c = line % C;
     const int tile = blockIdx.x * TPB + tb;  // tiles of every kz plane (three dimensions)
     const bool active = tile < g.NT * g.nkz;
+    const cx<T> *tw = tw_to_lds<T>(twy, lds + NL * N, N, tid, NL * G);
     cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)(active ? tile : 0) * N * C;
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) v[s] = active ? base[(gg + s * G) * C + c] : mk<T>((T)0, (T)0);
-    F::run(v, lds + line * N, twy, 0, gg, lds_xor_interleaved<T, N>(line, NL));
+    F::run(v, lds + line * N, tw, 0, gg, lds_xor_interleaved<T, N>(line, NL));
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) base[(gg + s * G) * C + c] = v[s];
@@ -564,6 +589,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         }
         return;
     }
+    const cx<T> *tw = tw_to_lds<T>(twx, lds + R * (L + 1), 2 * L, tid, nthr);
 
     const int C = g.C, logC = g.logC;
     const cx<T> *src = spec + (size_t)slot * g.slice_elems;
@@ -606,11 +632,11 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         const cx<T> XL = cconj(xb[L - k]);
         const cx<T> A = cadd(Xk, XL);
         const cx<T> D = csub(Xk, XL);
-        const cx<T> wD = cmul(cconj(twx[k]), D);  // e^{+2 pi i k / nkx} D
+        const cx<T> wD = cmul(cconj(tw[k]), D);  // e^{+2 pi i k / nkx} D
         v[s] = cadd(A, mk<T>(-wD.y, wD.x));      // A + i w D
     }
     __syncthreads();
-    F::run(v, xb, twx, 1, gg, lds_xor_gfast<L, G>(row));
+    F::run(v, xb, tw, 1, gg, lds_xor_gfast<L, G>(row));
 
     const T sc = (T)scale;
     const int qy = qy0 + row;
@@ -761,6 +787,9 @@ __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const
     const int tile = blockIdx.x * TPB + tb;
     const bool active = tile < g.NTe;
     const int Hy = g.Hy;
+    // twiddles first: the barrier that ends the copy then does not wait for
+    // the column loads as well
+    const cx<T> *tw = tw_to_lds<T>(twy, lds + NL * N, N, tid, NL * G);
     cx<T> *base = reinterpret_cast<cx<T> *>(spec + (size_t)blockIdx.y * g.slice_e +
                                             (size_t)(active ? tile : 0) * g.HyS * (2 * C));
     cx<T> v[E];
@@ -770,7 +799,7 @@ __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const
         const int row = ky <= N / 2 ? ky : N - ky;
         v[s] = active ? base[row * C + c] : mk<T>((T)0, (T)0);
     }
-    F::run(v, lds + line * N, twy, 0, gg, lds_xor_interleaved<T, N>(line, NL));
+    F::run(v, lds + line * N, tw, 0, gg, lds_xor_interleaved<T, N>(line, NL));
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) {
@@ -2218,7 +2247,7 @@ static void launch_p1(const Plan &pl, cx<T> *spec, int band, int z, int acc, hip
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, false>;
     const dim3 grid(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc));
-    const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>);
+    const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N);
     // band `band`, kz plane z of the table; the plane's spectrum at spec
     const size_t nk = (size_t)g.nkx * g.nky * g.nkz, off = band * nk + (size_t)z * g.nkx * g.nky;
     const double *xi = pl.xi + off;
@@ -2238,7 +2267,8 @@ static void launch_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st)
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
     hipLaunchKernelGGL((k_col<T, LOGN, INV>), dim3(cdiv(g.NT * g.nkz, TPB), nslices), dim3(F::G * TPB * C),
-                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twy);
+                       (size_t)TPB * C * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(F::N), st, spec, g,
+                       (const cx<T> *)pl.twy);
 }
 
 template <typename T, int LOGN, bool INV>
@@ -2268,7 +2298,7 @@ static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, in
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
-                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
+                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
                        pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
 }
 
@@ -2298,7 +2328,8 @@ static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
     hipLaunchKernelGGL((k_ecol<T, LOGN, INV>), dim3(cdiv(g.NTe, TPB), nslices), dim3(F::G * TPB * C),
-                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twy);
+                       (size_t)TPB * C * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(F::N), st, spec, g,
+                       (const cx<T> *)pl.twy);
 }
 
 template <typename T, int LOGNX, int MODE>
