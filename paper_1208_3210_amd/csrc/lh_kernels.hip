@@ -340,11 +340,12 @@ __global__ void __launch_bounds__(512) k_zcol(cx<T> *__restrict__ spec, Geo g, c
     const int line = tid % NL, gg = tid / NL;
     const int grp = blockIdx.x * TPB + line / C, c = line % C;
     const bool active = grp < g.NT * g.nky;
+    const cx<T> *tw = tw_to_lds<T>(twz, lds + NL * N, N, tid, NL * G);
     cx<T> *base = spec + (size_t)blockIdx.y * g.slice_elems + (size_t)(active ? grp : 0) * C + c;
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) v[s] = active ? base[(size_t)(gg + s * G) * g.plane_elems] : mk<T>((T)0, (T)0);
-    F::run(v, lds + line * N, twz, 0, gg, lds_xor_interleaved<T, N>(line, NL));
+    F::run(v, lds + line * N, tw, 0, gg, lds_xor_interleaved<T, N>(line, NL));
     if (active) {
 #pragma unroll
         for (int s = 0; s < E; ++s) base[(size_t)(gg + s * G) * g.plane_elems] = v[s];
@@ -509,6 +510,7 @@ __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, co
     const int ne = g.nS;
     const int j0 = g.j0 - g.jA;
     const int nthr = TR * G;
+    const cx<T> *tw = tw_to_lds<T>(twe, lds + TR * N, N, tid, nthr);
     for (int it0 = tid; it0 < (ne << logTR); it0 += 8 * nthr) {
         cx<T> v[8];
 #pragma unroll
@@ -534,14 +536,14 @@ __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, co
     __syncthreads();
     cx<T> *buf = lds + rp * N;
     const int lxe = lds_xor_interleaved<T, N>(rp, TR);
-    FF::run(vp, buf, twe, 0, gg, lxe);
-    FF::run(vh, buf, twe, 0, gg, lxe);
+    FF::run(vp, buf, tw, 0, gg, lxe);
+    FF::run(vh, buf, tw, 0, gg, lxe);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const cx<T> a = vp[s], b = vh[s];
         vh[s] = mk<T>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);  // conj(a) b
     }
-    FI::run(vh, buf, twe, 0, gg, lxe);
+    FI::run(vh, buf, tw, 0, gg, lxe);
     const T inv = (T)(1.0 / N);
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -2279,7 +2281,8 @@ static void launch_zcol(const Plan &pl, cx<T> *spec, int nslices, hipStream_t st
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);
     hipLaunchKernelGGL((k_zcol<T, LOGN, INV>), dim3(cdiv((long)g.NT * g.nky, TPB), nslices), dim3(F::G * TPB * C),
-                       (size_t)TPB * C * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twz);
+                       (size_t)TPB * C * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(F::N), st, spec, g,
+                       (const cx<T> *)pl.twz);
 }
 
 template <typename T, int LOGN>
@@ -2288,7 +2291,8 @@ static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGN, false>;
     hipLaunchKernelGGL((k_p3f<T, LOGN>), dim3(g.NT * g.nkz, g.nky / (g.p3f_TR >> g.logC)), dim3(g.p3f_TR * F::G),
-                       (size_t)g.p3f_TR * F::N * sizeof(cx<T>), st, spec, g, (const cx<T> *)pl.twe);
+                       (size_t)g.p3f_TR * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(F::N), st, spec, g,
+                       (const cx<T> *)pl.twe);
 }
 
 template <typename T, int LOGL, int MODE>
