@@ -185,16 +185,18 @@ __device__ __forceinline__ double form_factor_sq(const double2 fx, const double2
     return F * F;
 }
 
-// FP32: an FFT twiddle table of n values copied into LDS at dst, so that the
-// transform passes read it there rather than waiting on the cache for every
-// pass; returns the table to use.  FP64 keeps the global table (it would
+// FP32: an FFT twiddle table of n values copied into LDS at dst (stored with
+// tw_swz), so that the transform passes read it there rather than waiting on
+// the cache for every pass; returns the table to use.  FP64 keeps the global table (it would
 // double the LDS of the blocks that use it).  Every thread of the block calls
 // it (it ends with a barrier when it copies).
 template <typename T>
+constexpr bool kTwLds = sizeof(T) == 4;  // the kernels that copy their twiddles into LDS (FP32)
+template <typename T>
 __device__ __forceinline__ const cx<T> *tw_to_lds(const cx<T> *tw, cx<T> *dst, int n, int tid, int nthr)
 {
-    if constexpr (sizeof(T) == 4) {
-        for (int i = tid; i < n; i += nthr) dst[i] = tw[i];
+    if constexpr (kTwLds<T>) {
+        for (int i = tid; i < n; i += nthr) dst[tw_swz(i)] = tw[i];  // the layout RegFFT<..., true> reads
         __syncthreads();
         return dst;
     } else {
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
                                                 double gamma, const cx<T> *__restrict__ twx,
                                                 cx<T> *__restrict__ spec, const T *__restrict__ rho, int acc)
 {
-    using F = RegFFT<T, LOGL, false>;
+    using F = RegFFT<T, LOGL, false, 4, kTwLds<T>>;
     constexpr int L = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
                 const cx<T> ZL = cconj(lds[r * L + swz((L - k) & (L - 1))]);
                 const cx<T> Ev = cscale(cadd(Zk, ZL), (T)0.5);
                 const cx<T> D = cscale(csub(Zk, ZL), (T)0.5);
-                const cx<T> w = tw[k];
+                const cx<T> w = tw[kTwLds<T> ? tw_swz(k) : k];
                 X = cadd(Ev, cmul(mk<T>(w.y, -w.x), D));
             }
             cx<T> *o = dst + ((size_t)tile * g.nky + ky0 + r) * C + c;
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
 template <typename T, int LOGN, bool INV>
 __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
 {
-    using F = RegFFT<T, LOGN, INV>;
+    using F = RegFFT<T, LOGN, INV, 4, kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
@@ -329,7 +331,7 @@ __global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, co
 template <typename T, int LOGN, bool INV>
 __global__ void __launch_bounds__(512) k_zcol(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twz)
 {
-    using F = RegFFT<T, LOGN, INV>;
+    using F = RegFFT<T, LOGN, INV, 4, kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;
     constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
@@ -498,8 +500,8 @@ __global__ void __launch_bounds__(kThreads) k_p3(cx<T> *__restrict__ spec, Geo g
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(512) k_p3f(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twe)
 {
-    using FF = RegFFT<T, LOGN, false>;
-    using FI = RegFFT<T, LOGN, true>;
+    using FF = RegFFT<T, LOGN, false, 4, kTwLds<T>>;
+    using FI = RegFFT<T, LOGN, true, 4, kTwLds<T>>;
     constexpr int N = FF::N, E = FF::E, G = FF::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [N][TR], then [TR][N]
@@ -568,7 +570,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
                                                 T *__restrict__ out, int out_nx, int out_ny)
 {
-    using F = RegFFT<T, LOGL, true>;
+    using F = RegFFT<T, LOGL, true, 4, kTwLds<T>>;
     constexpr int L = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][L + 1]
@@ -634,7 +636,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         const cx<T> XL = cconj(xb[L - k]);
         const cx<T> A = cadd(Xk, XL);
         const cx<T> D = csub(Xk, XL);
-        const cx<T> wD = cmul(cconj(tw[k]), D);  // e^{+2 pi i k / nkx} D
+        const cx<T> wD = cmul(cconj(tw[kTwLds<T> ? tw_swz(k) : k]), D);  // e^{+2 pi i k / nkx} D
         v[s] = cadd(A, mk<T>(-wD.y, wD.x));      // A + i w D
     }
     __syncthreads();
@@ -685,7 +687,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
                                                 const T *__restrict__ rho, int acc)
 {
-    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
+    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems), kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N]
@@ -701,7 +703,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
     const cx<T> *tw = twx;
     if (sizeof(T) == 4) {
         cx<T> *twl = lds + R * N;
-        for (int i = tid; i < N; i += R * G) twl[i] = twx[i];
+        for (int i = tid; i < N; i += R * G) twl[tw_swz(i)] = twx[i];
         tw = twl;
         __syncthreads();
     }
@@ -776,7 +778,7 @@ __global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, 
 template <typename T, int LOGN, bool INV>
 __global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
 {
-    using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems)>;
+    using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems), kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     constexpr int C = sizeof(T) == 4 ? 4 : 2;  // complex pairs per tile row
     constexpr int TPB = (G * C >= 256) ? 1 : 256 / (G * C);
@@ -1360,7 +1362,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
                                                 int out_ny)
 {
-    using F = RegFFT<T, LOGNX, true>;
+    using F = RegFFT<T, LOGNX, true, 4, kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N] complex; staging [2R][N/2+1] reals
@@ -1398,7 +1400,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const cx<T> *tw = twx;
     if (sizeof(T) == 4) {
         cx<T> *twl = lds + R * N;
-        for (int i = tid; i < N; i += nthr) twl[i] = twx[i];
+        for (int i = tid; i < N; i += nthr) twl[tw_swz(i)] = twx[i];
         tw = twl;  // made visible by the barrier after the staging loop
     }
     // 16-byte loads (items ordered half-row, row, tile), independent in
@@ -1943,7 +1945,7 @@ __device__ __forceinline__ BsTab bs_lds_twiddles(BsTab t, cx<T> *lds, int R, int
     if constexpr (bs_tw_lds<T, ilog2_c(M)>()) {
         cx<T> *twl = lds + R * M;
         const cx<T> *tw = (const cx<T> *)t.tw;
-        for (int i = tid; i < M; i += nthr) twl[i] = tw[i];
+        for (int i = tid; i < M; i += nthr) twl[tw_swz(i)] = tw[i];
         __syncthreads();
         t.tw = twl;
     }
@@ -1951,12 +1953,13 @@ __device__ __forceinline__ BsTab bs_lds_twiddles(BsTab t, cx<T> *lds, int R, int
 }
 
 // v[s] = x[g + s G] (zero for n >= N) -> the DFT of length N (INV: inverse,
-// no 1/N) in the same places.  Every thread of the block calls it.
-template <typename T, int LOGM, bool INV>
+// no 1/N) in the same places; TWS: t.tw is an LDS table stored with tw_swz.
+// Every thread of the block calls it.
+template <typename T, int LOGM, bool INV, bool TWS = false>
 __device__ __forceinline__ void bs_line(cx<T> *v, cx<T> *buf, const BsTab &t, int g, int lx)
 {
-    using F = RegFFT<T, LOGM, false>;
-    using Fi = RegFFT<T, LOGM, true>;
+    using F = RegFFT<T, LOGM, false, 4, TWS>;
+    using Fi = RegFFT<T, LOGM, true, 4, TWS>;
     constexpr int E = F::E, G = F::G;
     const cx<T> *b = (const cx<T> *)t.b, *h = (const cx<T> *)(INV ? t.hi : t.hf), *tw = (const cx<T> *)t.tw;
 #pragma unroll
@@ -2087,7 +2090,7 @@ __global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g,
 #pragma unroll
         for (int s = 0; s < E; ++s) v[s] = nx[s];
         if (PF && j + 1 < j1) load(j + 1, go);
-        bs_line<T, LOGM, INV>(v, lds + line * M, tl, go, lx);
+        bs_line<T, LOGM, INV, bs_tw_lds<T, LOGM>()>(v, lds + line * M, tl, go, lx);
         if (active) {
             cx<T> *base = base0 + (size_t)j * g.slice_elems;
 #pragma unroll
@@ -2167,7 +2170,7 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
         }
         v[s] = z;
     }
-    bs_line<T, LOGM, true>(v, lds + line * M, tl, gg, lds_xor_gfast<M, G>(line));
+    bs_line<T, LOGM, true, bs_tw_lds<T, LOGM>()>(v, lds + line * M, tl, gg, lds_xor_gfast<M, G>(line));
     const T sc = (T)scale;
 #pragma unroll
     for (int s = 0; s < E; ++s) {

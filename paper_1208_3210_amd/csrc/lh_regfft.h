@@ -15,7 +15,8 @@
 // v[s] = x[g + s * G], s = 0 .. E-1 (natural order, stride G), so a column pass
 // can load from and store to global memory directly in that pattern.
 // Twiddles come from a table tw[x] = exp(-2 pi i x / (N << twsh)) built in FP64
-// and rounded once; the inverse uses the conjugates (no 1/N).
+// and rounded once (stored at tw_swz(x) when TWS); the inverse uses the
+// conjugates (no 1/N).
 #pragma once
 #include "lh_fft.h"
 
@@ -97,7 +98,13 @@ __device__ __forceinline__ void rdft(cx<T> *v)
 
 __device__ __forceinline__ int swz(int x) { return x ^ ((x >> 4) & 15); }
 
-template <typename T, int LOGN, bool INV, int LOGE_MAX = 4>
+// Twiddle tables kept in LDS are stored with this XOR swizzle (a bijection on
+// any power-of-two length): the reads of one pass, index (s k) << sh for the
+// butterflies of a wave, otherwise fall into a few LDS banks.
+__host__ __device__ constexpr int tw_swz(int i) { return i ^ ((i >> 5) & 31); }
+
+// TWS: the twiddle table is stored with tw_swz.
+template <typename T, int LOGN, bool INV, int LOGE_MAX = 4, bool TWS = false>
 struct RegFFT {
     static constexpr int N = 1 << LOGN;
     static constexpr int LOGE = LOGN < LOGE_MAX ? LOGN : LOGE_MAX;
@@ -138,7 +145,10 @@ struct RegFFT {
             if constexpr (!first) {
                 const int sh = LOGN - LOGP - LOGR + twsh;
 #pragma unroll
-                for (int s = 1; s < r; ++s) w[u * r + s] = cmul(w[u * r + s], twid<T, INV>(tw, (s * k) << sh));
+                for (int s = 1; s < r; ++s) {
+                    const int x = (s * k) << sh;
+                    w[u * r + s] = cmul(w[u * r + s], twid<T, INV>(tw, TWS ? tw_swz(x) : x));
+                }
             }
             rdft<T, r, INV>(w + u * r);
             if constexpr (last) {
