@@ -257,8 +257,8 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     // launch shapes
     const size_t cs = g.fp64 ? 16 : 8;
     {
-        // P1: G = L / E threads per row (E = min(16, L)), up to 256 threads
-        const int E = std::min(16, g.L), G = g.L / E;
+        // P1: G = L / E threads per row (E = min(kP1Elems, L)), up to 256 threads
+        const int E = std::min(kP1Elems, g.L), G = g.L / E;
         g.p1_R = std::min(p->nky, std::max(1, 256 / G));
         g.p1_logR = ilog2(g.p1_R);
     }

@@ -81,6 +81,9 @@ struct Geo {
 // Elements per thread of the register FFTs in the even builder pass (the
 // builder also keeps the band rows of its lines in registers).
 constexpr int kE1Elems = 8;
+// ... and in the general builder pass, for the same reason (with sixteen it
+// needs ~220 registers and two waves per SIMD; with eight ~120 and four).
+constexpr int kP1Elems = 8;
 // Partial sums per output plane of the q-average (plan scratch holds them).
 constexpr int kQavgBlocks = 32;
 // ... and in the even column passes (sixteen measured faster than eight there).

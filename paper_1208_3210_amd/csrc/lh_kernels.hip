@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
                                                 double gamma, const cx<T> *__restrict__ twx,
                                                 cx<T> *__restrict__ spec, const T *__restrict__ rho, int acc)
 {
-    using F = RegFFT<T, LOGL, false, 4, kTwLds<T>>;
+    using F = RegFFT<T, LOGL, false, ilog2_c(kP1Elems), kTwLds<T>>;
     constexpr int L = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
@@ -2250,7 +2250,7 @@ template <typename T, int LOGL>
 static void launch_p1(const Plan &pl, cx<T> *spec, int band, int z, int acc, hipStream_t st)
 {
     const Geo &g = pl.g;
-    using F = RegFFT<T, LOGL, false>;
+    using F = RegFFT<T, LOGL, false, ilog2_c(kP1Elems)>;
     const dim3 grid(g.nky / g.p1_R, cdiv(g.nS, g.p1_jc));
     const size_t lds = (size_t)g.p1_R * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N);
     // band `band`, kz plane z of the table; the plane's spectrum at spec
