@@ -682,8 +682,11 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // rx in [0, nkx/2] and ry in [0, nky/2] are stored (see Geo).
 
 // P1 (even): R row pairs (ky = 2p, 2p+1, ky <= nky/2) for jc slices.
+// FP32: at least four waves per SIMD (with the momentum-density weights the
+// kernel otherwise takes one register more than four waves allow); FP64 would
+// spill under that bound.
 template <typename T, int LOGNX, bool W>
-__global__ void __launch_bounds__(kThreads) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
+__global__ void __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 1) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
                                                 const T *__restrict__ rho, int acc)
 {
