@@ -27,9 +27,11 @@
  *
  * Output layout: float (LINDHARD_FP32C) or double (LINDHARD_FP64) arrays
  * [nomega][zones_y * nky][zones_x * nkx], row major.  Column X of the extended
- * map is h = (X - zones_x*nkx/2)/nkx reciprocal-lattice units, first-zone index
+ * map is h = k_zones (X - zones_x*nkx/2)/nkx reciprocal-lattice units (k_zones
+ * = 1 unless the momentum grid spans several zones), first-zone index
  * u = (X - zones_x*nkx/2) mod nkx (the same for rows): the maps are Gamma
- * centred.  Output buffers are device memory owned by the caller.
+ * centred; the form factor and the Coulomb interaction are taken at
+ * Q = 2 pi (h, l).  Output buffers are device memory owned by the caller.
  *
  * Streams are passed as `void *` holding a hipStream_t (NULL = the default
  * stream).  No function throws; every function returns a lindhard_status.
@@ -80,10 +82,10 @@ typedef struct {
                                    zone, one band, no form factor and no RPA */
     int32_t neps;               /* power of two, 4 .. 2048 */
     double emin, emax;          /* energy window, emin < 0 < emax */
-    int32_t nomega;             /* number of requested omegas, 1 .. 65536 */
+    int32_t nomega;             /* number of requested omegas, 1 .. 65535 */
     const double *omega;        /* host array of omegas, eV; each m*d, m >= 0
                                    (or >= 0 anywhere with omega_interp) */
-    int32_t zones_x, zones_y;   /* odd, >= 1, zones_x*nkx and zones_y*nky <= 65536 */
+    int32_t zones_x, zones_y;   /* odd, >= 1, zones_x*nkx <= 65536, zones_y*nky <= 65535 */
     int32_t ff_kind;            /* lindhard_ff */
     double ff_width;            /* orbital width w in lattice constants (> 0 if used) */
     int32_t precision;          /* lindhard_precision */

@@ -219,17 +219,21 @@ def form_factor(Qx, Qy, w: float):
     return np.exp(-s * q2) * (1.0 - 2.0 * s * q2 + s * s * (Qx * Qx - Qy * Qy) ** 2)
 
 
-def zone_axis(n: int, zones: int):
-    """For extended index X in [0, zones*n): (h in r.l.u., first-zone index u)."""
+def zone_axis(n: int, zones: int, kzones: int = 1):
+    """For extended index X in [0, zones*n): (h in r.l.u., first-zone index u).
+
+    On a momentum grid spanning kzones Brillouin zones per axis (extended
+    momentum p = 2 pi kzones ix / n, Eq. (9)) one grid step is kzones / n
+    reciprocal-lattice units, so h = kzones (X - zones n / 2) / n."""
     X = np.arange(zones * n)
     off = X - zones * n // 2
-    return off / n, np.mod(off, n)
+    return kzones * off / n, np.mod(off, n)
 
 
-def m2_extended(nkx: int, nky: int, zx: int, zy: int, ff_kind: int, w: float) -> np.ndarray:
+def m2_extended(nkx: int, nky: int, zx: int, zy: int, ff_kind: int, w: float, kzones: int = 1) -> np.ndarray:
     """|M(Q)|^2 on the extended output grid [Y][X]; 1 when ff_kind == 0."""
-    hx, _ = zone_axis(nkx, zx)
-    hy, _ = zone_axis(nky, zy)
+    hx, _ = zone_axis(nkx, zx, kzones)
+    hy, _ = zone_axis(nky, zy, kzones)
     if ff_kind == 0:
         return np.ones((zy * nky, zx * nkx))
     Qx = 2.0 * np.pi * hx[None, :]
@@ -237,13 +241,14 @@ def m2_extended(nkx: int, nky: int, zx: int, zy: int, ff_kind: int, w: float) ->
     return form_factor(Qx, Qy, w) ** 2
 
 
-def extend(im1bz: np.ndarray, zx: int, zy: int, ff_kind: int, w: float) -> np.ndarray:
-    """Extended-zone map out[..., Y, X] = |M(Q)|^2 chi_1BZ[..., v, u]."""
+def extend(im1bz: np.ndarray, zx: int, zy: int, ff_kind: int, w: float, kzones: int = 1) -> np.ndarray:
+    """Extended-zone map out[..., Y, X] = |M(Q)|^2 chi_1BZ[..., v, u], Q = 2 pi (h, l)
+    with h, l from ``zone_axis`` (grid step kzones / n r.l.u.)."""
     nky, nkx = im1bz.shape[-2:]
     _, ux = zone_axis(nkx, zx)
     _, uy = zone_axis(nky, zy)
     base = im1bz[..., uy[:, None], ux[None, :]]
-    return base * m2_extended(nkx, nky, zx, zy, ff_kind, w)
+    return base * m2_extended(nkx, nky, zx, zy, ff_kind, w, kzones)
 
 
 # --------------------------------------------------------------------------

@@ -1337,6 +1337,12 @@ lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, voi
     if (!plans || !outs || n < 0) return LINDHARD_EINVAL;
     for (int i = 0; i < n; ++i)
         if (!plans[i] || !outs[i] || plans[i]->pl.device != plans[0]->pl.device) return LINDHARD_EINVAL;
+    {
+        // a plan's workspace serves one instance at a time: no plan twice
+        std::vector<lindhard_plan_t> seen(plans, plans + n);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return LINDHARD_EINVAL;
+    }
     if (n == 0) return LINDHARD_OK;
     if (n == 1) return lindhard_exec(plans[0], outs[0], stream);
     int dev = 0;

@@ -113,12 +113,14 @@ __global__ void __launch_bounds__(kThreads) k_twiddle(cx<T> *__restrict__ tw, in
     tw[s] = mk<T>((T)cv, (T)sv);
 }
 
-// Per extended column (or row) X: (exp(-s Q^2), Q^2), Q = 2 pi (X - zones n/2)/n.
-__global__ void __launch_bounds__(kThreads) k_fftab(double2 *__restrict__ tab, int n, int zones, double s)
+// Per extended column (or row) X: (exp(-s Q^2), Q^2), Q = 2 pi h with
+// h = kz (X - zones n/2) / n reciprocal-lattice units (a momentum grid of n
+// points spanning kz zones has a step of kz / n).
+__global__ void __launch_bounds__(kThreads) k_fftab(double2 *__restrict__ tab, int n, int zones, double s, int kz)
 {
     const int X = blockIdx.x * kThreads + threadIdx.x;
     if (X >= n * zones) return;
-    const double h = (double)(X - (zones * n) / 2) / (double)n;
+    const double h = (double)kz * (double)(X - (zones * n) / 2) / (double)n;
     const double Q = 2.0 * kPi * h;
     const double Q2 = Q * Q;
     tab[X] = make_double2(exp(-s * Q2), Q2);
@@ -1608,7 +1610,7 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
                                                  int nky, int neps, const int *__restrict__ lags,
                                                  const double *__restrict__ fracs, int nw, int zx,
                                                  int zy, int ff, double ffs, const double2 *__restrict__ ffx,
-                                                 const double2 *__restrict__ ffy, int vkind, double V,
+                                                 const double2 *__restrict__ ffy, int vkind, double V, int kzn,
                                                  T *__restrict__ re_out, T *__restrict__ imr, T *__restrict__ rer,
                                                  int out_nx, int out_ny)
 {
@@ -1636,11 +1638,12 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
             const int X = zj * nkx + xu;
             // interaction: contact U = V, or Coulomb V / |Q|^2 with
             // Q = 2 pi (h, l) in units of 1/a (h, l the reciprocal-lattice
-            // coordinates of X, Y); at Q = 0 chi_RPA -> -1/V -> 0
+            // coordinates of X, Y: a grid spanning kzn zones has a step of
+            // kzn / n); at Q = 0 chi_RPA -> -1/V -> 0
             double U = V;
             bool q0 = false;
             if (vkind == 1) {
-                const double h = (double)(X - (zx * nkx) / 2) / nkx, l = (double)(Y - (zy * nky) / 2) / nky;
+                const double h = (double)kzn * (X - (zx * nkx) / 2) / nkx, l = (double)kzn * (Y - (zy * nky) / 2) / nky;
                 const double q2 = (2.0 * kPi) * (2.0 * kPi) * (h * h + l * l);
                 q0 = q2 == 0.0;
                 U = q0 ? 0.0 : V / q2;
@@ -2230,9 +2233,9 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
                        1 << g.logNE);
     if (pl.p.ff_kind != LINDHARD_FF_NONE) {
         hipLaunchKernelGGL(k_fftab, dim3(cdiv(pl.out_nx, kThreads)), dim3(kThreads), 0, st, pl.ffx, g.nkx, pl.zx,
-                           pl.ff_s);
+                           pl.ff_s, pl.p.k_zones);
         hipLaunchKernelGGL(k_fftab, dim3(cdiv(pl.out_ny, kThreads)), dim3(kThreads), 0, st, pl.ffy, g.nky, pl.zy,
-                           pl.ff_s);
+                           pl.ff_s, pl.p.k_zones);
     }
     if (pl.p.want_rpa) {
         const int nwp = (pl.p.nomega + kKkW - 1) / kKkW * kKkW;
@@ -2768,7 +2771,7 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
                        (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff,
-                       pl.ff_s, pl.ffx, pl.ffy, vkind, U, re, imr, rer, pl.out_nx, pl.out_ny);
+                       pl.ff_s, pl.ffx, pl.ffy, vkind, U, pl.p.k_zones, re, imr, rer, pl.out_nx, pl.out_ny);
     return hipGetLastError();
 }
 

@@ -124,3 +124,39 @@ def test_extended_full_size_sampled():
                                                                            plan.info.schedule.decode()))
     assert err <= 1e-5 and qerr <= 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("window", ["auto", "direct"], indirect=True)
+@pytest.mark.parametrize("prec", PRECS)
+def test_extended_grid_with_zones_form_factor_and_rpa(prec, window):
+    """A momentum grid spanning two zones, repeated over 3 x 3 output zones,
+    with the orbital form factor (Eq. (3)) and both RPA forms: |M(Q)|^2 and
+    V(Q) are taken at Q = 2 pi k_zones (X - Zx nkx/2)/nkx, the momentum the
+    grid point stands for."""
+    kz = 2
+    cfg = small_cfg(kz=kz, nk=16, neps=32)
+    cfg.update(zones=(3, 3), ff_kind=1, ff_width=0.6, want_rpa=True)
+    xi, mu = oracle_xi(cfg)
+    neps = cfg["neps"]
+    full = oracle.chi_full(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], np.arange(neps), rho=cfg["rho_table"])
+    lags = lags_of(cfg)
+    im1 = full[lags]
+    re1 = np.moveaxis(oracle.kk_real(np.moveaxis(full, 0, -1), lags), -1, 0)
+    im_ext = oracle.extend(im1, 3, 3, 1, 0.6, kzones=kz)
+    re_ext = oracle.extend(re1, 3, 3, 1, 0.6, kzones=kz)
+    U, v = 1.1, 0.8
+    imr_u, rer_u = oracle.rpa(re_ext, im_ext, U)
+    hx, _ = oracle.zone_axis(cfg["nkx"], 3, kz)
+    hy, _ = oracle.zone_axis(cfg["nky"], 3, kz)
+    imr_c, rer_c = oracle.rpa_coulomb(re_ext, im_ext, hx, hy, v)
+    plan = LH.Plan(precision=prec, **cfg)
+    im = plan.exec()
+    re, gimr_u, grer_u = plan.rpa(U)
+    got_u = [x.double().cpu().numpy() for x in (im, re, gimr_u, grer_u)]
+    _, gimr_c, grer_c = plan.rpa_coulomb(v)
+    torch.cuda.synchronize()
+    errs = [normwise(g, r) for g, r in zip(got_u, (im_ext, re_ext, imr_u, rer_u))]
+    errs += [normwise(gimr_c.double().cpu().numpy(), imr_c), normwise(grer_c.double().cpu().numpy(), rer_c)]
+    print("k_zones=2 zones 3x3 ff+rpa prec=%d window=%s errs=%s" % (prec, window, ["%.2e" % e for e in errs]))
+    assert max(errs) <= TOL[prec]
+    plan.close()

@@ -77,3 +77,29 @@ def test_weighted_q_sum_identity():
     full = oracle.chi_full(xi, 32, -1.0, 1.2, 0.07, ms, rho=rho)
     got = oracle.chi_qmean(xi, 32, -1.0, 1.2, 0.07, ms, rho=rho)
     assert np.allclose(got, full.mean(axis=(1, 2)), rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("kz", [2, 4])
+def test_extended_grid_momentum_of_the_output_points(kz):
+    """On a grid spanning kz zones per axis one step is kz/n reciprocal-lattice
+    units: the point n/kz grid steps left of the centre is the reciprocal
+    lattice vector G = (-1, 0), where a one-zone grid repeated over three
+    zones has its point h = -1.  The form factor (Eq. (3)) and the
+    Coulomb interaction must agree at that common momentum."""
+    n, w = 16, 0.6
+    hx_k, _ = oracle.zone_axis(n, 1, kz)
+    hx_1, _ = oracle.zone_axis(n, 3)
+    Xk = n // 2 - n // kz          # G = (-1, 0) on the kz-zone grid
+    X1 = 3 * n // 2 - n            # h = -1 on the three-zone grid
+    assert hx_k[Xk] == -1.0 and hx_1[X1] == -1.0
+    m2k = oracle.m2_extended(n, n, 1, 1, 1, w, kz)
+    m23 = oracle.m2_extended(n, n, 3, 3, 1, w)
+    assert m2k[n // 2, Xk] == m23[3 * n // 2, X1]
+    # |M(G)|^2 from the Gaussian orbital: F(Q) = exp(-s Q^2)(1 - 2 s Q^2 + s^2 Q^4) at Q = 2 pi, s = w^2/4
+    s, Q2 = w * w / 4.0, (2 * np.pi) ** 2
+    F = np.exp(-s * Q2) * (1 - 2 * s * Q2 + s * s * Q2 * Q2)
+    assert np.isclose(m2k[n // 2, Xk], F * F, rtol=1e-13)
+    # the interaction sees the same |Q|
+    hy_k, _ = oracle.zone_axis(n, 1, kz)
+    V = oracle.coulomb_v(hx_k, hy_k, 1.0)
+    assert np.isclose(V[n // 2, Xk] * Q2, 1.0, rtol=1e-15)
