@@ -210,6 +210,22 @@ lindhard_status lindhard_structure_factor(lindhard_plan_t plan, double kT, const
  * Errors: EINVAL (NULL), EDEVICE. */
 lindhard_status lindhard_q_average(lindhard_plan_t plan, const void *im, double *out, void *stream);
 
+/* lindhard_q_average without a plan and without any device allocation, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): out[w] = mean over the
+ * plane_elems elements of plane w of `im` (device, nomega planes of
+ * plane_elems contiguous elements, float if elem_bytes = 4, double if 8),
+ * accumulated in FP64 in a fixed order.  The partial sums live in a
+ * per-device array of the library (LINDHARD_NOALLOC_MAX_PLANES * 32 doubles,
+ * 1 MiB, held until the process ends), looked up on the first call on each
+ * device; calls that overlap on one device race on it (no two at once per
+ * device).  Asynchronous on `stream`.  Errors: EINVAL (NULL pointers,
+ * plane_elems < 1, elem_bytes not 4 or 8, nomega < 1 or above
+ * LINDHARD_NOALLOC_MAX_PLANES), EDEVICE. */
+#define LINDHARD_NOALLOC_MAX_PLANES 4096
+lindhard_status lindhard_q_average_noalloc(const void *im, int32_t nomega, int64_t plane_elems, int32_t elem_bytes,
+                                           double *out, void *stream);
+
 /* Peak search (plasmon modes as the peaks of -Im chi_RPA, Sec. 4): for every
  * extended point (X, Y), the index w in [0, nomega) of the largest -im[w][Y][X]
  * (the first on ties, compared in the plan's precision) into peak (device,

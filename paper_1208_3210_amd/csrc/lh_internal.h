@@ -149,6 +149,10 @@ hipError_t launch_rpa(const Plan &pl, int vkind, double U, void *re, void *imr, 
 hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStream_t st);
 hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st);
 hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t st);
+// q-average of nw planes of `plane` elements with the partial sums in `part`
+// (nw * kQavgBlocks doubles; every entry is written, none is read first).
+hipError_t launch_qavg_raw(const void *im, bool fp64, size_t plane, int nw, double *part, double *out,
+                           hipStream_t st);
 hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
 hipError_t launch_cut(const Plan &pl, const void *im, const int *xy, int npts, void *out, hipStream_t st);
 // res: 3 + 4 * nseg doubles of device memory; im_plane: the plane to cut

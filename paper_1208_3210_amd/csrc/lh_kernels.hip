@@ -2802,17 +2802,22 @@ hipError_t launch_sqw(const Plan &pl, double kT, const void *im, void *s, hipStr
                      : sqw_t<float>(pl, kT, (const float *)im, (float *)s, st);
 }
 
+hipError_t launch_qavg_raw(const void *im, bool fp64, size_t plane, int nw, double *part, double *out,
+                           hipStream_t st)
+{
+    const dim3 grid(kQavgBlocks, nw);
+    if (fp64)
+        hipLaunchKernelGGL(k_qavg_part<double>, grid, dim3(kThreads), 0, st, (const double *)im, plane, part);
+    else
+        hipLaunchKernelGGL(k_qavg_part<float>, grid, dim3(kThreads), 0, st, (const float *)im, plane, part);
+    hipLaunchKernelGGL(k_qavg_final, dim3(cdiv(nw, kThreads)), dim3(kThreads), 0, st, part, nw, 1.0 / (double)plane,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t st)
 {
-    const size_t plane = (size_t)pl.out_nx * pl.out_ny;
-    const dim3 grid(kQavgBlocks, pl.p.nomega);
-    if (pl.g.fp64)
-        hipLaunchKernelGGL(k_qavg_part<double>, grid, dim3(kThreads), 0, st, (const double *)im, plane, pl.scratch);
-    else
-        hipLaunchKernelGGL(k_qavg_part<float>, grid, dim3(kThreads), 0, st, (const float *)im, plane, pl.scratch);
-    hipLaunchKernelGGL(k_qavg_final, dim3(cdiv(pl.p.nomega, kThreads)), dim3(kThreads), 0, st, pl.scratch,
-                       pl.p.nomega, 1.0 / (double)plane, out);
-    return hipGetLastError();
+    return launch_qavg_raw(im, pl.g.fp64 != 0, (size_t)pl.out_nx * pl.out_ny, pl.p.nomega, pl.scratch, out, st);
 }
 
 hipError_t launch_peak(const Plan &pl, const void *im, int32_t *idx, hipStream_t st)

@@ -102,7 +102,8 @@ class Envelope(ctypes.Structure):
 
 EXPORTS = [
     "lindhard_plan", "lindhard_plan_info", "lindhard_exec", "lindhard_exec_timed", "lindhard_rpa",
-    "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_q_average", "lindhard_peak_index",
+    "lindhard_rpa_coulomb", "lindhard_structure_factor", "lindhard_q_average", "lindhard_q_average_noalloc",
+    "lindhard_peak_index",
     "lindhard_cut", "lindhard_high_symmetry_path", "lindhard_zone_envelope", "lindhard_exec_batch",
     "lindhard_problem_shape",
     "lindhard_plan_destroy", "lindhard_serve_create", "lindhard_serve_submit", "lindhard_serve_poll",
@@ -134,6 +135,7 @@ def lib() -> ctypes.CDLL:
             L.lindhard_structure_factor.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp]
             L.lindhard_peak_index.argtypes = [_vp, _vp, _vp, _vp]
             L.lindhard_q_average.argtypes = [_vp, _vp, _vp, _vp]
+            L.lindhard_q_average_noalloc.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _vp, _vp]
             L.lindhard_problem_shape.argtypes = [ctypes.POINTER(Problem)] + [ctypes.POINTER(ctypes.c_int32)] * 4
             _i32p = ctypes.POINTER(ctypes.c_int32)
             L.lindhard_cut.argtypes = [_vp, _vp, _i32p, _i32p, ctypes.c_int32, _vp, _vp]
@@ -254,6 +256,29 @@ def lindhard_structure_factor(plan: int, kT: float, im_ptr: int, s_ptr: int, str
 
 def lindhard_q_average(plan: int, im_ptr: int, out_ptr: int, stream_ptr: int) -> None:
     _check(lib().lindhard_q_average(_vp(plan), _vp(im_ptr), _vp(out_ptr), _vp(stream_ptr)), "lindhard_q_average")
+
+
+NOALLOC_MAX_PLANES = 4096
+
+
+def lindhard_q_average_noalloc(im_ptr: int, nomega: int, plane_elems: int, elem_bytes: int, out_ptr: int,
+                               stream_ptr: int) -> None:
+    _check(lib().lindhard_q_average_noalloc(_vp(im_ptr), int(nomega), int(plane_elems), int(elem_bytes),
+                                            _vp(out_ptr), _vp(stream_ptr)), "lindhard_q_average_noalloc")
+
+
+def q_average_noalloc(im: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Mean of every plane of im ([nomega, ...] float32 or float64, contiguous,
+    on the GPU) into the caller's float64 tensor `out` (nomega values), with
+    the library's per-device scratch: no device memory is allocated."""
+    if not (im.is_cuda and im.is_contiguous() and im.dtype in (torch.float32, torch.float64)):
+        raise ValueError("im must be a contiguous float32/float64 GPU tensor")
+    if not (out.is_cuda and out.is_contiguous() and out.dtype == torch.float64 and out.numel() == im.shape[0]):
+        raise ValueError("out must be a contiguous float64 GPU tensor of im.shape[0] values")
+    plane = im.numel() // im.shape[0]
+    lindhard_q_average_noalloc(im.data_ptr(), im.shape[0], plane, im.element_size(), out.data_ptr(),
+                               _stream_ptr(stream))
+    return out
 
 
 def _i32(a):
