@@ -1,0 +1,85 @@
+"""Full-size parity of the 2048^2 k x 512-energy x 256-lag instance (the
+benchmarked workload) against stored FP64 oracle values.
+
+``tests/golden/config3_imchi_oracle.npz`` holds Im chi_1BZ(q, m) at 72 q
+points (an 8 x 8 grid of stride 256 shifted off the symmetry lines, Gamma, X,
+M and five seeded points) for every lag m = 1..256, written by
+``tests/golden/make_config3_golden.py`` from the oracle alone (the direct FP64
+double sum over k and energy of Eq. (9) in its discrete form).  Both GPU
+precisions are compared with it normwise per omega slice: for every lag,
+max |gpu - oracle| / max |oracle| over the 72 q points, FP32 with compensated
+energy sums <= 1e-5, FP64 <= 1e-11, and the L2 error is reported."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1208_3210_amd import lindhard as LH
+from paper_1208_3210_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config3_imchi_oracle.npz")
+TOL = {LH.LINDHARD_FP64: 1e-11, LH.LINDHARD_FP32C: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def golden():
+    d = np.load(GOLDEN, allow_pickle=False)
+    cfg = W.config3()
+    # the stored values belong to this workload: same band, grid, window
+    assert np.array_equal(d["band"], np.array([cfg["t"], cfg["tp"], cfg["tpp"], cfg["filling"], cfg["gamma"]]))
+    assert tuple(d["grid"]) == (cfg["nkx"], cfg["nky"], cfg["neps"])
+    assert tuple(d["window"]) == (cfg["emin"], cfg["emax"])
+    assert np.array_equal(d["lags"], np.arange(1, 257))
+    return dict(qx=d["qx"], qy=d["qy"], im=d["imchi"], mu=float(d["mu"]), cfg=cfg)
+
+
+@pytest.fixture
+def window(request, monkeypatch):
+    for v in ("LINDHARD_WINDOW", "LINDHARD_SYMMETRY", "LINDHARD_EVEN_WINDOW"):
+        monkeypatch.delenv(v, raising=False)
+    if request.param in ("direct", "fft"):
+        monkeypatch.setenv("LINDHARD_SYMMETRY", "off")
+        monkeypatch.setenv("LINDHARD_WINDOW", request.param)
+    elif request.param.startswith("even-"):
+        monkeypatch.setenv("LINDHARD_EVEN_WINDOW", request.param[5:])
+    return request.param
+
+
+def per_slice_errors(got, ref):
+    """Normwise error of every omega slice (columns: lags) over the q samples."""
+    diff = np.abs(got - ref).max(axis=0)
+    scale = np.abs(ref).max(axis=0)
+    return diff / scale, np.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum())
+
+
+def gather(out, qx, qy, n):
+    """Im chi at the natural-order q of the samples from the Gamma-centred map."""
+    X = torch.as_tensor((qx + n // 2) % n, device=out.device, dtype=torch.long)
+    Y = torch.as_tensor((qy + n // 2) % n, device=out.device, dtype=torch.long)
+    return out[:, Y, X].double().cpu().numpy().T  # (nq, nlag)
+
+
+@pytest.mark.parametrize("window,prec", [("auto", LH.LINDHARD_FP32C), ("even-direct", LH.LINDHARD_FP32C),
+                                         ("even-mfma", LH.LINDHARD_FP32C), ("direct", LH.LINDHARD_FP32C),
+                                         ("fft", LH.LINDHARD_FP32C), ("auto", LH.LINDHARD_FP64),
+                                         ("fft", LH.LINDHARD_FP64)], indirect=["window"])
+def test_config3_per_omega_slice_against_stored_oracle(golden, window, prec):
+    cfg = golden["cfg"]
+    n = cfg["nkx"]
+    plan = LH.Plan(precision=prec, **cfg)
+    assert abs(plan.info.mu - golden["mu"]) < 1e-12
+    out = plan.exec()
+    torch.cuda.synchronize()
+    sched = plan.info.schedule.decode()
+    got = gather(out, golden["qx"], golden["qy"], n)
+    plan.close()
+    del out
+    err, l2 = per_slice_errors(got, golden["im"])
+    worst = int(np.argmax(err))
+    print("config3 golden prec=%d window=%s: worst slice lag %d err %.3e, median slice %.3e, L2 %.3e; %s"
+          % (prec, window, worst + 1, err[worst], np.median(err), l2, sched))
+    assert np.all(err <= TOL[prec])
+    assert l2 <= TOL[prec]
