@@ -61,7 +61,8 @@ static void describe_schedule(Plan &pl)
     if (g.even)
         std::snprintf(buf, sizeof buf, "%s even lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d%s P5 R%d%s",
                       g.fp64 ? "fp64" : "fp32c", g.m_lo, g.m_hi, g.jA, g.jB, g.e1_R, g.e1_jc,
-                      g.e3_variant ? "mfma" : "direct", g.e3_variant ? g.e3m_TR : g.e3_TR, tn, g.e5_R,
+                      g.e3_variant == 2 ? "mfma4" : g.e3_variant ? "mfma" : "direct",
+                      g.e3_variant == 2 ? 16 * g.e3q_W : g.e3_variant ? g.e3m_TR : g.e3_TR, tn, g.e5_R,
                       pl.p.want_rpa ? " +kk/rpa" : "");
     else
         std::snprintf(buf, sizeof buf, "%s lags[%d,%d] slices[%d,%d) P1 R%d jc%d P3 %s TR%d%s P5 R%d%s",
@@ -395,9 +396,35 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             g.e3m_buf = (size_t)g.e3m_nA * g.slice_e * es3 < lim && (size_t)g.e3m_nHe * g.slice_e * es3 < lim;
         }
         g.e3m_TR = 4;
+        // rank-1 matrix window (FP32): tiles of 16 lags, chunks of 16 steps
+        g.e3q_ok = 0;
+        if (!g.fp64 && g.nL > 0 && g.e3m_nA > 0 && g.e3m_nHe > 0) {
+            g.e3q_nT = (g.nL + 15) / 16;
+            g.e3q_U0 = (g.m_lo + 14) / 16;
+            g.e3q_a0 = g.m_lo + 2 - 16 * g.e3q_U0;
+            g.e3q_offP = 15 - g.e3q_a0;
+            g.e3q_umax = std::min((g.e3m_nA - g.e3q_a0 + 14) / 16, g.e3q_nT - 1 + g.e3q_U0);
+            g.e3q_cmax = std::min((g.e3m_nHe + 2) / 16, g.e3q_nT - 1 + g.e3q_U0);
+            // P' row: 16 zeros, then P'[a] at 16 + offP + a, zeros up to the
+            // set u = umax + 1 (out-of-range sets read zeros, no branch)
+            g.e3q_LP = 16 * g.e3q_umax + 60;
+            g.e3q_LH = 16 * g.e3q_cmax + 20;
+            g.e3q_nAst = std::max(0, std::min(g.e3m_nA, g.e3q_LP - 16 - g.e3q_offP));
+            g.e3q_nHst = std::max(0, std::min(g.e3m_nHe, g.e3q_LH - 3));
+            g.e3q_PSP = g.e3q_LP + (((16 - g.e3q_LP) % 32) + 32) % 32;
+            g.e3q_PSH = g.e3q_LH + (((4 - g.e3q_LH) % 32) + 32) % 32;
+            g.e3q_W = 1;
+            // byte offsets of the buffer loads and stores stay below 4 GiB
+            // (the zero rows of the staging wrap to offsets past the range)
+            const double sl4 = (double)g.slice_e * 4.0, lim = 4294967040.0;
+            const bool fits32 = (g.e3q_nAst + 96) * sl4 < lim && (g.e3q_nHst + 96) * sl4 < lim && g.nL * sl4 < lim;
+            g.e3q_ok = g.e3q_umax >= 0 && fits32 && e3q_lds_bytes(g, 1) <= 65536;
+        }
         g.e3_variant = 0;
-        if (const char *ev = std::getenv("LINDHARD_EVEN_WINDOW"))
+        if (const char *ev = std::getenv("LINDHARD_EVEN_WINDOW")) {
             if (!std::strcmp(ev, "mfma") && even_mfma_lds(g, 4) <= 65536) g.e3_variant = 1;
+            if (!std::strcmp(ev, "mfma4") && g.e3q_ok) g.e3_variant = 2;
+        }
     }
 
     pl.zx = p->zones_x;
@@ -588,8 +615,8 @@ std::string tune_key(const Geo &g)
         for (int TR = 32; TR >= 4 && !maxfit_m; TR >>= 1)
             if (even_mfma_lds(g, TR) <= 65536) maxfit_m = TR;
     const char *ev = g.even ? std::getenv("LINDHARD_EVEN_WINDOW") : nullptr;
-    std::snprintf(b, sizeof b, "w4 %d %d %d %d %d %d %d %d %d %d %s z%d", g.even, g.fp64, g.nkx, g.nky, g.neps, g.j0,
-                  g.m_lo, (g.m_hi + 31) / 32, maxfit, maxfit_m, ev ? ev : "auto", g.nkz);
+    std::snprintf(b, sizeof b, "w5 %d %d %d %d %d %d %d %d %d %d %d %s z%d", g.even, g.fp64, g.nkx, g.nky, g.neps,
+                  g.j0, g.m_lo, (g.m_hi + 31) / 32, maxfit, maxfit_m, g.e3q_ok, ev ? ev : "auto", g.nkz);
     return b;
 }
 
@@ -642,7 +669,9 @@ void set_even_tr(Geo &g, int TR)
 void set_even(Geo &g, int variant, int TR)
 {
     g.e3_variant = variant;
-    if (variant == 1) {
+    if (variant == 2) {
+        g.e3q_W = TR / 16;
+    } else if (variant == 1) {
         g.e3m_TR = TR;
         g.e3m_PS = even_mfma_ps(g, TR);
     } else
@@ -651,6 +680,7 @@ void set_even(Geo &g, int variant, int TR)
 
 bool even_fits(const Geo &g, int variant, int TR)
 {
+    if (variant == 2) return g.e3q_ok && TR == 16 && e3q_lds_bytes(g, 1) <= 65536;
     if (variant == 1) return TR >= 4 && TR <= 32 && even_mfma_lds(g, TR) <= 65536;
     return even_tr_fits(g, TR);
 }
@@ -694,8 +724,9 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
     std::vector<std::pair<int, int>> cands;
     if (g.even) {
         const char *ev = std::getenv("LINDHARD_EVEN_WINDOW");
-        const bool want_direct = !ev || std::strcmp(ev, "mfma") != 0;
-        const bool want_mfma = !ev || std::strcmp(ev, "direct") != 0;
+        const bool want_direct = !ev || !std::strcmp(ev, "direct");
+        const bool want_mfma = !ev || !std::strcmp(ev, "mfma");
+        const bool want_mfma4 = !ev || !std::strcmp(ev, "mfma4");
         if (want_direct)
             for (int TR = 64, n = 0; TR >= 1 && n < 3; TR >>= 1)
                 if (even_tr_fits(g, TR)) {
@@ -708,6 +739,7 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
                     cands.push_back({1, TR});
                     ++n;
                 }
+        if (want_mfma4 && even_fits(g, 2, 16)) cands.push_back({2, 16});
         if (cands.empty()) cands.push_back({0, g.e3_TR});
     } else {
         cands.push_back({0, 0});

@@ -66,6 +66,13 @@ struct Geo {
     int e3_variant;
     int e3m_TR, e3m_PA, e3m_nA, e3m_nHe, e3m_PS, e3m_NAG, e3m_NMG;
     int e3m_buf;              // occupied and unoccupied slice ranges each below 4 GiB: buffer loads
+    // even window as 4 x 4 rank-1 matrix updates (e3_variant 2, FP32): lag
+    // tiles of 16, nT of them; chunk c of tile t reads the B set u = t - c + U0;
+    // P' at LDS position 16 + a + offP (a0 + offP = 15), u <= umax, c <= cmax;
+    // nAst / nHst values staged, rows of PSP / PSH floats (LP / LH used);
+    // e3q_W waves of 16 points per block
+    int e3q_ok, e3q_nT, e3q_U0, e3q_a0, e3q_offP, e3q_umax, e3q_cmax, e3q_LP, e3q_LH, e3q_PSP, e3q_PSH;
+    int e3q_nAst, e3q_nHst, e3q_W;
     // energy-window variant: 0 direct (compensated in FP32), 1 FFT along energy
     int p3_variant;
     int logNE;                // FFT length along energy for variant 1
@@ -154,6 +161,9 @@ hipError_t launch_qavg(const Plan &pl, const void *im, double *out, hipStream_t 
 hipError_t launch_qavg_raw(const void *im, bool fp64, size_t plane, int nw, double *part, double *out,
                            hipStream_t st);
 hipError_t launch_window(const Plan &pl, hipStream_t st);  // energy-window pass alone
+// The even window as 4 x 4 rank-1 matrix updates (FP32), W waves per block.
+size_t e3q_lds_bytes(const Geo &g, int W);
+hipError_t launch_e3q(const Plan &pl, int W, hipStream_t st);
 hipError_t launch_cut(const Plan &pl, const void *im, const int *xy, int npts, void *out, hipStream_t st);
 // res: 3 + 4 * nseg doubles of device memory; im_plane: the plane to cut
 hipError_t launch_envelope(const Plan &pl, const void *im_plane, int dir, int W, int nseg, double qstep, double *res,

@@ -2706,6 +2706,10 @@ static hipError_t window_t(const Plan &pl, hipStream_t st)
         else                                                                                          \
             hipLaunchKernelGGL((k_e3<T, true, TRV>), g3, dim3(kThreads), lds3, st, spr, g);           \
     } while (0)
+        if (g.e3_variant == 2) {
+            if constexpr (sizeof(T) == 4) return launch_e3q(pl, g.e3q_W, st);
+            return hipErrorInvalidValue;
+        }
         if (g.e3_variant == 1) {
             const size_t tile = (size_t)256 * (g.e3m_TR + 1), stage = (size_t)g.e3m_TR * g.e3m_PS;
             const size_t ldsm = (g.e3m_NMG == 1 ? std::max(tile, stage) : tile + stage) * es;

@@ -54,7 +54,7 @@ def oracle_xi(cfg):
     return eps - mu, mu
 
 
-@pytest.mark.parametrize("window", ["auto", "even-mfma", "even-direct", "direct", "fft"], indirect=True)
+@pytest.mark.parametrize("window", ["auto", "even-mfma", "even-mfma4", "even-direct", "direct", "fft"], indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
 def test_extended_full_grid(prec, window):
     cfg = small_cfg()

@@ -63,7 +63,8 @@ def gather(out, qx, qy, n):
 
 
 @pytest.mark.parametrize("window,prec", [("auto", LH.LINDHARD_FP32C), ("even-direct", LH.LINDHARD_FP32C),
-                                         ("even-mfma", LH.LINDHARD_FP32C), ("direct", LH.LINDHARD_FP32C),
+                                         ("even-mfma", LH.LINDHARD_FP32C), ("even-mfma4", LH.LINDHARD_FP32C),
+                                         ("direct", LH.LINDHARD_FP32C),
                                          ("fft", LH.LINDHARD_FP32C), ("auto", LH.LINDHARD_FP64),
                                          ("fft", LH.LINDHARD_FP64)], indirect=["window"])
 def test_config3_per_omega_slice_against_stored_oracle(golden, window, prec):
@@ -74,6 +75,8 @@ def test_config3_per_omega_slice_against_stored_oracle(golden, window, prec):
     out = plan.exec()
     torch.cuda.synchronize()
     sched = plan.info.schedule.decode()
+    if window == "even-mfma4":
+        assert " P3 mfma4 " in sched
     got = gather(out, golden["qx"], golden["qy"], n)
     plan.close()
     del out

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = {LH.LINDHARD_FP64: 1e-11, LH.LINDHARD_FP32C: 1e-5}
 PRECS = [LH.LINDHARD_FP64, LH.LINDHARD_FP32C]
-WINDOWS = ["auto", "direct", "fft", "even-direct", "even-mfma"]
-EVEN_WINDOWS = ("auto", "even-direct", "even-mfma")
+WINDOWS = ["auto", "direct", "fft", "even-direct", "even-mfma", "even-mfma4"]
+EVEN_WINDOWS = ("auto", "even-direct", "even-mfma", "even-mfma4")
 
 
 @pytest.fixture
@@ -28,8 +28,9 @@ def window(request, monkeypatch):
     """Pipeline chosen at plan time.  auto: the plan's own choice (the real
     even path for mirror-symmetric bands, window form timed); direct / fft:
     the general complex path with the direct or the energy-FFT window;
-    even-direct / even-mfma: the even path with the vector-ALU or the
-    matrix-core window (the latter where its LDS tiles fit)."""
+    even-direct / even-mfma / even-mfma4: the even path with the vector-ALU
+    window, the Toeplitz-blocked matrix-core window or the rank-1 matrix-core
+    window (FP32; each where its LDS tiles fit, else the vector form)."""
     for v in ("LINDHARD_WINDOW", "LINDHARD_SYMMETRY", "LINDHARD_EVEN_WINDOW"):
         monkeypatch.delenv(v, raising=False)
     if request.param in ("direct", "fft"):
@@ -89,6 +90,8 @@ def test_config1_full_grid(prec, window):
     assert (" even " in sched) == (window in EVEN_WINDOWS)
     if window == "even-mfma":
         assert " P3 mfma " in sched
+    if window == "even-mfma4":
+        assert (" P3 mfma4 " in sched) == (prec == LH.LINDHARD_FP32C)
     if window == "even-direct":
         assert " P3 direct " in sched
     assert err <= TOL[prec]
@@ -247,7 +250,7 @@ def test_rpa_zero_U_is_identity_and_needs_want_rpa():
     plan.close()
 
 
-@pytest.mark.parametrize("window", ["auto", "fft", "even-mfma"], indirect=True)
+@pytest.mark.parametrize("window", ["auto", "fft", "even-mfma", "even-mfma4"], indirect=True)
 @pytest.mark.parametrize("prec", PRECS)
 def test_config2_full_size_sampled(prec, window):
     """512^2 k, 256 energies, 5x5 zones, form factor, KK and RPA: every output
@@ -315,7 +318,7 @@ def q_sum_identity_rhs(xi, neps, emin, emax, gamma, lags):
     return np.array(out)
 
 
-@pytest.mark.parametrize("window", ["auto", "fft", "direct", "even-direct", "even-mfma"], indirect=True)
+@pytest.mark.parametrize("window", ["auto", "fft", "direct", "even-direct", "even-mfma", "even-mfma4"], indirect=True)
 def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
     """2048^2 k, 512 energies, 256 lags, G = 0.01 eV: FP32 (the benchmarked
     launch) against the oracle at sampled (q, m), the q-sum identity at every
@@ -329,6 +332,8 @@ def test_config3_full_size_sampled_fp32_vs_oracle_and_fp64(window):
     print("config3 [%s] schedule %s" % (window, plan32.info.schedule.decode()))
     if window == "even-mfma":
         assert " P3 mfma " in plan32.info.schedule.decode()
+    if window == "even-mfma4":
+        assert " P3 mfma4 " in plan32.info.schedule.decode()
     out32 = plan32.exec()
     torch.cuda.synchronize()
     plan32.close()
