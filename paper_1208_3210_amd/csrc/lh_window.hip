@@ -51,7 +51,7 @@ __device__ __forceinline__ f4v mfma4x4(float a, float b, f4v c)
 constexpr int kPoints = 16;   // real-space points per block (one per MFMA block)
 constexpr int kWaves = 2;     // waves per block, sharing the staged points
 constexpr int kTiles = 4;     // lag tiles processed together (T), B sets in the ring
-constexpr int kFoldChunks = 8;  // chunks (16 products each) summed in FP32 between folds
+constexpr int kFoldChunks = 8;  // chunks (16 products each) summed in FP32 between folds (a multiple of T)
 
 // Launch index -> logical block: the blocks of one XCD (launch index mod 8)
 // take one contiguous range, so that neighbouring blocks (whose rows share
@@ -200,29 +200,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, G
         // chunks up to t0 + U0 feed every tile of the group; in the last T - 1
         // chunks after it, tile k < cc - t0 - U0 has no more terms
         const int cm = min(cl, t0 + U0);
-        int c = cf;
-        for (; c + kFoldChunks - 1 <= cm; c += kFoldChunks) {
+        int c = cf, nbody = 0;
+        for (; c + kTiles - 1 <= cm; c += kTiles) {
             chunk(I0{}, c, I0{});
             chunk(I1{}, c + 1, I0{});
             chunk(I2{}, c + 2, I0{});
             chunk(I3{}, c + 3, I0{});
-            chunk(std::integral_constant<int, 4>{}, c + 4, I0{});
-            chunk(std::integral_constant<int, 5>{}, c + 5, I0{});
-            chunk(std::integral_constant<int, 6>{}, c + 6, I0{});
-            chunk(std::integral_constant<int, 7>{}, c + 7, I0{});
-            fold();
+            if ((++nbody & (kFoldChunks / kTiles - 1)) == 0) fold();
         }
-        // the remaining 0 .. 7 chunks of the full part, the ring phase
-        // restarting at 0 (8 is a multiple of T), then the tail at the phase
-        // where they stop
+        // the remaining 0 .. 3 chunks of the full part (ring phase 0 after
+        // whole bodies), then the tail at the phase where they stop
         const int rem = max(0, cm - c + 1);
         if (rem > 0) chunk(I0{}, c, I0{});
         if (rem > 1) chunk(I1{}, c + 1, I0{});
         if (rem > 2) chunk(I2{}, c + 2, I0{});
-        if (rem > 3) chunk(I3{}, c + 3, I0{});
-        if (rem > 4) chunk(std::integral_constant<int, 4>{}, c + 4, I0{});
-        if (rem > 5) chunk(std::integral_constant<int, 5>{}, c + 5, I0{});
-        if (rem > 6) chunk(std::integral_constant<int, 6>{}, c + 6, I0{});
         const int ct = c + rem;  // first tail chunk (t0 + U0 + 1 unless clipped)
         auto tail = [&](auto P) {
             constexpr int ph = decltype(P)::value;
