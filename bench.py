@@ -294,6 +294,50 @@ def bench_multiband(LH, W, torch, steps=3):
     return res
 
 
+def bench_general(LH, W, torch, cfg, steps=3):
+    """The same 2048^2 x 512 x 256 FP32 instance on the general complex path
+    (mirror symmetry not used): complex half-plane slices, 52 bytes per chi
+    point of algorithmic traffic (55.9 GB per step) against the even path's
+    16 (17.2 GB); per-pass times, rates and the roofline of its dominant pass."""
+    old = os.environ.get("LINDHARD_SYMMETRY")
+    os.environ["LINDHARD_SYMMETRY"] = "off"
+    try:
+        plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    finally:
+        if old is None:
+            os.environ.pop("LINDHARD_SYMMETRY", None)
+        else:
+            os.environ["LINDHARD_SYMMETRY"] = old
+    out = plan.empty()
+    plan.exec_timed(out)
+    runs = np.array([plan.exec_timed(out) for _ in range(steps)])
+    pass_avg = runs.mean(axis=0)
+    ms = float(pass_avg.sum())
+    schedule = plan.info.schedule.decode()
+    by, fl_win = algorithmic(cfg, plan.info.lag_hi, False)
+    gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, pass_avg)]
+    fft_window = " P3 fft " in schedule
+    names = ["k_p1", "k_col<float, false>", "k_p3f" if fft_window else "k_p3", "k_col<float, true>", "k_p5"]
+    dom = int(np.argmax(pass_avg))
+    if dom == 2 and not fft_window:
+        ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
+        roof = {"kernel": names[2], "bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS / 2, "unit": "TFLOP/s",
+                "frac": ach / (PEAK_FP32_TFLOPS / 2)}
+    else:
+        roof = {"kernel": names[dom], "bound": "hbm", "achieved": gbs[dom], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": gbs[dom] / PEAK_HBM_GBS}
+    roof["avg_ms"] = float(pass_avg[dom])
+    pts = cfg["nkx"] * cfg["nky"] * len(cfg["omega"])
+    res = {"workload": "2048^2 k, 512 energies, 256 omegas, FP32, general complex path", "ms_per_step": ms,
+           "points_per_s": pts / (ms * 1e-3), "alg_GB_per_step": sum(by) / 1e9,
+           "GB/s_per_step": sum(by) / (ms * 1e-3) / 1e9, "frac_hbm_per_step": sum(by) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "passes": {n: {"ms": float(t), "alg_GB": b / 1e9, "GB/s": g, "frac_hbm": g / PEAK_HBM_GBS, "kernel": k}
+                      for n, t, b, g, k in zip(PASS_NAMES, pass_avg, by, gbs, names)},
+           "roofline": roof, "schedule": schedule}
+    plan.close()
+    return res
+
+
 def bench_3d(LH, W, torch, steps=3):
     """Three-dimensional k-grid with as many points as the main instance:
     256 x 256 x 64 k, 512 energies, 256 omegas, FP32 (general complex path
@@ -316,7 +360,8 @@ def bench_grid_2049(LH, W, torch, steps=2):
     """The paper's own grid size: 2049 x 2049 momenta spanning 16 x 16 zones
     (128 points per zone plus the closing point) with the d(x2-y2) momentum
     density, 512 energies, 256 omegas, FP32 -- a size that is not a power of
-    two, so every transform runs as a Bluestein convolution of length 8192."""
+    two, so every transform runs as a Bluestein convolution of length 4096
+    (the chirp is even, so 2N - 2 points suffice)."""
     cfg = W.config_extended(nk=2049)
     plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
     out = plan.empty()
@@ -341,9 +386,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nk", type=int, default=2048)
     ap.add_argument("--neps", type=int, default=512)
-    ap.add_argument("--window", choices=["auto", "direct", "fft", "even-direct", "even-mfma"], default="auto",
+    ap.add_argument("--window", choices=["auto", "direct", "fft", "even-direct", "even-mfma", "even-mfma4"],
+                    default="auto",
                     help="energy-window variant (auto: the plan's own choice; direct / fft: general path; "
-                         "even-direct / even-mfma: even path on the vector ALUs / the matrix cores)")
+                         "even-direct / even-mfma / even-mfma4: even path on the vector ALUs / the matrix cores "
+                         "as Toeplitz blocks / as 4x4 rank-1 updates)")
     ap.add_argument("--general", action="store_true",
                     help="force the general complex path even for a mirror-symmetric band")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched run")
@@ -353,6 +400,8 @@ def main():
     ap.add_argument("--no-extended", action="store_true",
                     help="skip the extended-momentum instance (16x16 zones, momentum density weights)")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional k-grid instance")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the same instance on the general complex path (symmetry not used)")
     ap.add_argument("--no-2049", action="store_true", help="skip the 2049^2 (not a power of two) instance")
     ap.add_argument("--no-multiband", action="store_true",
                     help="skip the two-band instances (summed spectral function, band-pair sum)")
@@ -426,12 +475,14 @@ def main():
     gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, pass_avg)]
     dom = int(np.argmax(pass_avg))
     src = [os.path.join(ROOT, "paper_1208_3210_amd", "csrc", f) for f in ("lh_kernels.hip", "lh_fft.h",
-                                                                           "lh_regfft.h")]
+                                                                           "lh_regfft.h", "lh_window.hip")]
     khash = src_hash(src)
     fft_window = " P3 fft " in schedule
     mfma_window = " P3 mfma " in schedule
+    mfma4_window = " P3 mfma4 " in schedule
     if even:
-        KERNEL_NAMES[:] = ["k_e1", "k_ecol<float, false>", "k_e3m" if mfma_window else "k_e3",
+        KERNEL_NAMES[:] = ["k_e1", "k_ecol<float, false>",
+                           "k_e3q" if mfma4_window else "k_e3m" if mfma_window else "k_e3",
                            "k_ecol<float, true>", "k_e5"]
     elif fft_window:
         KERNEL_NAMES[2] = "k_p3f"
@@ -440,9 +491,11 @@ def main():
         # event-timed duration; the matrix-core form runs on the FP32 MFMA
         # peak, the direct form on the FP32 vector peak
         ach = fl_win / (pass_avg[2] * 1e-3) / 1e12
-        roof = {"kernel": KERNEL_NAMES[2], "bound": "mfma" if mfma_window else "alu", "achieved": ach,
+        on_mfma = mfma_window or mfma4_window
+        roof = {"kernel": KERNEL_NAMES[2], "bound": "mfma" if on_mfma else "alu", "achieved": ach,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS,
-                "traffic": traffic_from_profiles(KERNEL_NAMES[2], khash)}
+                "traffic": traffic_from_profiles(KERNEL_NAMES[2], khash),
+                "count": "useful flops: 2 per multiply-add of the energy sums, %.3g per step" % fl_win}
     else:
         roof = {"kernel": KERNEL_NAMES[dom], "bound": "hbm", "achieved": gbs[dom], "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM_GBS,
@@ -456,6 +509,13 @@ def main():
         # the 16x16 Toeplitz blocks also multiply the zero upper triangle
         pts = (cfg["nkx"] // 2 + 1) * (cfg["nky"] // 2 + 1)
         passes["p3_window"]["mfma_issued_TFLOP/s"] = pts * 16 * 2 * 16 ** 3 / (pass_avg[2] * 1e-3) / 1e12
+    if mfma4_window:
+        # 4x4 rank-1 blocks, one point each: tile t of 16 lags takes 16 (t + 1)
+        # steps, plus the zero-padded ends (T(T-1)/2 partial chunks per group skipped)
+        pts = (cfg["nkx"] // 2 + 1) * (cfg["nky"] // 2 + 1)
+        nT = (plan.info.lag_hi + 15) // 16
+        steps4 = sum(16 * (t + 1) for t in range(nT))
+        passes["p3_window"]["mfma_issued_TFLOP/s"] = pts * steps4 * 32 / (pass_avg[2] * 1e-3) / 1e12
     for n, k in zip(PASS_NAMES, KERNEL_NAMES):
         passes[n]["kernel"] = k
     lat = np.array(step_ms)
@@ -497,6 +557,11 @@ def main():
         print("bench: two bands summed %.3f ms, pairs %.3f ms" % (mb["summed"]["ms_per_step"],
                                                                  mb["pairs"]["ms_per_step"]), file=sys.stderr,
               flush=True)
+    gen = None if args.no_general else bench_general(LH, W, torch, cfg)
+    if gen:
+        print("bench: general path %.3f ms/step (%.2f TB/s on its 55.9 GB)" % (gen["ms_per_step"],
+                                                                           gen["GB/s_per_step"] / 1e3),
+              file=sys.stderr, flush=True)
     k3 = None if args.no_3d else bench_3d(LH, W, torch)
     if k3:
         print("bench: 3d %.3f ms/step" % k3["ms_per_step"], file=sys.stderr, flush=True)
@@ -517,7 +582,13 @@ def main():
                    "neps": cfg["neps"], "nomega": len(cfg["omega"]), "gamma_eV": cfg["gamma"],
                    "points_per_step": points, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": roof, "passes": passes, "fp64_gpu": fp64, "batched": batched, "served": served,
+        "roofline": roof, "passes": passes,
+        "traffic_basis": {"even_path_alg_GB_per_step": sum(by) / 1e9 if even else None,
+                          "even_path_B_per_point": sum(by) / points if even else None,
+                          "general_schedule_alg_GB_per_step": sum(algorithmic(cfg, plan.info.lag_hi, False)[0]) / 1e9,
+                          "note": "pass rates use the bytes of the path that ran (the even path stores real quarter "
+                                  "planes: 16 B per chi point; the general complex schedule moves 52 B per point)"},
+        "general_path": gen, "fp64_gpu": fp64, "batched": batched, "served": served,
         "epilogues": epi, "extended_momentum": ext, "multiband": mb, "k3d": k3, "grid_2049": g2049,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
