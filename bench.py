@@ -338,6 +338,24 @@ def bench_general(LH, W, torch, cfg, steps=3):
     return res
 
 
+def bench_grid_4096(LH, W, torch, steps=3):
+    """The largest power-of-two grid: 4096 x 4096 k, 512 energies, 256 omegas,
+    FP32 (four times the points of the main instance; the staged slices of the
+    energy window span more than 4 GiB)."""
+    cfg = W.config3(nk=4096)
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    out = plan.empty()
+    plan.exec_timed(out)
+    runs = [plan.exec_timed(out) for _ in range(steps)]
+    ms = float(np.mean([sum(r) for r in runs]))
+    pts = cfg["nkx"] * cfg["nky"] * len(cfg["omega"])
+    res = {"workload": "4096^2 k, 512 energies, 256 omegas, FP32", "ms_per_step": ms,
+           "points_per_s": pts / (ms * 1e-3), "passes_ms": [float(np.mean([r[i] for r in runs])) for i in range(5)],
+           "schedule": plan.info.schedule.decode()}
+    plan.close()
+    return res
+
+
 def bench_3d(LH, W, torch, steps=3):
     """Three-dimensional k-grid with as many points as the main instance:
     256 x 256 x 64 k, 512 energies, 256 omegas, FP32 (general complex path
@@ -403,6 +421,7 @@ def main():
     ap.add_argument("--no-general", action="store_true",
                     help="skip the same instance on the general complex path (symmetry not used)")
     ap.add_argument("--no-2049", action="store_true", help="skip the 2049^2 (not a power of two) instance")
+    ap.add_argument("--no-4096", action="store_true", help="skip the 4096^2 instance")
     ap.add_argument("--no-multiband", action="store_true",
                     help="skip the two-band instances (summed spectral function, band-pair sum)")
     ap.add_argument("--epilogues-only", action="store_true",
@@ -568,6 +587,9 @@ def main():
     g2049 = None if args.no_2049 else bench_grid_2049(LH, W, torch)
     if g2049:
         print("bench: 2049^2 grid %.3f ms/step" % g2049["ms_per_step"], file=sys.stderr, flush=True)
+    g4096 = None if args.no_4096 else bench_grid_4096(LH, W, torch)
+    if g4096:
+        print("bench: 4096^2 grid %.3f ms/step" % g4096["ms_per_step"], file=sys.stderr, flush=True)
     epi = None if args.no_epilogues else bench_epilogues(LH, W, torch)
     if epi:
         print("bench: epilogues " + ", ".join("%s %.3f ms" % (k, v["ms"]) for k, v in epi.items()
@@ -590,6 +612,7 @@ def main():
                                   "planes: 16 B per chi point; the general complex schedule moves 52 B per point)"},
         "general_path": gen, "fp64_gpu": fp64, "batched": batched, "served": served,
         "epilogues": epi, "extended_momentum": ext, "multiband": mb, "k3d": k3, "grid_2049": g2049,
+        "grid_4096": g4096,
         "cpu_baseline": cpu,
         "kernel_src_hash": khash, "schedule": schedule,
     }

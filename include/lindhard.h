@@ -77,7 +77,7 @@ typedef struct {
     double mu;                  /* eV; NaN = solve from `filling` */
     double filling;             /* electrons per site, both spins (1 + x) */
     double gamma;               /* Lorentzian half width of Eq. (5), eV, > 0 */
-    int32_t nkx, nky;           /* powers of two 4 .. 2048; other sizes >= 4 (Bluestein
+    int32_t nkx, nky;           /* powers of two 4 .. 4096; other sizes >= 4 (Bluestein
                                    transforms) up to 4097 in FP32 and 2049 in FP64 with one
                                    zone, one band, no form factor and no RPA */
     int32_t neps;               /* power of two, 4 .. 2048 */

@@ -76,11 +76,11 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
 {
     if (!p) return LINDHARD_EINVAL;
     if (p->precision != LINDHARD_FP32C && p->precision != LINDHARD_FP64) return LINDHARD_EINVAL;
-    // powers of two up to 2048; other sizes (Bluestein transforms) up to 4097
+    // powers of two up to 4096; other sizes (Bluestein transforms) up to 4097
     // in FP32 and 2049 in FP64, one zone, one band, no form factor, no RPA
     const bool any_size = !is_pow2(p->nkx) || !is_pow2(p->nky);
     if (p->nkx < 4 || p->nky < 4) return LINDHARD_EINVAL;
-    if (!any_size && (p->nkx > 2048 || p->nky > 2048)) return LINDHARD_EINVAL;
+    if (!any_size && (p->nkx > 4096 || p->nky > 4096)) return LINDHARD_EINVAL;
     if (any_size) {
         const int lim = p->precision == LINDHARD_FP64 ? 2049 : 4097;
         if (p->nkx > lim || p->nky > lim) return LINDHARD_EINVAL;
@@ -363,7 +363,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             if ((1 << ilog2(np)) > np) R = std::min(R, 1 << (ilog2(np) - 1));
             return std::max(1, R);
         };
-        g.e1_R = rows_per_block(kE1Elems);
+        g.e1_R = rows_per_block(e1_elems(g.logNx));
         g.e5_R = rows_per_block(16);
         {
             const long blocks = (np + g.e1_R - 1) / g.e1_R;
@@ -418,7 +418,8 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
             // (the zero rows of the staging wrap to offsets past the range)
             const double sl4 = (double)g.slice_e * 4.0, lim = 4294967040.0;
             const bool fits32 = (g.e3q_nAst + 96) * sl4 < lim && (g.e3q_nHst + 96) * sl4 < lim && g.nL * sl4 < lim;
-            g.e3q_ok = g.e3q_umax >= 0 && fits32 && e3q_lds_bytes(g, 1) <= 65536;
+            g.e3q_big = fits32 ? 0 : 1;  // else 64-bit addresses
+            g.e3q_ok = g.e3q_umax >= 0 && e3q_lds_bytes(g, 1) <= 65536;
         }
         g.e3_variant = 0;
         if (const char *ev = std::getenv("LINDHARD_EVEN_WINDOW")) {

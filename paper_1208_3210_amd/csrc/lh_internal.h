@@ -73,6 +73,7 @@ struct Geo {
     // e3q_W waves of 16 points per block
     int e3q_ok, e3q_nT, e3q_U0, e3q_a0, e3q_offP, e3q_umax, e3q_cmax, e3q_LP, e3q_LH, e3q_PSP, e3q_PSH;
     int e3q_nAst, e3q_nHst, e3q_W;
+    int e3q_big;              // offsets past 4 GiB: 64-bit addressing
     // energy-window variant: 0 direct (compensated in FP32), 1 FFT along energy
     int p3_variant;
     int logNE;                // FFT length along energy for variant 1
@@ -88,6 +89,11 @@ struct Geo {
 // Elements per thread of the register FFTs in the even builder pass (the
 // builder also keeps the band rows of its lines in registers).
 constexpr int kE1Elems = 8;
+// ... except on 4096-point rows, where eight would take 512 threads per line
+constexpr int e1_elems(int logn) { return logn >= 12 ? 16 : kE1Elems; }
+// Threads per block of the column passes: up to 512, 1024 for 4096-point
+// columns (one tile of C lines of 256 threads each)
+constexpr int col_threads(int logn) { return logn >= 12 ? 1024 : 512; }
 // ... and in the general builder pass, for the same reason (with sixteen it
 // needs ~220 registers and two waves per SIMD; with eight ~120 and four).
 constexpr int kP1Elems = 8;

@@ -300,7 +300,8 @@ __global__ void __launch_bounds__(kThreads) k_p1(const double *__restrict__ xi, 
 // register FFT and back.  TPB tiles per block keep small transforms at 256
 // threads.  Transformed in place.
 template <typename T, int LOGN, bool INV>
-__global__ void __launch_bounds__(512) k_col(cx<T> *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
+__global__ void __launch_bounds__(col_threads(LOGN)) k_col(cx<T> *__restrict__ spec, Geo g,
+                                                          const cx<T> *__restrict__ twy)
 {
     using F = RegFFT<T, LOGN, INV, 4, kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -688,11 +689,11 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // kernel otherwise takes one register more than four waves allow); FP64 would
 // spill under that bound.
 template <typename T, int LOGNX, bool W>
-__global__ void __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 1) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 4 && LOGNX < 12) ? 4 : 1) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
                                                 const T *__restrict__ rho, int acc)
 {
-    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems), kTwLds<T>>;
+    using F = RegFFT<T, LOGNX, false, ilog2_c(e1_elems(LOGNX)), kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N]
@@ -781,7 +782,8 @@ __global__ void __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 1) k_e1(const d
 // real columns of a tile (read as one complex value per row); rows above
 // nky/2 are the mirror of the stored ones.  Transformed in place.
 template <typename T, int LOGN, bool INV>
-__global__ void __launch_bounds__(512) k_ecol(T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twy)
+__global__ void __launch_bounds__(col_threads(LOGN)) k_ecol(T *__restrict__ spec, Geo g,
+                                                           const cx<T> *__restrict__ twy)
 {
     using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems), kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -2319,7 +2321,7 @@ template <typename T, int LOGNX>
 static void launch_e1(const Plan &pl, T *spec, int band, int acc, hipStream_t st)
 {
     const Geo &g = pl.g;
-    using F = RegFFT<T, LOGNX, false, ilog2_c(kE1Elems)>;
+    using F = RegFFT<T, LOGNX, false, ilog2_c(e1_elems(LOGNX))>;
     const int np = (g.Hy + 1) / 2;
     const dim3 grid(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc));
     const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);
@@ -2372,6 +2374,13 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     case 10: CALL(10); break;                    \
     case 11: CALL(11); break;                    \
     default: return hipErrorInvalidValue;        \
+    }
+
+// The same for the transform lengths of the k axes (up to 4096 points).
+#define LH_SWITCH_LOG12(v, CALL)                 \
+    switch (v) {                                 \
+    case 12: CALL(12); break;                    \
+    default: LH_SWITCH_LOG(v, CALL)              \
     }
 
 #define LH_HIP_TRY(x)                     \
@@ -2516,7 +2525,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     auto p1 = [&](void *dst, int band, int acc) -> hipError_t {
         if (g.even) {
 #define LH_E1(LG) launch_e1<T, LG>(pl, (T *)dst, band, acc, st)
-            LH_SWITCH_LOG(g.logNx, LH_E1)
+            LH_SWITCH_LOG12(g.logNx, LH_E1)
 #undef LH_E1
         } else {
             for (int z = 0; z < g.nkz; ++z) {
@@ -2533,11 +2542,11 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         if (g.even) {
             if (inv) {
 #define LH_E4(LG) launch_ecol<T, LG, true>(pl, (T *)buf, n, st)
-                LH_SWITCH_LOG(g.logNy, LH_E4)
+                LH_SWITCH_LOG12(g.logNy, LH_E4)
 #undef LH_E4
             } else {
 #define LH_E2(LG) launch_ecol<T, LG, false>(pl, (T *)buf, n, st)
-                LH_SWITCH_LOG(g.logNy, LH_E2)
+                LH_SWITCH_LOG12(g.logNy, LH_E2)
 #undef LH_E2
             }
         } else {
@@ -2548,11 +2557,11 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
 #undef LH_PZ
                 }
 #define LH_P4(LG) launch_col<T, LG, true>(pl, (cx<T> *)buf, n, st)
-                LH_SWITCH_LOG(g.logNy, LH_P4)
+                LH_SWITCH_LOG12(g.logNy, LH_P4)
 #undef LH_P4
             } else {
 #define LH_P2(LG) launch_col<T, LG, false>(pl, (cx<T> *)buf, n, st)
-                LH_SWITCH_LOG(g.logNy, LH_P2)
+                LH_SWITCH_LOG12(g.logNy, LH_P2)
 #undef LH_P2
                 if (g.nkz > 1) {
 #define LH_PZ(LG) launch_zcol<T, LG, false>(pl, (cx<T> *)buf, n, st)
@@ -2570,11 +2579,11 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
             T *spr = (T *)buf;
             if (rpa) {
 #define LH_E5(LG) launch_e5<T, LG, 1>(pl, spr, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
-                LH_SWITCH_LOG(g.logNx, LH_E5)
+                LH_SWITCH_LOG12(g.logNx, LH_E5)
 #undef LH_E5
             } else {
 #define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
-                LH_SWITCH_LOG(g.logNx, LH_E5)
+                LH_SWITCH_LOG12(g.logNx, LH_E5)
 #undef LH_E5
             }
         } else {

@@ -85,6 +85,10 @@ __device__ __forceinline__ f4v buf_load4(__amdgpu_buffer_rsrc_t r, unsigned off)
 // shares are equal when the group count is a multiple of four).  Two blocks'
 // waves share each SIMD, so one block's staging and operand loads overlap
 // another's products.
+// BIG: the staged slice ranges or the output reach past 4 GiB of byte
+// offsets, so the block uses 64-bit addresses (flat loads and stores) instead
+// of buffer descriptors.
+template <bool BIG>
 __global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, Geo g)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -129,8 +133,36 @@ __global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, G
                 }
             }
         };
-        stage(rP, Pl + (size_t)(4 * q) * PSP, LP, pb4 + (unsigned)(nAst - 1 + 16 + g.e3q_offP) * sl4, -1);
-        stage(rH, Hl + (size_t)(4 * q) * PSH, LH, pb4 - 3u * sl4, 1);
+        // 64-bit form: row r of P' is slice j0 - 1 - (r - 16 - offP) when that
+        // holds a value, of H' slice j0 + r - 3; other rows read 0
+        auto stage64 = [&](float *dst0, int st, int npos, int vlo, int vhi, long slice0, int dir) {
+            const float *src0 = spec + p0 + 4 * q;
+            for (int rb = r0; rb < npos; rb += UNR * RPI) {
+                f4v v[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const int r = rb + k * RPI;
+                    const bool ok = r >= vlo && r < vhi;
+                    const f4v x4 = *reinterpret_cast<const f4v *>(src0 + (ok ? (size_t)(slice0 + (long)dir * r) * sl : 0));
+                    v[k] = ok ? x4 : f4v{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    if (rb + k * RPI < npos) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dst0[e * st + rb + k * RPI] = v[k][e];
+                    }
+                }
+            }
+        };
+        const int offP = g.e3q_offP;
+        if constexpr (BIG) {
+            stage64(Pl + (size_t)(4 * q) * PSP, PSP, LP, 16 + offP, 16 + offP + nAst, (long)j0r - 1 + 16 + offP, -1);
+            stage64(Hl + (size_t)(4 * q) * PSH, PSH, LH, 3, 3 + nHst, (long)j0r - 3, 1);
+        } else {
+            stage(rP, Pl + (size_t)(4 * q) * PSP, LP, pb4 + (unsigned)(nAst - 1 + 16 + offP) * sl4, -1);
+            stage(rH, Hl + (size_t)(4 * q) * PSH, LH, pb4 - 3u * sl4, 1);
+        }
     }
     __syncthreads();
 
@@ -240,9 +272,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, G
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int slot = 16 * t + i + 4 * qd;
-                if (slot < nL)
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, sum[k][i] - cmp[k][i]), rO,
-                                                          (int)(ob0 + (unsigned)(16 * t + i) * sl4), 0, 0);
+                if (slot < nL) {
+                    if constexpr (BIG)
+                        spec[(size_t)slot * sl + p0 + b] = sum[k][i] - cmp[k][i];
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, sum[k][i] - cmp[k][i]),
+                                                              rO, (int)(ob0 + (unsigned)(16 * t + i) * sl4), 0, 0);
+                }
             }
         }
     }
@@ -260,7 +296,10 @@ hipError_t launch_e3q(const Plan &pl, int, hipStream_t st)
 {
     const Geo &g = pl.g;
     const dim3 grid((unsigned)((g.slice_e + kPoints - 1) / kPoints));
-    hipLaunchKernelGGL(k_e3q, grid, dim3(64 * kWaves), e3q_lds_bytes(g, 1), st, (float *)pl.spec, g);
+    if (g.e3q_big)
+        hipLaunchKernelGGL(k_e3q<true>, grid, dim3(64 * kWaves), e3q_lds_bytes(g, 1), st, (float *)pl.spec, g);
+    else
+        hipLaunchKernelGGL(k_e3q<false>, grid, dim3(64 * kWaves), e3q_lds_bytes(g, 1), st, (float *)pl.spec, g);
     return hipGetLastError();
 }
 

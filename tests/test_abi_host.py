@@ -48,7 +48,9 @@ def _base(**over):
 
 @pytest.mark.parametrize("over,status", [
     (dict(nkx=48, zones=(3, 1)), -1), (dict(nkx=2050), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
-    (dict(nkx=4096), -1), (dict(nkx=48, want_rpa=True), -1), (dict(neps=100), -1), (dict(neps=2), -1),
+    (dict(nkx=8192), -1), (dict(nky=8192), -1), (dict(nkx=48, want_rpa=True), -1), (dict(neps=100), -1),
+    (dict(neps=2), -1), (dict(omega=np.arange(65536) / 32.0 % 1.0), -1),
+    (dict(nky=4096, zones=(1, 17)), -1),
     (dict(emin=0.1), -1), (dict(emax=-0.1), -1), (dict(gamma=0.0), -1), (dict(gamma=math.nan), -1),
     (dict(precision=3), -1), (dict(zones=(2, 1)), -1), (dict(zones=(1, 0)), -1), (dict(ff_kind=7), -1),
     (dict(ff_kind=1, ff_width=0.0), -1), (dict(filling=2.5), -1), (dict(mu=math.inf), -1),
@@ -145,3 +147,24 @@ def test_offgrid_omega_accepted_with_interp_on_the_host():
 
     p, keep = LH.make_problem(**_base(omega=[1.5 / 32.0, 2.0 / 32.0], omega_interp=True))
     assert LH.problem_shape(p) == (2, 32, 32)
+
+
+def test_shape_limits_match_the_header():
+    """Powers of two up to 4096 per axis, up to 65535 omegas, zones_y * nky
+    up to 65535 (host-side validation through lindhard_problem_shape)."""
+    import ctypes
+
+    from paper_1208_3210_amd import lindhard as LH
+
+    def shape(**over):
+        p, keep = LH.make_problem(**_base(**over))
+        v = [ctypes.c_int32() for _ in range(4)]
+        st = LH.lib().lindhard_problem_shape(ctypes.byref(p), *[ctypes.byref(x) for x in v])
+        return st, tuple(x.value for x in v)
+
+    assert shape(nkx=4096, nky=4096) == (0, (32, 4096, 4096, 8))
+    assert shape(nkx=4096, nky=4096, precision=1) == (0, (32, 4096, 4096, 4))
+    assert shape(nkx=8192)[0] == -1
+    assert shape(omega=np.arange(65535) % 32 / 32.0)[0] == 0
+    assert shape(nky=4096, zones=(1, 15))[0] == 0
+    assert shape(nkx=4096, zones=(15, 1)) == (0, (32, 32, 15 * 4096, 8))

@@ -410,3 +410,62 @@ def test_autotuner_times_once_per_shape_and_caches(tmp_path, monkeypatch):
     assert normwise(got.double().cpu().numpy(), ref) <= 1e-5
     gen.close()
     assert (tmp_path / "tune.txt").exists()
+
+
+@pytest.mark.parametrize("window", ["auto", "direct", "fft"], indirect=True)
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid_4096_sampled_and_q_sum(prec, window):
+    """The largest power-of-two grid, 4096^2 k (128 energies on [-2, 2] eV,
+    lags 1..64, G = 0.02 eV): sampled (q, m) against the oracle's direct sum
+    and the q-sum identity (the oracle's q-average from k-averaged spectral
+    weights) at every lag, on the even and the general path."""
+    cfg = W.config3(nk=4096, neps=128)
+    cfg.update(gamma=0.02, omega=W.lag_omegas(128, -2.0, 2.0, range(1, 65)))
+    n, neps = cfg["nkx"], cfg["neps"]
+    xi, mu = oracle_xi(cfg)
+    plan = LH.Plan(precision=prec, **cfg)
+    assert abs(plan.info.mu - mu) < 1e-12
+    sched = plan.info.schedule.decode()
+    assert (" even " in sched) == (window == "auto")
+    out = plan.exec()
+    torch.cuda.synchronize()
+    samples = [(0, 0, 1), (n // 2, 0, 32), (n // 2, n // 2, 64), (1234, 3001, 17), (4095, 1, 50), (7, 2048, 3)]
+    qx = np.array([s[0] for s in samples])
+    qy = np.array([s[1] for s in samples])
+    ms = np.array([s[2] for s in samples])
+    ref = oracle.chi_pairs(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], qx, qy, ms)
+    got = np.array([out[m - 1, (b + n // 2) % n, (a + n // 2) % n].item() for a, b, m in samples])
+    scale = out.abs().max().item()
+    err_s = np.abs(got - ref).max() / scale
+    qref = oracle.chi_qmean(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], lags_of(cfg))
+    qgot = out.double().mean(dim=(1, 2)).cpu().numpy()
+    err_q = normwise(qgot, qref)
+    print("4096^2 prec=%d window=%s sampled err %.3e, q-sum err %.3e, %s" % (prec, window, err_s, err_q, sched))
+    plan.close()
+    assert err_s <= TOL[prec] and err_q <= TOL[prec]
+
+
+@pytest.mark.parametrize("window", ["auto", "even-mfma4"], indirect=True)
+def test_grid_4096_512_energies_sampled(window):
+    """4096^2 k x 512 energies x 256 lags, FP32: the energy window's staged
+    slices then span more than 4 GiB of byte offsets (the rank-1 matrix window
+    switches to 64-bit addressing); sampled (q, m) against the oracle."""
+    cfg = W.config3(nk=4096)
+    n, neps = cfg["nkx"], cfg["neps"]
+    xi, mu = oracle_xi(cfg)
+    plan = LH.Plan(precision=LH.LINDHARD_FP32C, **cfg)
+    sched = plan.info.schedule.decode()
+    if window == "even-mfma4":
+        assert " P3 mfma4 " in sched
+    out = plan.exec()
+    torch.cuda.synchronize()
+    samples = [(0, 0, 1), (n // 2, n // 2, 256), (1234, 3001, 170), (4095, 1, 50), (7, 2048, 255), (999, 17, 128)]
+    qx = np.array([s[0] for s in samples])
+    qy = np.array([s[1] for s in samples])
+    ms = np.array([s[2] for s in samples])
+    ref = oracle.chi_pairs(xi, neps, cfg["emin"], cfg["emax"], cfg["gamma"], qx, qy, ms)
+    got = np.array([out[m - 1, (b + n // 2) % n, (a + n // 2) % n].item() for a, b, m in samples])
+    err = np.abs(got - ref).max() / out.abs().max().item()
+    print("4096^2 x 512 [%s] sampled err %.3e, %s" % (window, err, sched))
+    plan.close()
+    assert err <= 1e-5
