@@ -122,13 +122,36 @@ def bench_batched(LH, W, torch, steps=3):
             "points_per_s": points / (ms * 1e-3), "plan_s_total": t_plan}
 
 
-def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
-    """Poisson stream (mean 200 req/s) of mixed jobs through the server;
-    latency = submit -> result ready, reported over the requests after warm-up."""
+def served_warm_set(LH, W):
+    """One problem per plan class and window-schedule bucket of the served
+    stream: every grid and energy count, RPA or not, and (without RPA) the
+    highest lag of each 32-lag bucket that 16..128 omegas reach."""
+    warm = []
+    band = dict(t=0.4, tp=-0.1, tpp=0.04, filling=1.1, gamma=0.04)
+    for nk in (128, 256, 512, 1024):
+        for neps in (64, 128, 256, 512):
+            base = dict(**band, nkx=nk, nky=nk, neps=neps, emin=-2.0, emax=2.0, zones=(1, 1), ff_kind=0,
+                        ff_width=0.0, precision=LH.LINDHARD_FP32C)
+            warm.append(dict(base, omega=W.lag_omegas(neps, -2.0, 2.0, range(1, 129)), want_rpa=True))
+            for top in (32, 64, 96, 128):
+                if top - 31 < neps:
+                    warm.append(dict(base, omega=W.lag_omegas(neps, -2.0, 2.0, range(1, min(top, neps - 1) + 1))))
+    return warm
+
+
+def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0, n_iso=400):
+    """Poisson stream (mean 200 req/s) of mixed jobs through the server, its
+    plan classes planned at creation; latency = submit -> result ready,
+    reported over the requests after warm-up.  Then every fifth measured job
+    again, alone (submitted after the previous one finished), for its
+    isolated latency: the ratio served / isolated per job shows what the mix
+    adds to each job, apart from the spread of job sizes."""
     jobs = W.config5(n_req=n_warm + n_req, rate_hz=rate_hz)
-    srv = LH.Server(hbm_budget_bytes=64 << 30, max_inflight=8, max_queue=4096)
+    t_c = time.perf_counter()
+    srv = LH.Server(hbm_budget_bytes=64 << 30, max_inflight=8, max_queue=4096, warm=served_warm_set(LH, W))
+    t_create = time.perf_counter() - t_c
     live = {}
-    lat = []
+    lat = {}
     t0 = time.perf_counter()
     done_points = 0
 
@@ -139,7 +162,7 @@ def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
             if fin:
                 k, t_sub, pts = live.pop(t)
                 if st == LH.LINDHARD_OK and k >= n_warm:
-                    lat.append((time.perf_counter() - t_sub) * 1e3)
+                    lat[k] = (time.perf_counter() - t_sub) * 1e3
                     done_points += pts
                 srv._keep.pop(t, None)
     t_first = None
@@ -163,13 +186,33 @@ def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0):
         time.sleep(0.0005)
     wall = time.perf_counter() - t_first
     st = srv.stats()
+    # isolated latencies of a sample of the same jobs
+    iso = {}
+    for k in sorted(lat)[::max(1, n_req // n_iso)]:
+        job = jobs[k]
+        t_sub = time.perf_counter()
+        ticket, outs = srv.submit(job["U"], precision=LH.LINDHARD_FP32C, **job["problem"])
+        while not srv.poll(ticket)[0]:
+            time.sleep(0.00005)
+        iso[k] = (time.perf_counter() - t_sub) * 1e3
+        srv._keep.pop(ticket, None)
+    st2 = srv.stats()
     srv.close()
-    lat = np.array(lat)
+    v = np.array(list(lat.values()))
+    ks = sorted(iso)
+    iv = np.array([iso[k] for k in ks])
+    ratio = np.array([lat[k] / iso[k] for k in ks])
+    pc = lambda a, q: float(np.percentile(a, q))  # noqa: E731
     return {"requests": n_req, "warmup_requests": n_warm, "rate_hz": rate_hz,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "p50_ms": pc(v, 50), "p99_ms": pc(v, 99),
+            "isolated_p50_ms": pc(iv, 50), "isolated_p99_ms": pc(iv, 99), "isolated_sample": len(ks),
+            "served_over_isolated_p50": pc(ratio, 50), "served_over_isolated_p99": pc(ratio, 99),
             "points_per_s": done_points / wall, "completed": int(st.completed), "failed": int(st.failed),
-            "hbm_high_water_GB": st.hbm_high_water / 1e9, "max_inflight": 8,
-            "latency_note": "submit -> result ready, host clock, requests after warm-up"}
+            "plan_builds": int(st.plan_builds), "plan_reuses": int(st.plan_reuses),
+            "plan_evictions": int(st.plan_evictions), "warm_classes_s": t_create,
+            "hbm_high_water_GB": st2.hbm_high_water / 1e9, "max_inflight": 8,
+            "latency_note": "submit -> result ready, host clock, requests after warm-up; isolated: the same "
+                            "jobs one at a time on the warm server"}
 
 
 def bench_epilogues(LH, W, torch, reps=3):
@@ -566,8 +609,11 @@ def main():
         print("bench: batched %.3f ms per 64 instances" % batched["ms_per_batch"], file=sys.stderr, flush=True)
     served = None if args.no_served else bench_served(LH, W, torch)
     if served:
-        print("bench: served p50 %.2f ms p99 %.2f ms" % (served["p50_ms"], served["p99_ms"]), file=sys.stderr,
-              flush=True)
+        print("bench: served p50 %.2f ms p99 %.2f ms (isolated p50 %.2f p99 %.2f; served/isolated p50 %.2f "
+              "p99 %.2f; %d builds, %d reuses)" % (served["p50_ms"], served["p99_ms"], served["isolated_p50_ms"],
+                                                   served["isolated_p99_ms"], served["served_over_isolated_p50"],
+                                                   served["served_over_isolated_p99"], served["plan_builds"],
+                                                   served["plan_reuses"]), file=sys.stderr, flush=True)
     ext = None if args.no_extended else bench_extended(LH, W, torch)
     if ext:
         print("bench: extended momentum %.3f ms/step" % ext["ms_per_step"], file=sys.stderr, flush=True)

@@ -300,25 +300,46 @@ lindhard_status lindhard_plan_destroy(lindhard_plan_t plan);
 
 /* ---------------------------------------------------------------- serving */
 typedef struct {
-    size_t hbm_budget_bytes; /* admission limit on the sum of in-flight workspaces */
+    size_t hbm_budget_bytes; /* limit on the device memory of every plan the server holds */
     int32_t max_inflight;    /* concurrent jobs on the device (>= 1) */
     int32_t max_queue;       /* queued (not yet admitted) jobs (>= 1) */
+    /* optional: problems planned when the server starts (n_warm of them, the
+     * arrays they point to read during lindhard_serve_create only), so that
+     * the first jobs of their classes find a plan and a tuned window schedule;
+     * NULL / 0 for none */
+    const lindhard_problem *warm;
+    int32_t n_warm;
 } lindhard_serve_config;
 
 typedef struct lindhard_server_s *lindhard_server_t;
 
 typedef struct {
     uint64_t submitted, completed, failed, rejected, canceled;
-    double p50_ms, p99_ms;   /* submit -> result-ready latency of completed jobs */
+    double p50_ms, p99_ms;   /* submit -> result-ready latency of the last 65536 completed jobs */
     double points_per_s;     /* output points of completed jobs / wall time since create */
-    size_t hbm_high_water;   /* largest sum of admitted workspaces seen */
+    size_t hbm_high_water;   /* largest device memory held by the server's plans */
     int32_t queue_depth, inflight;
+    uint64_t plan_reuses;    /* jobs that ran on a cached plan of their class */
+    uint64_t plan_builds;    /* plans built from scratch (warm problems included) */
+    uint64_t plan_evictions; /* idle plans freed to make room */
+    int32_t cached_plans;    /* idle plans held right now */
+    size_t resident_bytes;   /* device memory held by the server's plans right now */
 } lindhard_serve_stats;
 
-/* Start a server: a host admission thread that admits queued jobs while the
- * sum of their workspaces stays within the budget and a slot is free, and runs
- * each admitted job (plan, exec, optional rpa) on a stream of its own so that
- * jobs overlap on the device.  Errors: EINVAL, ENOMEM, EDEVICE. */
+/* Start a server.  Worker threads (max_inflight of them, each with a stream
+ * of its own) admit queued jobs in arrival order while a slot is free and the
+ * memory of all plans the server holds stays within the budget, and run each
+ * admitted job (exec, optional rpa) so that jobs overlap on the device.
+ * Plans are cached by class: everything that fixes a plan's tables and buffer
+ * layout (precision, grid, energy window, zones, form factor, RPA, bands,
+ * symmetry), but not the band, broadening, filling, chemical potential or
+ * omega list.  A job takes an idle plan of its class and rebinds it (band, mu,
+ * omegas; buffers grow when its lag range needs more), so it neither builds
+ * tables nor times window schedules; only a job of a new class plans from
+ * scratch.  Idle plans are freed, least recently used first, when a job
+ * needs their memory.  A job's result equals that of lindhard_plan +
+ * lindhard_exec (+ lindhard_rpa) on its problem, bit for bit.
+ * Errors: EINVAL, ENOMEM, EDEVICE, or the planning status of a warm problem. */
 lindhard_status lindhard_serve_create(const lindhard_serve_config *cfg, lindhard_server_t *out);
 
 /* Queue one job.  The problem (and its omega / eps_table arrays) is copied.
@@ -331,11 +352,14 @@ lindhard_status lindhard_serve_submit(lindhard_server_t s, const lindhard_proble
                                       void *re_rpa, uint64_t *ticket);
 
 /* Non-blocking completion check: *done = 1 when finished (then *job_status is
- * the job's own status). */
+ * the job's own status).  Once a call has reported a job finished, the server
+ * forgets it: later calls with its ticket return EINVAL. */
 lindhard_status lindhard_serve_poll(lindhard_server_t s, uint64_t ticket, int32_t *done,
                                     lindhard_status *job_status);
 
-/* Block until the job finishes or timeout_s passes (EBUSY on timeout). */
+/* Block until the job finishes or timeout_s passes (EBUSY on timeout); a
+ * negative timeout waits for good.  As with poll, the ticket is released once
+ * the job has been reported finished. */
 lindhard_status lindhard_serve_wait(lindhard_server_t s, uint64_t ticket, double timeout_s,
                                     lindhard_status *job_status);
 

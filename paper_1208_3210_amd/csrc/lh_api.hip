@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <complex>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -11,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <new>
+#include <set>
 #include <vector>
 
 #include "lh_internal.h"
@@ -447,29 +449,49 @@ static size_t scratch_bytes(const Plan &pl)
     return std::max<size_t>(2 * kOccBlocks + 2, (size_t)pl.p.nomega * kQavgBlocks) * sizeof(double);
 }
 
-size_t plan_footprint(const Plan &pl)
+// The device buffers of a plan in a fixed order, each with its size for the
+// plan's geometry (0: not needed).  Planning allocates them; rebinding a
+// cached plan to another problem of its class grows the ones that are short.
+std::vector<BufSpec> plan_buffers(const Plan &cpl)
 {
+    Plan &pl = const_cast<Plan &>(cpl);
     const Geo &g = pl.g;
     const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
     const size_t nk = (size_t)g.nkx * g.nky * g.nkz;
+    const size_t sl = g.even ? g.slice_e * es : g.slice_elems * cs;  // bytes per slice
+    const bool pair_ws = pl.pairs && g.nL > 0, rpa = pl.p.want_rpa != 0;
+    const size_t Mx = g.bs ? ((size_t)1 << g.logMx) * cs : 0, My = g.bs ? ((size_t)1 << g.logMy) * cs : 0;
+    const size_t nw = (size_t)pl.p.nomega;
+    return {
+        {(void **)&pl.xi, nk * 8 * pl.nb},
+        {&pl.rho, pl.has_rho ? nk * es * pl.nb : 0},
+        {&pl.bspec, pair_ws ? (size_t)pl.nb * g.nS * sl : 0},
+        {&pl.sacc, pair_ws ? (size_t)g.nL * sl : 0},
+        {&pl.twx, g.nkx * cs},
+        {&pl.twy, g.nky * cs},
+        {&pl.twz, g.nkz * cs},
+        {&pl.bsx[0], g.bs ? g.nkx * cs : 0},
+        {&pl.bsy[0], g.bs ? g.nky * cs : 0},
+        {&pl.bsx[1], Mx}, {&pl.bsx[2], Mx}, {&pl.bsx[3], Mx},
+        {&pl.bsy[1], My}, {&pl.bsy[2], My}, {&pl.bsy[3], My},
+        {&pl.twe, ((size_t)1 << g.logNE) * cs},
+        {(void **)&pl.ffx, (size_t)pl.out_nx * 16},
+        {(void **)&pl.ffy, (size_t)pl.out_ny * 16},
+        {(void **)&pl.d_src, nw * sizeof(PlaneSrc)},
+        {(void **)&pl.d_frac, nw * sizeof(double)},
+        {(void **)&pl.d_lag, nw * sizeof(int)},
+        {&pl.spec, (size_t)g.nslots * sl},
+        {(void **)&pl.scratch, scratch_bytes(pl)},
+        {&pl.im1, rpa ? (size_t)g.neps * nk * es : 0},
+        {&pl.re1, rpa ? nw * nk * es : 0},
+        {(void **)&pl.kkw, rpa ? (nw + 7) / 8 * 8 * g.neps * 8 : 0},
+    };
+}
+
+size_t plan_footprint(const Plan &pl)
+{
     size_t b = 0;
-    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    b += al(nk * 8 * pl.nb);
-    if (pl.has_rho) b += al(nk * es * pl.nb);
-    if (pl.pairs && g.nL > 0)
-        b += al((size_t)(pl.nb * g.nS + g.nL) * (g.even ? g.slice_e * (cs / 2) : g.slice_elems * cs));
-    b += al(g.nkx * cs) + al(g.nky * cs) + al(g.nkz * cs) + al(((size_t)1 << g.logNE) * cs);
-    if (g.bs)
-        b += al(g.nkx * cs) + al(g.nky * cs) + 3 * (al(((size_t)1 << g.logMx) * cs) + al(((size_t)1 << g.logMy) * cs));
-    b += al((size_t)pl.out_nx * 16) + al((size_t)pl.out_ny * 16);
-    b += al(pl.p.nomega * sizeof(PlaneSrc)) + al(pl.p.nomega * sizeof(int)) + al(pl.p.nomega * sizeof(double));
-    b += al(g.even ? (size_t)g.nslots * g.slice_e * (cs / 2) : (size_t)g.nslots * g.slice_elems * cs);
-    b += al(scratch_bytes(pl));
-    if (pl.p.want_rpa) {
-        b += al((size_t)g.neps * nk * es);
-        b += al((size_t)pl.p.nomega * nk * es);
-        b += al((size_t)(pl.p.nomega + 7) / 8 * 8 * g.neps * 8);
-    }
+    for (const BufSpec &r : plan_buffers(pl)) b += (r.bytes + 255) & ~(size_t)255;
     return b;
 }
 
@@ -596,8 +618,25 @@ static lindhard_status dalloc(Plan &pl, void **p, size_t bytes)
 // the general-path form.
 namespace {
 std::mutex g_tune_mu;
+std::condition_variable g_tune_cv;
 std::map<std::string, std::pair<int, int>> g_tune;  // key -> (variant, TR)
+std::set<std::string> g_tune_busy;                  // keys being timed right now
 bool g_tune_loaded = false;
+
+// Marks a key as being timed; clears the mark (and wakes the plans waiting
+// for it) on every way out of the timing.
+struct TuneBusy {
+    std::string key;
+    explicit TuneBusy(const std::string &k) : key(k) { g_tune_busy.insert(k); }
+    ~TuneBusy()
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_busy.erase(key);
+        }
+        g_tune_cv.notify_all();
+    }
+};
 
 bool even_tr_fits(const Geo &g, int TR);
 
@@ -706,12 +745,13 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
     const bool forced = !g.even && std::getenv("LINDHARD_WINDOW") != nullptr;
     if (forced) return LINDHARD_OK;
     const std::string key = tune_key(g);
-    // One decision per shape for the whole process: the lock is held while a
-    // shape is timed, so concurrent plans of that shape (served jobs) wait and
-    // then take the same schedule, which keeps their results bit-identical.
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    // One decision per shape for the whole process.  A shape is timed by one
+    // plan at a time: concurrent plans of that shape (served jobs) wait for
+    // its decision and take it, which keeps their results bit-identical,
+    // while plans of other shapes go on (the lock is not held while timing).
+    std::unique_lock<std::mutex> lk(g_tune_mu);
     tune_load_file();
-    {
+    for (;;) {
         auto it = g_tune.find(key);
         if (it != g_tune.end() && (!g.even || even_fits(g, it->second.first, it->second.second))) {
             if (g.even)
@@ -721,7 +761,11 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
             g.tuned = 2;
             return LINDHARD_OK;
         }
+        if (!g_tune_busy.count(key)) break;
+        g_tune_cv.wait(lk);
     }
+    TuneBusy busy(key);
+    lk.unlock();
     std::vector<std::pair<int, int>> cands;
     if (g.even) {
         const char *ev = std::getenv("LINDHARD_EVEN_WINDOW");
@@ -782,6 +826,7 @@ static lindhard_status autotune_window(Plan &pl, hipStream_t st)
         else
             g.p3_variant = pick.first;
         g.tuned = 1;
+        std::lock_guard<std::mutex> lk2(g_tune_mu);
         g_tune[key] = pick;
         tune_store_file(key, pick.first, pick.second);
     }
@@ -822,46 +867,12 @@ static lindhard_status solve_mu(Plan &pl, hipStream_t st, double band_lo, double
 
 lindhard_status plan_build(Plan &pl, hipStream_t st)
 {
-    const Geo &g = pl.g;
-    const size_t cs = g.fp64 ? 16 : 8, es = g.fp64 ? 8 : 4;
-    const size_t nk = (size_t)g.nkx * g.nky * g.nkz;
-    lindhard_status s;
-#define LH_ALLOC(ptr, bytes)                                 \
-    do {                                                     \
-        s = dalloc(pl, (void **)&(ptr), (bytes));            \
-        if (s != LINDHARD_OK) return s;                      \
-    } while (0)
-    LH_ALLOC(pl.xi, nk * 8 * pl.nb);
-    if (pl.has_rho) LH_ALLOC(pl.rho, nk * es * pl.nb);
-    if (pl.pairs && g.nL > 0) {
-        LH_ALLOC(pl.bspec, (size_t)pl.nb * g.nS * (g.even ? g.slice_e * es : g.slice_elems * cs));
-        LH_ALLOC(pl.sacc, (size_t)g.nL * (g.even ? g.slice_e * es : g.slice_elems * cs));
+    (void)st;
+    for (const BufSpec &r : plan_buffers(pl)) {
+        if (!r.bytes) continue;
+        const lindhard_status s = dalloc(pl, r.ptr, r.bytes);
+        if (s != LINDHARD_OK) return s;
     }
-    LH_ALLOC(pl.twx, g.nkx * cs);
-    LH_ALLOC(pl.twy, g.nky * cs);
-    LH_ALLOC(pl.twz, g.nkz * cs);
-    if (g.bs) {
-        LH_ALLOC(pl.bsx[0], g.nkx * cs);
-        LH_ALLOC(pl.bsy[0], g.nky * cs);
-        for (int i = 1; i < 4; ++i) {
-            LH_ALLOC(pl.bsx[i], ((size_t)1 << g.logMx) * cs);
-            LH_ALLOC(pl.bsy[i], ((size_t)1 << g.logMy) * cs);
-        }
-    }
-    LH_ALLOC(pl.twe, ((size_t)1 << g.logNE) * cs);
-    LH_ALLOC(pl.ffx, (size_t)pl.out_nx * 16);
-    LH_ALLOC(pl.ffy, (size_t)pl.out_ny * 16);
-    LH_ALLOC(pl.d_src, pl.p.nomega * sizeof(PlaneSrc));
-    LH_ALLOC(pl.d_frac, pl.p.nomega * sizeof(double));
-    LH_ALLOC(pl.d_lag, pl.p.nomega * sizeof(int));
-    LH_ALLOC(pl.spec, g.even ? (size_t)g.nslots * g.slice_e * es : (size_t)g.nslots * g.slice_elems * cs);
-    LH_ALLOC(pl.scratch, scratch_bytes(pl));
-    if (pl.p.want_rpa) {
-        LH_ALLOC(pl.im1, (size_t)g.neps * nk * es);
-        LH_ALLOC(pl.re1, (size_t)pl.p.nomega * nk * es);
-        LH_ALLOC(pl.kkw, (size_t)(pl.p.nomega + 7) / 8 * 8 * g.neps * 8);
-    }
-#undef LH_ALLOC
     return LINDHARD_OK;
 }
 
@@ -875,6 +886,8 @@ struct lindhard_plan_s {
     hipEvent_t done = nullptr;  // recorded after each exec / rpa
     int32_t *d_cut = nullptr;   // staged (X, Y) pairs of lindhard_cut (owned by pl.allocs)
     size_t cut_cap = 0;
+    std::string key;            // class key (plan caching in the server)
+    std::vector<size_t> cap;    // allocated bytes of each buffer of plan_buffers
 };
 
 // One setup stream per host thread and device, kept for the life of the
@@ -966,18 +979,18 @@ static hipError_t bs_tables(const Plan &pl, int n, int logM, void *const *dst, h
     return hipSuccess;
 }
 
-static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_plan_s *o)
+// Band-dependent state of a plan: the band (caller table or tight-binding),
+// momentum-density and band-pair weights, the chemical potential and
+// xi = eps - mu, on stream st (synchronous: the host tables may go after).
+static lindhard_status plan_bind_band(Plan &pl, const lindhard_problem *p, hipStream_t st)
 {
-    Plan &pl = o->pl;
-    lindhard_status s = plan_describe(p, pl);
-    if (s != LINDHARD_OK) return s;
-    if (hipGetDevice(&pl.device) != hipSuccess) return LINDHARD_EDEVICE;
-    o->setup = thread_setup_stream(pl.device);
-    if (!o->setup) return LINDHARD_EDEVICE;
-    if (hipEventCreateWithFlags(&o->done, hipEventDisableTiming) != hipSuccess) return LINDHARD_EDEVICE;
-    hipStream_t st = o->setup;
-    s = plan_build(pl, st);
-    if (s != LINDHARD_OK) return s;
+    pl.p.t = p->t;
+    pl.p.tp = p->tp;
+    pl.p.tpp = p->tpp;
+    pl.p.mu = p->mu;
+    pl.p.filling = p->filling;
+    pl.p.gamma = p->gamma;
+    if (pl.pairs) pl.pairw.assign(p->pair_weight, p->pair_weight + pl.nb * pl.nb);
     const size_t nk = (size_t)pl.g.nkx * pl.g.nky * pl.g.nkz;
     double band_lo = 0.0, band_hi = 0.0;
     const size_t nall = nk * pl.nb;
@@ -1003,22 +1016,51 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
         }
     }
     if (std::isnan(p->mu)) {
-        s = solve_mu(pl, st, band_lo, band_hi);
+        const lindhard_status s = solve_mu(pl, st, band_lo, band_hi);
         if (s != LINDHARD_OK) return s;
     } else {
         pl.mu = p->mu;
         pl.mu_iters = 0;
     }
     LH_TRY(launch_xi_shift(pl, pl.mu, st));
+    LH_TRY(hipStreamSynchronize(st));
+    return LINDHARD_OK;
+}
+
+// Omega-dependent state: lag, fraction and window slot of every omega, and
+// the Kramers-Kronig weights of an RPA plan (asynchronous on st; the host
+// vectors live in the plan).
+static lindhard_status plan_bind_omega(Plan &pl, hipStream_t st)
+{
     LH_TRY(hipMemcpyAsync(pl.d_src, pl.src.data(), pl.src.size() * sizeof(PlaneSrc), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_frac, pl.frac.data(), pl.frac.size() * sizeof(double), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_lag, pl.lag.data(), pl.lag.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    return LINDHARD_OK;
+}
+
+static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_plan_s *o)
+{
+    Plan &pl = o->pl;
+    lindhard_status s = plan_describe(p, pl);
+    if (s != LINDHARD_OK) return s;
+    if (hipGetDevice(&pl.device) != hipSuccess) return LINDHARD_EDEVICE;
+    o->setup = thread_setup_stream(pl.device);
+    if (!o->setup) return LINDHARD_EDEVICE;
+    if (hipEventCreateWithFlags(&o->done, hipEventDisableTiming) != hipSuccess) return LINDHARD_EDEVICE;
+    hipStream_t st = o->setup;
+    s = plan_build(pl, st);
+    if (s != LINDHARD_OK) return s;
+    s = plan_bind_band(pl, p, st);
+    if (s != LINDHARD_OK) return s;
+    s = plan_bind_omega(pl, st);
+    if (s != LINDHARD_OK) return s;
     LH_TRY(launch_tables(pl, st));
     std::vector<std::vector<double>> keep;
     if (pl.g.bs) {
         LH_TRY(bs_tables(pl, pl.g.nkx, pl.g.logMx, pl.bsx, st, keep));
         LH_TRY(bs_tables(pl, pl.g.nky, pl.g.logMy, pl.bsy, st, keep));
     }
+    const size_t nk = (size_t)pl.g.nkx * pl.g.nky * pl.g.nkz;
     if (pl.p.want_rpa)
         LH_TRY(hipMemsetAsync(pl.im1, 0, (size_t)pl.g.neps * nk * pl.elem_bytes, st));
     if (pl.g.even) {
@@ -1033,8 +1075,102 @@ static lindhard_status build_plan_object(const lindhard_problem *p, lindhard_pla
     s = autotune_window(pl, st);
     if (s != LINDHARD_OK) return s;
     describe_schedule(pl);
+    o->key = plan_class_key(pl);
+    for (const BufSpec &r : plan_buffers(pl)) o->cap.push_back(r.bytes);
     return LINDHARD_OK;
 }
+
+namespace lh {
+
+// Everything that fixes a plan's tables and the layout of its buffers, and
+// nothing that a cached plan may change when it is rebound to another
+// problem: the band, broadening, filling or chemical potential, and the omega
+// list (its lag range sizes some buffers, which grow as needed).
+std::string plan_class_key(const Plan &pl)
+{
+    const lindhard_problem &p = pl.p;
+    const Geo &g = pl.g;
+    char b[320];
+    std::snprintf(b, sizeof b, "p%d k%dx%dx%d e%d[%a,%a] z%dx%d ff%d:%a rpa%d kz%d nb%d pr%d rho%d ev%d bs%d",
+                  p.precision, g.nkx, g.nky, g.nkz, g.neps, p.emin, p.emax, p.zones_x, p.zones_y, p.ff_kind,
+                  p.ff_kind ? p.ff_width : 0.0, p.want_rpa ? 1 : 0, p.k_zones, pl.nb, pl.pairs ? 1 : 0,
+                  pl.has_rho ? 1 : 0, g.even, g.bs);
+    return b;
+}
+
+const std::string &plan_key(lindhard_plan_t plan) { return plan->key; }
+
+std::vector<size_t> plan_capacity(lindhard_plan_t plan) { return plan->cap; }
+
+size_t plan_resident_bytes(lindhard_plan_t plan)
+{
+    size_t b = 0;
+    for (const size_t c : plan->cap) b += (c + 255) & ~(size_t)255;
+    return b;
+}
+
+// Rebind a built plan to another problem of its class: the geometry of the
+// new omega list, the band, mu and the tables are redone in place, buffers
+// that are too small for the new geometry are replaced, and the window
+// schedule is taken from the tuning cache.  The result equals that of a plan
+// built for the problem afresh, bit for bit (the same geometry, schedule and
+// kernels; every buffer is written before it is read).  Synchronous on st;
+// the plan's earlier work must have completed.  EINVAL if the class differs.
+lindhard_status plan_rebind(lindhard_plan_t plan, const lindhard_problem *p, hipStream_t st)
+{
+    if (!plan || !p) return LINDHARD_EINVAL;
+    Plan d;
+    lindhard_status s = plan_describe(p, d);
+    if (s != LINDHARD_OK) return s;
+    if (plan_class_key(d) != plan->key) return LINDHARD_EINVAL;
+    Plan &pl = plan->pl;
+    // the new description takes over the device buffers
+    const std::vector<BufSpec> oldb = plan_buffers(pl);
+    d.device = pl.device;
+    d.allocs = std::move(pl.allocs);
+    std::vector<BufSpec> nb = plan_buffers(d);
+    for (size_t i = 0; i < nb.size(); ++i) *nb[i].ptr = *oldb[i].ptr;
+    pl = std::move(d);
+    nb = plan_buffers(pl);
+    std::vector<bool> grown(nb.size(), false);
+    for (size_t i = 0; i < nb.size(); ++i) {
+        if (nb[i].bytes <= plan->cap[i]) continue;
+        void *old = *nb[i].ptr;
+        if (old) {
+            for (auto it = pl.allocs.begin(); it != pl.allocs.end(); ++it)
+                if (it->first == old) {
+                    pool_free(it->first, it->second, pl.device);
+                    pl.allocs.erase(it);
+                    break;
+                }
+            *nb[i].ptr = nullptr;
+        }
+        plan->cap[i] = 0;
+        s = dalloc(pl, nb[i].ptr, nb[i].bytes);
+        if (s != LINDHARD_OK) return s;
+        plan->cap[i] = nb[i].bytes;
+        grown[i] = true;
+    }
+    s = plan_bind_omega(pl, st);
+    if (s != LINDHARD_OK) return s;
+    LH_TRY(launch_tables(pl, st));
+    if (pl.g.even) {
+        // replaced spectral buffers: padding rows zero, as at planning
+        const size_t sl = pl.g.slice_e * pl.elem_bytes;
+        for (size_t i = 0; i < nb.size(); ++i)
+            if (grown[i] && (nb[i].ptr == &pl.spec || nb[i].ptr == &pl.bspec || nb[i].ptr == &pl.sacc))
+                LH_TRY(hipMemsetAsync(*nb[i].ptr, 0, nb[i].bytes / sl * sl, st));
+    }
+    s = plan_bind_band(pl, p, st);
+    if (s != LINDHARD_OK) return s;
+    s = autotune_window(pl, st);
+    if (s != LINDHARD_OK) return s;
+    describe_schedule(pl);
+    pl.executed = false;
+    return LINDHARD_OK;
+}
+
+}  // namespace lh
 
 extern "C" {
 

@@ -150,6 +150,20 @@ struct Plan {
 
 // Validate and derive everything host-side (no device work).  Fills `pl`.
 lindhard_status plan_describe(const lindhard_problem *p, Plan &pl);
+// One device buffer of a plan: where its pointer lives and its size (0: unused).
+struct BufSpec {
+    void **ptr;
+    size_t bytes;
+};
+std::vector<BufSpec> plan_buffers(const Plan &pl);
+// Plan caching (the server): the class key of a described problem, the key,
+// allocated buffer sizes and resident bytes of a built plan, and rebinding a
+// built plan to another problem of its class (synchronous on st).
+std::string plan_class_key(const Plan &pl);
+const std::string &plan_key(lindhard_plan_t plan);
+std::vector<size_t> plan_capacity(lindhard_plan_t plan);
+size_t plan_resident_bytes(lindhard_plan_t plan);
+lindhard_status plan_rebind(lindhard_plan_t plan, const lindhard_problem *p, hipStream_t st);
 // Allocate device memory, build band / mu / tables.  Synchronous on `st`.
 lindhard_status plan_build(Plan &pl, hipStream_t st);
 void plan_free(Plan &pl);

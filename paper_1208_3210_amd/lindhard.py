@@ -76,7 +76,7 @@ class Info(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32)]
+                ("max_queue", ctypes.c_int32), ("warm", ctypes.POINTER(Problem)), ("n_warm", ctypes.c_int32)]
 
 
 class ServeStats(ctypes.Structure):
@@ -85,6 +85,8 @@ class ServeStats(ctypes.Structure):
         ("rejected", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("points_per_s", ctypes.c_double),
         ("hbm_high_water", ctypes.c_size_t), ("queue_depth", ctypes.c_int32), ("inflight", ctypes.c_int32),
+        ("plan_reuses", ctypes.c_uint64), ("plan_builds", ctypes.c_uint64), ("plan_evictions", ctypes.c_uint64),
+        ("cached_plans", ctypes.c_int32), ("resident_bytes", ctypes.c_size_t),
     ]
 
 
@@ -446,10 +448,16 @@ def nan() -> float:
 class Server:
     """Continuous-batching server (lindhard_serve_*); outputs are torch tensors."""
 
-    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_queue: int = 1024):
-        cfg = ServeConfig(int(hbm_budget_bytes), int(max_inflight), int(max_queue))
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_queue: int = 1024, warm=()):
+        """warm: problems (keyword dicts as for make_problem, want_rpa set for
+        RPA jobs) planned before the first job is taken."""
+        made = [make_problem(**w) for w in warm]
+        arr = (Problem * max(1, len(made)))(*[m[0] for m in made])
+        cfg = ServeConfig(int(hbm_budget_bytes), int(max_inflight), int(max_queue),
+                          ctypes.cast(arr, ctypes.POINTER(Problem)) if made else None, len(made))
         h = _vp()
         _check(lib().lindhard_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "lindhard_serve_create")
+        del made, arr
         self.handle = h.value
         self._keep = {}
 

@@ -171,3 +171,83 @@ def test_served_extended_forms_equal_alone():
         assert torch.equal(outs["im_chi"], alone), t
         plan.close()
     srv.close()
+
+
+def _tb(seed):
+    band = W.seeded_band(np.random.Generator(np.random.PCG64(seed)))
+    return dict(**band, filling=1.05 + 0.01 * (seed % 7), gamma=0.03 + 0.005 * (seed % 5))
+
+
+def test_cached_plans_rebound_across_lag_ranges_equal_alone():
+    """Jobs of one class (grid, energy window, precision) with different bands
+    and omega lists run on one cached plan, rebound in place: a small lag
+    range first, then larger ones (the spectral buffers grow), then a small
+    one again on the grown buffers, then an RPA job (its own class).  Each
+    result equals the problem planned afresh, bit for bit, and the server
+    reports the reuse."""
+    neps, e0, e1 = 128, -2.0, 2.0
+    lag_sets = [range(1, 9), range(1, 41), range(3, 64, 5), range(1, 17), range(20, 60)]
+    jobs = []
+    for i, lags in enumerate(lag_sets):
+        for prec in (LH.LINDHARD_FP32C, LH.LINDHARD_FP64):
+            jobs.append((float("nan"), dict(**_tb(i), nkx=64, nky=64, neps=neps, emin=e0, emax=e1,
+                                            omega=W.lag_omegas(neps, e0, e1, lags), precision=prec)))
+    jobs.append((0.7, dict(**_tb(9), nkx=64, nky=64, neps=neps, emin=e0, emax=e1,
+                           omega=W.lag_omegas(neps, e0, e1, range(1, 33)), precision=LH.LINDHARD_FP32C)))
+    jobs.append((1.3, dict(**_tb(10), nkx=64, nky=64, neps=neps, emin=e0, emax=e1,
+                           omega=W.lag_omegas(neps, e0, e1, range(2, 50, 3)), precision=LH.LINDHARD_FP32C)))
+    # one worker: the jobs run in order, each on the plan its predecessor of
+    # the class left behind
+    srv = LH.Server(hbm_budget_bytes=4 << 30, max_inflight=1, max_queue=64)
+    tickets = [srv.submit(U, **prob) for U, prob in jobs]
+    for t, _ in tickets:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st = srv.stats()
+    assert st.plan_builds == 3 and st.plan_reuses == len(jobs) - 3, (st.plan_builds, st.plan_reuses)
+    assert st.cached_plans == 3 and st.resident_bytes <= st.hbm_high_water <= 4 << 30
+    for (U, prob), (t, outs) in zip(jobs, tickets):
+        alone = run_alone(U, prob)
+        for k, v in alone.items():
+            assert torch.equal(outs[k], v), (t, k)
+    srv.close()
+
+
+def test_warm_problems_and_eviction():
+    """Problems given at creation are planned before the first job, so a job
+    of their class reuses a plan at once; under a budget that holds about one
+    plan, idle plans of other classes are evicted least recently used first
+    and every result still equals the problem run alone."""
+    e0, e1 = -2.0, 2.0
+    mk = lambda nk, neps, seed, lags: dict(**_tb(seed), nkx=nk, nky=nk, neps=neps, emin=e0, emax=e1,  # noqa: E731
+                                           omega=W.lag_omegas(neps, e0, e1, lags), precision=LH.LINDHARD_FP32C)
+    warm = [mk(128, 64, 0, range(1, 33)), mk(64, 128, 1, range(1, 33))]
+    srv = LH.Server(hbm_budget_bytes=8 << 30, max_inflight=2, max_queue=16, warm=warm)
+    st = srv.stats()
+    assert st.plan_builds == 2 and st.cached_plans == 2 and st.completed == 0
+    t, outs = srv.submit(float("nan"), **mk(128, 64, 5, range(1, 20)))
+    assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st = srv.stats()
+    assert st.plan_reuses == 1 and st.plan_builds == 2
+    assert torch.equal(outs["im_chi"], run_alone(float("nan"), mk(128, 64, 5, range(1, 20)))["im_chi"])
+    # a wait that reported the job finished released its ticket
+    with pytest.raises(LH.LindhardError):
+        srv.wait(t, 1.0)
+    srv.close()
+
+    # two classes of about one budget each: every job evicts the other's plan
+    probs = [mk(256, 128, 2, range(1, 33)), mk(256, 64, 3, range(1, 33)), mk(256, 128, 4, range(1, 40))]
+    fps = []
+    for pr in probs:
+        p = LH.Plan(**pr)
+        fps.append(p.info.workspace_bytes)
+        p.close()
+    budget = int(max(fps) * 1.3)
+    srv = LH.Server(hbm_budget_bytes=budget, max_inflight=1, max_queue=16)
+    tickets = [srv.submit(float("nan"), **pr) for pr in probs]
+    for t, _ in tickets:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st = srv.stats()
+    assert st.plan_evictions == 2 and st.plan_builds == 3 and st.hbm_high_water <= budget
+    for pr, (t, outs) in zip(probs, tickets):
+        assert torch.equal(outs["im_chi"], run_alone(float("nan"), pr)["im_chi"]), t
+    srv.close()
