@@ -430,6 +430,40 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         }
     }
 
+    if (p->want_rpa) {
+        // Kramers-Kronig rows: every lag an omega reads (and the next one
+        // for an omega between lags), by parity in tiles of 16
+        std::vector<int> need;
+        for (int w = 0; w < p->nomega; ++w) {
+            need.push_back(pl.lag[w]);
+            if (pl.frac[w] > 0.0) need.push_back(pl.lag[w] + 1);
+        }
+        std::sort(need.begin(), need.end());
+        need.erase(std::unique(need.begin(), need.end()), need.end());
+        pl.kk_lags = need;
+        pl.kk_rows.clear();
+        for (int par = 0; par < 2; ++par) {
+            int n = 0;
+            for (size_t s = 0; s < need.size(); ++s)
+                if ((need[s] & 1) == par) {
+                    pl.kk_rows.push_back(make_int2(need[s], (int)s));
+                    ++n;
+                }
+            while (n % 16) {
+                pl.kk_rows.push_back(make_int2(-1, -1));
+                ++n;
+            }
+        }
+        pl.kk_ntiles = (int)pl.kk_rows.size() / 16;
+        pl.kk_nch = (p->neps + 31) / 32;
+        pl.kk_slot.assign((size_t)2 * p->nomega, -1);
+        auto slot = [&](int m) { return (int)(std::lower_bound(need.begin(), need.end(), m) - need.begin()); };
+        for (int w = 0; w < p->nomega; ++w) {
+            pl.kk_slot[2 * w] = slot(pl.lag[w]);
+            if (pl.frac[w] > 0.0) pl.kk_slot[2 * w + 1] = slot(pl.lag[w] + 1);
+        }
+    }
+
     pl.zx = p->zones_x;
     pl.zy = p->zones_y;
     pl.out_nx = p->zones_x * p->nkx;
@@ -483,8 +517,10 @@ std::vector<BufSpec> plan_buffers(const Plan &cpl)
         {&pl.spec, (size_t)g.nslots * sl},
         {(void **)&pl.scratch, scratch_bytes(pl)},
         {&pl.im1, rpa ? (size_t)g.neps * nk * es : 0},
-        {&pl.re1, rpa ? nw * nk * es : 0},
-        {(void **)&pl.kkw, rpa ? (nw + 7) / 8 * 8 * g.neps * 8 : 0},
+        {&pl.re1, rpa ? pl.kk_lags.size() * nk * es : 0},
+        {(void **)&pl.kkw, rpa ? (size_t)pl.kk_ntiles * 16 * pl.kk_nch * 16 * 8 : 0},
+        {(void **)&pl.d_kkrow, rpa ? pl.kk_rows.size() * sizeof(int2) : 0},
+        {(void **)&pl.d_kkslot, rpa ? pl.kk_slot.size() * sizeof(int) : 0},
     };
 }
 
@@ -587,7 +623,8 @@ void plan_free(Plan &pl)
                      (void **)&pl.ffy,    (void **)&pl.d_src, (void **)&pl.d_lag, (void **)&pl.d_frac, &pl.spec,
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
                      &pl.rho,              &pl.bspec,         &pl.sacc,         &pl.bsx[0], &pl.bsx[1], &pl.bsx[2], &pl.bsx[3],
-                     &pl.bsy[0],           &pl.bsy[1],        &pl.bsy[2], &pl.bsy[3]};
+                     &pl.bsy[0],           &pl.bsy[1],        &pl.bsy[2], &pl.bsy[3], (void **)&pl.d_kkrow,
+                     (void **)&pl.d_kkslot};
     for (void **p : ptrs) *p = nullptr;
 }
 
@@ -1035,6 +1072,12 @@ static lindhard_status plan_bind_omega(Plan &pl, hipStream_t st)
     LH_TRY(hipMemcpyAsync(pl.d_src, pl.src.data(), pl.src.size() * sizeof(PlaneSrc), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_frac, pl.frac.data(), pl.frac.size() * sizeof(double), hipMemcpyHostToDevice, st));
     LH_TRY(hipMemcpyAsync(pl.d_lag, pl.lag.data(), pl.lag.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (pl.p.want_rpa) {
+        LH_TRY(hipMemcpyAsync(pl.d_kkrow, pl.kk_rows.data(), pl.kk_rows.size() * sizeof(int2), hipMemcpyHostToDevice,
+                              st));
+        LH_TRY(hipMemcpyAsync(pl.d_kkslot, pl.kk_slot.data(), pl.kk_slot.size() * sizeof(int), hipMemcpyHostToDevice,
+                              st));
+    }
     return LINDHARD_OK;
 }
 

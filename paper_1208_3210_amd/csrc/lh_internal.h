@@ -139,8 +139,17 @@ struct Plan {
     int *d_lag = nullptr;      // per omega: lag
     void *spec = nullptr;      // spectral / real-space array, nslots slices
     void *im1 = nullptr;       // RPA: Im chi_1BZ [neps][nky][nkx]
-    void *re1 = nullptr;       // RPA: Re chi_1BZ [nomega][nky][nkx]
-    double *kkw = nullptr;     // RPA: Kramers-Kronig weights [nomega][neps]
+    void *re1 = nullptr;       // RPA: Re chi_1BZ [kk_lags.size()][nky][nkx], one plane per needed lag
+    double *kkw = nullptr;     // RPA: Kramers-Kronig weights [kk_ntiles][16 kk_nch][16]
+    // RPA: the lags whose Re chi is needed (sorted; the slots of re1), in
+    // tiles of 16 lags of one parity ((lag, slot) per row, (-1, -1) padding),
+    // and per omega the slots of its lag and of the next one (-1: none)
+    std::vector<int> kk_lags;
+    std::vector<int2> kk_rows;
+    std::vector<int> kk_slot;
+    int kk_ntiles = 0, kk_nch = 0;  // tiles, chunks of 32 energies
+    int2 *d_kkrow = nullptr;
+    int *d_kkslot = nullptr;
     double *scratch = nullptr; // mu-solve partial sums
     size_t ws_bytes = 0;
     std::vector<std::pair<void *, size_t>> allocs;  // pooled device buffers

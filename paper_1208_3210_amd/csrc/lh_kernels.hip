@@ -127,30 +127,29 @@ __global__ void __launch_bounds__(kThreads) k_fftab(double2 *__restrict__ tab, i
 }
 
 // Kramers-Kronig weights of the alternate-point rule (Sec. 4):
-// w[i][j] = (2/pi) 2j / (j^2 - i^2) for j - i odd, 1 <= j < neps, else 0,
-// stored j-major, w[j * nwp + i] with nwp = nw rounded up to kKkW (zero
-// padding) so that the weights of consecutive output lags are contiguous.
-constexpr int kKkW = 8;
-// An omega between lags m and m + 1 (frac f > 0) takes (1 - f) w[m] + f w[m + 1].
+// w(i, j) = (2/pi) 2j / (j^2 - i^2) for j - i odd, 1 <= j < neps, else 0.
 __device__ __forceinline__ double kk_weight(long i, int j)
 {
     if (j < 1 || !(((long)j - i) & 1)) return 0.0;
     const double di = (double)i, dj = (double)j;
     return (2.0 / kPi) * 2.0 * dj / (dj * dj - di * di);
 }
-__global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const int *__restrict__ lags,
-                                                 const double *__restrict__ fracs, int nw, int nwp, int neps)
+// Energy of position jp (0 <= jp < 16 nch) in the sequence a tile of lags of
+// parity par sums over: in each chunk of 32 energies the 16 of the other parity.
+__device__ __forceinline__ int kk_energy(int jp, int par) { return 32 * (jp >> 4) + (1 - par) + 2 * (jp & 15); }
+// Weights per tile t of 16 lags (rows (lag, slot), lag < 0: padding), per
+// energy position jp and per row r: w[(t * 16 nch + jp) * 16 + r].
+__global__ void __launch_bounds__(kThreads) k_kkw(double *__restrict__ w, const int2 *__restrict__ rows, int ntiles,
+                                                 int nch, int neps)
 {
+    const long n = (long)ntiles * 16 * nch * 16;
     const long idx = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= (long)nwp * neps) return;
-    const int j = (int)(idx / nwp), wi = (int)(idx % nwp);
-    double v = 0.0;
-    if (wi < nw) {
-        const double f = fracs[wi];
-        v = kk_weight(lags[wi], j);
-        if (f > 0.0) v = (1.0 - f) * v + f * kk_weight((long)lags[wi] + 1, j);
-    }
-    w[idx] = v;
+    if (idx >= n) return;
+    const int r = (int)(idx & 15), t = (int)(idx / (16L * nch * 16));
+    const int jp = (int)((idx >> 4) % (16L * nch));
+    const int lag = rows[t * 16 + r].x, par = rows[t * 16].x & 1;
+    const int j = kk_energy(jp, par);
+    w[idx] = (lag >= 0 && j < neps) ? kk_weight(lag, j) : 0.0;
 }
 
 // 16 bytes of consecutive elements (one vector load or store per lane).
@@ -1541,66 +1540,98 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
     }
 }
 
-// Kramers-Kronig: re1[w][q] = sum_j kkw[j][w] im1[j][q], FP64 accumulation.
-// One block: QT consecutive q with every lag staged in LDS; each thread sums
-// kKkW output lags at once (independent accumulators sharing each staged
-// value; the zero weights of the other parity are multiplied too), the
-// weights of one j read as one contiguous, wave-uniform block.
-template <typename T, bool WAVEQ>
-__global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int nk, int neps, int nw,
-                                                const double *__restrict__ kkw, T *__restrict__ re1, int logQT)
+// Kramers-Kronig on the matrix cores: re1[slot][q] = sum_j w(lag, j) im1[j][q]
+// for every needed lag, with FP64 products and sums (v_mfma_f64_16x16x4f64).
+// The weights vanish unless j - lag is odd, so the lags come in tiles of 16
+// of one parity and a tile sums over the 16 energies of the other parity in
+// each chunk of 32.  Block: four waves (one lag tile each) and 128 q; the
+// chunk of Im (32 energies x 128 q) is staged through LDS and shared by the
+// tiles, the next chunk's loads in flight while the current one is summed.
+// Per step of 4 energies a wave loads its 16 x 4 weights (one double per
+// lane, contiguous) and issues eight MFMAs, one per 16 q.
+//   MFMA operands: lane l holds A[l % 16][l / 16] (lag row, energy) and
+//   B[l / 16][l % 16] (energy, q); result register r of lane l is the sum for
+//   lag row 4 r + l / 16 and q column l % 16.
+typedef double lh_d4 __attribute__((ext_vector_type(4)));
+constexpr int kKkQ = 128;            // q per block
+constexpr int kKkStride = kKkQ + 8;  // LDS row stride (energies two apart land 16 banks apart)
+template <typename T>
+__global__ void __launch_bounds__(256) k_kkm(const T *__restrict__ im1, int nk, int neps,
+                                            const double *__restrict__ w, const int2 *__restrict__ rows,
+                                            int ntiles, int nch, T *__restrict__ re1)
 {
-    // WAVEQ: QT = 64, one wave per group of output lags (wave-uniform weights)
-    if constexpr (WAVEQ) logQT = 6;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);
-    const int QT = 1 << logQT;
-    const int tid = threadIdx.x;
-    const int q0 = blockIdx.x * QT;
-    for (int it0 = tid; it0 < neps * QT; it0 += 8 * kThreads) {
-        T v[8];
+    __shared__ __align__(16) T tile[32 * kKkStride];
+    constexpr int VEC = 16 / sizeof(T);             // values per 16-byte load
+    constexpr int NV = 32 * kKkQ / VEC / 256;       // loads per thread per chunk
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int t = blockIdx.y * 4 + (tid >> 6);     // this wave's lag tile
+    const bool active = t < ntiles;
+    const long q0 = (long)blockIdx.x * kKkQ;
+    const int par = active ? (rows[t * 16].x & 1) : 0;
+    const int J = 16 * nch;
+    // staging: load v of a chunk covers energy row e = idx / (kKkQ / VEC), q group
+    auto load = [&](int c, Vec16<T> *v) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int it = it0 + k * kThreads;
-            const int j = it >> logQT, c = it & (QT - 1);
-            v[k] = im1[it < neps * QT ? (size_t)j * nk + q0 + c : 0];
+        for (int k = 0; k < NV; ++k) {
+            const int idx = tid + k * 256, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
+            const int j = 32 * c + e;
+            if (j < neps && q0 + qv < nk)
+                v[k] = *reinterpret_cast<const Vec16<T> *>(im1 + (size_t)j * nk + q0 + qv);
+            else
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) v[k].v[u] = (T)0;
         }
+    };
+    auto store = [&](const Vec16<T> *v) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (it0 + k * kThreads < neps * QT) tile[it0 + k * kThreads] = v[k];
+        for (int k = 0; k < NV; ++k) {
+            const int idx = tid + k * 256, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
+            *reinterpret_cast<Vec16<T> *>(&tile[e * kKkStride + qv]) = v[k];
+        }
+    };
+    lh_d4 acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = lh_d4{0.0, 0.0, 0.0, 0.0};
+    Vec16<T> v[NV];
+    double a[4];
+    load(0, v);
+    const double *wt = w + (size_t)(active ? t : 0) * J * 16 + lane;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = active ? wt[(size_t)(4 * s) * 16] : 0.0;
+    // energy row of this lane's B operand within a chunk, step s: (1 - par) + 2 (4 s + lane / 16)
+    const int erow = (1 - par) + 2 * (lane >> 4), qcol = lane & 15;
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();
+        store(v);
+        __syncthreads();
+        double an[4];
+        if (c + 1 < nch) {
+            load(c + 1, v);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) an[s] = active ? wt[(size_t)(16 * (c + 1) + 4 * s) * 16] : 0.0;
+        }
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const T *brow = tile + (erow + 8 * s) * kKkStride + qcol;
+#pragma unroll
+                for (int qt = 0; qt < 8; ++qt)
+                    acc[qt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], (double)brow[16 * qt], acc[qt], 0, 0, 0);
+            }
+        }
+        if (c + 1 < nch)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[s] = an[s];
     }
-    __syncthreads();
-    const int c = tid & (QT - 1);
-    // groups of QT lanes take groups of kKkW output lags; with QT >= 64 the
-    // group index is wave-uniform and the weights come through scalar loads
-    const int grp = WAVEQ ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> logQT;
-    const int ngrp = kThreads >> logQT;
-    const int nwp = (nw + kKkW - 1) / kKkW * kKkW;
-    for (int w0 = grp * kKkW; w0 < nw; w0 += ngrp * kKkW) {
-        double acc[kKkW];
+    if (!active) return;
 #pragma unroll
-        for (int i = 0; i < kKkW; ++i) acc[i] = 0.0;
-        // four energies per step so that their weight loads overlap
-        int j = 1;
-        for (; j + 3 < neps; j += 4) {
-            double x[4];
+    for (int r = 0; r < 4; ++r) {
+        const int slot = rows[t * 16 + 4 * r + (lane >> 4)].y;
+        if (slot < 0) continue;
+        T *dst = re1 + (size_t)slot * nk + q0 + qcol;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) x[jj] = (double)tile[((j + jj) << logQT) + c];
-            const double *kr = kkw + (size_t)j * nwp + w0;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                for (int i = 0; i < kKkW; ++i) acc[i] += kr[jj * nwp + i] * x[jj];
-        }
-        for (; j < neps; ++j) {
-            const double x = (double)tile[(j << logQT) + c];
-            const double *kr = kkw + (size_t)j * nwp + w0;
-#pragma unroll
-            for (int i = 0; i < kKkW; ++i) acc[i] += kr[i] * x;
-        }
-#pragma unroll
-        for (int i = 0; i < kKkW; ++i)
-            if (w0 + i < nw) re1[(size_t)(w0 + i) * nk + q0 + c] = (T)acc[i];
+        for (int qt = 0; qt < 8; ++qt)
+            if (q0 + 16 * qt + qcol < nk) dst[16 * qt] = (T)acc[qt][r];
     }
 }
 
@@ -1610,7 +1641,8 @@ __global__ void __launch_bounds__(kThreads) k_kk(const T *__restrict__ im1, int 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, const T *__restrict__ re1, int nkx,
                                                  int nky, int neps, const int *__restrict__ lags,
-                                                 const double *__restrict__ fracs, int nw, int zx,
+                                                 const double *__restrict__ fracs,
+                                                 const int *__restrict__ kkslot, int nw, int zx,
                                                  int zy, int ff, double ffs, const double2 *__restrict__ ffx,
                                                  const double2 *__restrict__ ffy, int vkind, double V, int kzn,
                                                  T *__restrict__ re_out, T *__restrict__ imr, T *__restrict__ rer,
@@ -1630,7 +1662,10 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
         const double f = fracs[w];
         imv[i] = f > 0.0 ? (double)(T)lag_blend(im1, nk, q, neps, lags[w], f)
                          : (double)lag_value(im1, nk, q, neps, lags[w]);
-        rev[i] = (double)re1[(size_t)w * nk + q];
+        // Re chi at the omega: its lag's plane, or the blend of two lags
+        const int sa = kkslot[2 * w], sb = kkslot[2 * w + 1];
+        const double ra = (double)re1[(size_t)sa * nk + q];
+        rev[i] = f > 0.0 && sb >= 0 ? (double)(T)((1.0 - f) * ra + f * (double)re1[(size_t)sb * nk + q]) : ra;
     }
     const size_t plane = (size_t)out_nx * out_ny;
     const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
@@ -2240,10 +2275,9 @@ static hipError_t tables_t(const Plan &pl, hipStream_t st)
                            pl.ff_s, pl.p.k_zones);
     }
     if (pl.p.want_rpa) {
-        const int nwp = (pl.p.nomega + kKkW - 1) / kKkW * kKkW;
-        const long n = (long)nwp * g.neps;
-        hipLaunchKernelGGL(k_kkw, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, pl.kkw, pl.d_lag, pl.d_frac, pl.p.nomega,
-                           nwp, g.neps);
+        const long n = (long)pl.kk_ntiles * 16 * pl.kk_nch * 16;
+        hipLaunchKernelGGL(k_kkw, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, st, pl.kkw, pl.d_kkrow, pl.kk_ntiles,
+                           pl.kk_nch, g.neps);
     }
     return hipGetLastError();
 }
@@ -2772,18 +2806,12 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
 {
     const Geo &g = pl.g;
     const int nk = g.nkx * g.nky;
-    int logQT = 6;
-    while (logQT > 0 && ((size_t)g.neps << logQT) * sizeof(T) > 65536) --logQT;
-    while ((1 << logQT) > nk) --logQT;
-    if (logQT == 6)
-        hipLaunchKernelGGL((k_kk<T, true>), dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T),
-                           st, (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
-    else
-        hipLaunchKernelGGL((k_kk<T, false>), dim3(nk >> logQT), dim3(kThreads), ((size_t)g.neps << logQT) * sizeof(T),
-                           st, (const T *)pl.im1, nk, g.neps, pl.p.nomega, pl.kkw, (T *)pl.re1, logQT);
+    hipLaunchKernelGGL(k_kkm<T>, dim3(cdiv(nk, kKkQ), cdiv(pl.kk_ntiles, 4)), dim3(256), 0, st, (const T *)pl.im1, nk,
+                       g.neps, pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
-                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx, pl.zy, ff,
+                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.d_kkslot,
+                       pl.p.nomega, pl.zx, pl.zy, ff,
                        pl.ff_s, pl.ffx, pl.ffy, vkind, U, pl.p.k_zones, re, imr, rer, pl.out_nx, pl.out_ny);
     return hipGetLastError();
 }
