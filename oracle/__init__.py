@@ -540,6 +540,27 @@ def chi_full_mb(xi_bands: np.ndarray, neps: int, emin: float, emax: float, gamma
     return np.moveaxis(g.reshape(nky, nkx, -1), -1, 0)
 
 
+def chi_pair_maps(xi_bands: np.ndarray, neps: int, emin: float, emax: float, gamma: float, ms, m2,
+                  zx: int, zy: int, rho=None) -> np.ndarray:
+    """Eq. (2) with a matrix element per band pair that varies with Q (Eq. (3)):
+    out[m, Y, X] = sum_{nu,mu} m2[nu, mu, Y, X] chi_{nu,mu}(q, m), where
+    chi_{nu,mu} is the first-zone map of the pair alone (band nu occupied,
+    band mu empty: ``chi_full_mb`` with the weight 1 on that pair and 0
+    elsewhere) and q = (u, v) the first-zone point of the extended point
+    (X, Y) (``zone_axis``).  m2 has shape (nb, nb, zy*nky, zx*nkx)."""
+    x = np.asarray(xi_bands, dtype=np.float64)
+    nb, nky, nkx = x.shape
+    m2 = np.asarray(m2, dtype=np.float64).reshape(nb, nb, zy * nky, zx * nkx)
+    out = np.zeros((len(np.atleast_1d(ms)), zy * nky, zx * nkx))
+    for nu in range(nb):
+        for mu in range(nb):
+            w = np.zeros((nb, nb))
+            w[nu, mu] = 1.0
+            pair = chi_full_mb(x, neps, emin, emax, gamma, ms, rho=rho, pair_weight=w)
+            out += extend(pair, zx, zy, 0, 0.0) * m2[nu, mu]
+    return out
+
+
 # --------------------------------------------------------------------------
 # Three-dimensional k-grids (the d^3p of Eq. (9))
 # --------------------------------------------------------------------------
