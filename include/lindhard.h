@@ -123,6 +123,16 @@ typedef struct {
      * The output planes are [omega][Z][Y][X] with Z = (qz + nkz/2) mod nkz,
      * reported as out_ny = nkz * nky rows of out_nx = nkx. */
     int32_t nkz;
+    /* Band-pair matrix elements that vary with the momentum transfer (Eqs.
+     * (2), (3)): optional host array of n_bands * n_bands maps
+     * m2[nu][mu][Y][X] = |M^{nu,mu}_G(Q)|^2 on the extended output grid
+     * (zones_y * nky rows of zones_x * nkx, indexed like the output planes),
+     * finite and >= 0, read only during lindhard_plan.  Then
+     * Im chi(Q, omega) = sum_{nu,mu} m2[nu][mu](Q) chi_{nu,mu}(q, omega), band
+     * nu occupied and band mu empty, q the first-zone point of Q; with one
+     * band it is a tabulated |M(Q)|^2.  It excludes pair_weight (NULL),
+     * ff_kind (NONE), want_rpa, nkz > 1 and grids that are not powers of two. */
+    const double *pair_m2;
 } lindhard_problem;
 
 #define LINDHARD_MAX_BANDS 8

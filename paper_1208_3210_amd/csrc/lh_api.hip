@@ -125,6 +125,13 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     if (p->rho_table)
         for (long k = 0; k < nall; ++k)
             if (!std::isfinite(p->rho_table[k])) return LINDHARD_EINVAL;
+    if (p->pair_m2) {
+        if (p->pair_weight || p->ff_kind != LINDHARD_FF_NONE || p->want_rpa || nkz > 1 || any_size)
+            return LINDHARD_EINVAL;
+        const size_t n = (size_t)nbands * nbands * p->zones_x * p->nkx * p->zones_y * p->nky;
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(p->pair_m2[i]) || p->pair_m2[i] < 0.0) return LINDHARD_EINVAL;
+    }
     if (p->pair_weight) {
         bool any = false;
         for (int i = 0; i < nbands * nbands; ++i) {
@@ -139,6 +146,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.p.eps_table = nullptr;
     pl.p.rho_table = nullptr;
     pl.p.pair_weight = nullptr;
+    pl.p.pair_m2 = nullptr;
     pl.p.k_zones = std::max(1, p->k_zones);
     pl.p.n_bands = nbands;
     pl.p.nkz = nkz;
@@ -146,6 +154,16 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.nb = nbands;
     pl.pairs = p->pair_weight != nullptr;
     if (pl.pairs) pl.pairw.assign(p->pair_weight, p->pair_weight + nbands * nbands);
+    pl.has_m2 = p->pair_m2 != nullptr;
+    pl.m2_pairs.clear();
+    if (pl.has_m2) {
+        const size_t plane = (size_t)p->zones_x * p->nkx * p->zones_y * p->nky;
+        for (int k = 0; k < nbands * nbands; ++k) {
+            const double *m = p->pair_m2 + (size_t)k * plane;
+            if (std::any_of(m, m + plane, [](double v) { return v != 0.0; })) pl.m2_pairs.push_back(k);
+        }
+        if (pl.m2_pairs.empty()) pl.m2_pairs.push_back(0);  // all zero: one pair gives the zero map
+    }
     pl.omega.assign(p->omega, p->omega + p->nomega);
     pl.deps = (p->emax - p->emin) / p->neps;
     Geo &g = pl.g;
@@ -494,12 +512,13 @@ std::vector<BufSpec> plan_buffers(const Plan &cpl)
     const size_t nk = (size_t)g.nkx * g.nky * g.nkz;
     const size_t sl = g.even ? g.slice_e * es : g.slice_elems * cs;  // bytes per slice
     const bool pair_ws = pl.pairs && g.nL > 0, rpa = pl.p.want_rpa != 0;
+    const bool band_ws = (pl.pairs || (pl.has_m2 && pl.nb > 1)) && g.nL > 0;  // per-band spectra
     const size_t Mx = g.bs ? ((size_t)1 << g.logMx) * cs : 0, My = g.bs ? ((size_t)1 << g.logMy) * cs : 0;
     const size_t nw = (size_t)pl.p.nomega;
     return {
         {(void **)&pl.xi, nk * 8 * pl.nb},
         {&pl.rho, pl.has_rho ? nk * es * pl.nb : 0},
-        {&pl.bspec, pair_ws ? (size_t)pl.nb * g.nS * sl : 0},
+        {&pl.bspec, band_ws ? (size_t)pl.nb * g.nS * sl : 0},
         {&pl.sacc, pair_ws ? (size_t)g.nL * sl : 0},
         {&pl.twx, g.nkx * cs},
         {&pl.twy, g.nky * cs},
@@ -521,6 +540,7 @@ std::vector<BufSpec> plan_buffers(const Plan &cpl)
         {(void **)&pl.kkw, rpa ? (size_t)pl.kk_ntiles * 16 * pl.kk_nch * 16 * 8 : 0},
         {(void **)&pl.d_kkrow, rpa ? pl.kk_rows.size() * sizeof(int2) : 0},
         {(void **)&pl.d_kkslot, rpa ? pl.kk_slot.size() * sizeof(int) : 0},
+        {&pl.m2, pl.has_m2 ? (size_t)pl.nb * pl.nb * pl.out_nx * pl.out_ny * es : 0},
     };
 }
 
@@ -624,7 +644,7 @@ void plan_free(Plan &pl)
                      &pl.im1,             &pl.re1,           (void **)&pl.kkw, (void **)&pl.scratch,
                      &pl.rho,              &pl.bspec,         &pl.sacc,         &pl.bsx[0], &pl.bsx[1], &pl.bsx[2], &pl.bsx[3],
                      &pl.bsy[0],           &pl.bsy[1],        &pl.bsy[2], &pl.bsy[3], (void **)&pl.d_kkrow,
-                     (void **)&pl.d_kkslot};
+                     (void **)&pl.d_kkslot, &pl.m2};
     for (void **p : ptrs) *p = nullptr;
 }
 
@@ -1028,6 +1048,17 @@ static lindhard_status plan_bind_band(Plan &pl, const lindhard_problem *p, hipSt
     pl.p.filling = p->filling;
     pl.p.gamma = p->gamma;
     if (pl.pairs) pl.pairw.assign(p->pair_weight, p->pair_weight + pl.nb * pl.nb);
+    std::vector<float> m2_32;
+    if (pl.has_m2) {
+        // the pair maps, rounded once to the plan's precision
+        const size_t n = (size_t)pl.nb * pl.nb * pl.out_nx * pl.out_ny;
+        if (pl.g.fp64) {
+            LH_TRY(hipMemcpyAsync(pl.m2, p->pair_m2, n * sizeof(double), hipMemcpyHostToDevice, st));
+        } else {
+            m2_32.assign(p->pair_m2, p->pair_m2 + n);
+            LH_TRY(hipMemcpyAsync(pl.m2, m2_32.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+        }
+    }
     const size_t nk = (size_t)pl.g.nkx * pl.g.nky * pl.g.nkz;
     double band_lo = 0.0, band_hi = 0.0;
     const size_t nall = nk * pl.nb;
@@ -1134,10 +1165,10 @@ std::string plan_class_key(const Plan &pl)
     const lindhard_problem &p = pl.p;
     const Geo &g = pl.g;
     char b[320];
-    std::snprintf(b, sizeof b, "p%d k%dx%dx%d e%d[%a,%a] z%dx%d ff%d:%a rpa%d kz%d nb%d pr%d rho%d ev%d bs%d",
+    std::snprintf(b, sizeof b, "p%d k%dx%dx%d e%d[%a,%a] z%dx%d ff%d:%a rpa%d kz%d nb%d pr%d m2%d rho%d ev%d bs%d",
                   p.precision, g.nkx, g.nky, g.nkz, g.neps, p.emin, p.emax, p.zones_x, p.zones_y, p.ff_kind,
                   p.ff_kind ? p.ff_width : 0.0, p.want_rpa ? 1 : 0, p.k_zones, pl.nb, pl.pairs ? 1 : 0,
-                  pl.has_rho ? 1 : 0, g.even, g.bs);
+                  pl.has_m2 ? 1 : 0, pl.has_rho ? 1 : 0, g.even, g.bs);
     return b;
 }
 

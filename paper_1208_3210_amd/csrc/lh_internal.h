@@ -130,6 +130,12 @@ struct Plan {
     int nb = 1;                // bands (xi and rho hold nb planes)
     bool pairs = false;        // band-pair sum with weights pairw[nu * nb + mu] (else one summed band)
     std::vector<double> pairw;
+    // band-pair maps |M^{nu,mu}(Q)|^2 on the extended output grid, in T
+    // ([nu][mu][out_ny][out_nx]); m2_pairs: the pairs nu * nb + mu whose map is
+    // not all zero (at least one entry)
+    bool has_m2 = false;
+    void *m2 = nullptr;
+    std::vector<int> m2_pairs;
     void *bspec = nullptr;     // pair sum: forward-transformed spectra of every band, nb x nS slices
     void *sacc = nullptr;      // pair sum: the summed window outputs, nL slices
     double2 *ffx = nullptr;    // (exp(-s Qx^2), Qx^2) per extended column

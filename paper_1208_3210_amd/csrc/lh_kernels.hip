@@ -570,7 +570,8 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                                                 const cx<T> *__restrict__ twx, const PlaneSrc *__restrict__ psrc,
                                                 double scale, int zx, int zy, int ff, double ffs,
                                                 const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
-                                                T *__restrict__ out, int out_nx, int out_ny)
+                                                T *__restrict__ out, int out_nx, int out_ny,
+                                                const T *__restrict__ m2, int acc)
 {
     using F = RegFFT<T, LOGL, true, 4, kTwLds<T>>;
     constexpr int L = F::N, E = F::E, G = F::G;
@@ -587,6 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
     const int nkx = g.nkx, nky = g.nky;
 
     if (MODE == 0 && slot < 0) {
+        if (acc) return;  // adds nothing
         for (int rz = 0; rz < R * zy; ++rz) {
             const int r = rz % R, zi = rz / R;
             const int Y = zi * nky + ((qy0 + r + zy * nky / 2) & (nky - 1));
@@ -660,6 +662,17 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                     if (ff) {
                         a = (T)((double)a * form_factor_sq(ffx[X], fy, ffs));
                         b = (T)((double)b * form_factor_sq(ffx[X + 1], fy, ffs));
+                    }
+                    if (m2) {
+                        // a band pair's |M(Q)|^2 map, the pairs summed in the output
+                        const cx<T> mm = *reinterpret_cast<const cx<T> *>(m2 + (size_t)Y * out_nx + X);
+                        a = (T)((double)a * (double)mm.x);
+                        b = (T)((double)b * (double)mm.y);
+                        if (acc) {
+                            const cx<T> o = *reinterpret_cast<const cx<T> *>(orow + X);
+                            a += o.x;
+                            b += o.y;
+                        }
                     }
                     *reinterpret_cast<cx<T> *>(orow + X) = mk<T>(a, b);
                 }
@@ -1366,7 +1379,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
                                                 const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
-                                                int out_ny)
+                                                int out_ny, const T *__restrict__ m2, int acc)
 {
     using F = RegFFT<T, LOGNX, true, 4, kTwLds<T>>;
     constexpr int N = F::N, E = F::E, G = F::G;
@@ -1384,6 +1397,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
 
     if (MODE == 0 && slot < 0) {
+        if (acc) return;  // adds nothing
         for (int rz = 0; rz < rows * 2 * zy; ++rz) {
             const int r = rz % rows, mir = (rz / rows) & 1, zi = rz / (2 * rows);
             const int qy0 = 2 * p0 + r;
@@ -1473,6 +1487,11 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
                             const int X = zj * nkx + ((qx + nkx / 2) & (nkx - 1));
                             T val = (half ? v[s].y : v[s].x) * sc;
                             if (ff) val = (T)((double)val * form_factor_sq(ffx[X], fy, ffs));
+                            if (m2) {
+                                // a band pair's |M(Q)|^2 map, the pairs summed in the output
+                                val = (T)((double)val * (double)m2[(size_t)Y * out_nx + X]);
+                                if (acc) val += orow[X];
+                            }
                             orow[X] = val;
                         }
                     }
@@ -2341,14 +2360,15 @@ static void launch_p3f(const Plan &pl, cx<T> *spec, hipStream_t st)
 }
 
 template <typename T, int LOGL, int MODE>
-static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, int onx, int ony, hipStream_t st,
+                      const T *m2 = nullptr, int acc = 0)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
                        (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
-                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony);
+                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony, m2, acc);
 }
 
 template <typename T, int LOGNX>
@@ -2382,7 +2402,8 @@ static void launch_ecol(const Plan &pl, T *spec, int nslices, hipStream_t st)
 }
 
 template <typename T, int LOGNX, int MODE>
-static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, hipStream_t st)
+static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int onx, int ony, hipStream_t st,
+                      const T *m2 = nullptr, int acc = 0)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGNX, true>;
@@ -2391,7 +2412,7 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
                        (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g,
                        (const cx<T> *)pl.twx, pl.d_src, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out,
-                       onx, ony);
+                       onx, ony, m2, acc);
 }
 
 #define LH_SWITCH_LOG(v, CALL)                   \
@@ -2606,8 +2627,9 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         }
         return hipGetLastError();
     };
-    // P5 from the window output in buf
-    auto p5 = [&](void *buf) -> hipError_t {
+    // P5 from the window output in buf; m2: a band pair's |M(Q)|^2 map
+    // (acc: the pair adds to the output)
+    auto p5 = [&](void *buf, const T *m2 = nullptr, int acc = 0) -> hipError_t {
         const bool rpa = pl.p.want_rpa != 0;
         if (g.even) {
             T *spr = (T *)buf;
@@ -2616,7 +2638,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
                 LH_SWITCH_LOG12(g.logNx, LH_E5)
 #undef LH_E5
             } else {
-#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st)
+#define LH_E5(LG) launch_e5<T, LG, 0>(pl, spr, pl.p.nomega, out, pl.out_nx, pl.out_ny, st, m2, acc)
                 LH_SWITCH_LOG12(g.logNx, LH_E5)
 #undef LH_E5
             }
@@ -2631,7 +2653,7 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
                 for (int z = 0; z < g.nkz; ++z) {
                     const cx<T> *sz = spec + (size_t)z * g.plane_elems;
                     T *oz = out + (size_t)((z + g.nkz / 2) & (g.nkz - 1)) * g.nky * pl.out_nx;
-#define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, st)
+#define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, st, m2, acc)
                     LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
                 }
@@ -2639,8 +2661,9 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         }
         return hipGetLastError();
     };
+    const size_t plane_out = (size_t)pl.out_nx * pl.out_ny;
     mark(0);
-    if (g.nL > 0 && !pl.pairs) {
+    if (g.nL > 0 && !pl.pairs && !(pl.has_m2 && pl.nb > 1)) {
         for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(p1(pl.spec, b, b > 0));
         mark(1);
         LH_HIP_TRY(col(pl.spec, g.nS, false));
@@ -2649,7 +2672,32 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         mark(3);
         LH_HIP_TRY(col(pl.spec, g.nL, true));
         mark(4);
-        LH_HIP_TRY(p5(pl.spec));
+        LH_HIP_TRY(p5(pl.spec, pl.has_m2 ? (const T *)pl.m2 : nullptr, 0));
+    } else if (g.nL > 0 && pl.has_m2) {
+        // Eqs. (2), (3) with a |M(Q)|^2 map per band pair: the map multiplies
+        // after the inverse transforms, so every pair (nu occupied, mu empty)
+        // is correlated and transformed back on its own -- the occupied slices
+        // of band nu followed by the empty ones of band mu -- and the pairs
+        // are summed into the output, in a fixed order
+        const size_t nocc = (size_t)(g.j0 - g.jA), nb = (size_t)pl.nb;
+        char *bs = (char *)pl.bspec, *sp = (char *)pl.spec;
+        for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(p1(bs + b * g.nS * sb, b, 0));
+        mark(1);
+        for (int b = 0; b < pl.nb; ++b) LH_HIP_TRY(col(bs + b * g.nS * sb, g.nS, false));
+        mark(2);
+        const size_t nemp = (size_t)g.nS - nocc;
+        for (size_t k = 0; k < pl.m2_pairs.size(); ++k) {
+            const size_t nu = (size_t)pl.m2_pairs[k] / nb, mu = (size_t)pl.m2_pairs[k] % nb;
+            if (nocc > 0) LH_HIP_TRY(hipMemcpyAsync(sp, bs + nu * g.nS * sb, nocc * sb, hipMemcpyDeviceToDevice, st));
+            if (nemp > 0)
+                LH_HIP_TRY(hipMemcpyAsync(sp + nocc * sb, bs + (mu * g.nS + nocc) * sb, nemp * sb,
+                                          hipMemcpyDeviceToDevice, st));
+            LH_HIP_TRY(window_t<T>(pl, st));
+            LH_HIP_TRY(col(pl.spec, g.nL, true));
+            LH_HIP_TRY(p5(pl.spec, (const T *)pl.m2 + (size_t)pl.m2_pairs[k] * plane_out, k > 0));
+        }
+        mark(3);
+        mark(4);
     } else if (g.nL > 0) {
         // Eq. (2): sum over band pairs (nu occupied, mu empty).  The window
         // pairs occupied slices (energies below j0) with empty ones only and

@@ -44,7 +44,7 @@ size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Job {
     uint64_t id = 0;
     lindhard_problem p{};
-    std::vector<double> omega, table, rho, pairw;  // the job's copies (dropped when it ends)
+    std::vector<double> omega, table, rho, pairw, m2;  // the job's copies (dropped when it ends)
     double U = NAN;
     void *im = nullptr, *re = nullptr, *imr = nullptr, *rer = nullptr;
     std::string key;            // plan class
@@ -189,6 +189,7 @@ static lindhard_status run_job(lindhard_server_s *S, Job &j, lindhard_plan_t *pl
     p.eps_table = j.table.empty() ? nullptr : j.table.data();
     p.rho_table = j.rho.empty() ? nullptr : j.rho.data();
     p.pair_weight = j.pairw.empty() ? nullptr : j.pairw.data();
+    p.pair_m2 = j.m2.empty() ? nullptr : j.m2.data();
     lindhard_status s;
     if (*plan) {
         s = plan_rebind(*plan, &p, st);
@@ -205,6 +206,7 @@ static lindhard_status run_job(lindhard_server_s *S, Job &j, lindhard_plan_t *pl
     std::vector<double>().swap(j.table);
     std::vector<double>().swap(j.rho);
     std::vector<double>().swap(j.pairw);
+    std::vector<double>().swap(j.m2);
     return s;
 }
 
@@ -371,10 +373,13 @@ lindhard_status lindhard_serve_submit(lindhard_server_t S, const lindhard_proble
     if (p->eps_table) job->table.assign(p->eps_table, p->eps_table + nall);
     if (p->rho_table) job->rho.assign(p->rho_table, p->rho_table + nall);
     if (p->pair_weight) job->pairw.assign(p->pair_weight, p->pair_weight + nb * nb);
+    if (p->pair_m2)
+        job->m2.assign(p->pair_m2, p->pair_m2 + nb * nb * (size_t)p->zones_x * p->nkx * (size_t)p->zones_y * p->nky);
     job->p.omega = nullptr;
     job->p.eps_table = nullptr;
     job->p.rho_table = nullptr;
     job->p.pair_weight = nullptr;
+    job->p.pair_m2 = nullptr;
     job->U = U_or_nan;
     job->im = im_chi;
     job->re = re_chi;
@@ -441,6 +446,7 @@ lindhard_status lindhard_serve_cancel(lindhard_server_t S, uint64_t ticket)
     std::vector<double>().swap(j.table);
     std::vector<double>().swap(j.rho);
     std::vector<double>().swap(j.pairw);
+    std::vector<double>().swap(j.m2);
     S->canceled += 1;
     S->cv_done.notify_all();
     S->cv_work.notify_all();

@@ -60,7 +60,7 @@ class Problem(ctypes.Structure):
         ("k_zones", ctypes.c_int32), ("rho_table", ctypes.POINTER(ctypes.c_double)),
         ("omega_interp", ctypes.c_int32),
         ("n_bands", ctypes.c_int32), ("pair_weight", ctypes.POINTER(ctypes.c_double)),
-        ("nkz", ctypes.c_int32),
+        ("nkz", ctypes.c_int32), ("pair_m2", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -179,14 +179,15 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
                  zones: tuple = (1, 1), ff_kind: int = LINDHARD_FF_NONE, ff_width: float = 0.0,
                  precision: int = LINDHARD_FP32C, want_rpa: bool = False, k_zones: int = 1,
                  rho_table: Optional[np.ndarray] = None, omega_interp: bool = False, n_bands: int = 1,
-                 pair_weight: Optional[np.ndarray] = None, nkz: int = 1):
+                 pair_weight: Optional[np.ndarray] = None, nkz: int = 1, pair_m2: Optional[np.ndarray] = None):
     """Fill a Problem; returns (problem, keepalive) -- keep `keepalive` until the call."""
     om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
     keep = [om]
     nb = max(1, int(n_bands))
     nk3 = nkx * nky * max(1, int(nkz))
+    n_m2 = nb * nb * int(zones[0]) * nkx * int(zones[1]) * nky
     for name, tab, n in (("eps_table", eps_table, nb * nk3), ("rho_table", rho_table, nb * nk3),
-                         ("pair_weight", pair_weight, nb * nb)):
+                         ("pair_weight", pair_weight, nb * nb), ("pair_m2", pair_m2, n_m2)):
         if tab is not None and np.asarray(tab).size != n:
             raise ValueError("%s holds %d values, %d expected" % (name, np.asarray(tab).size, n))
     p = Problem()
@@ -215,6 +216,10 @@ def make_problem(*, nkx: int, nky: int, neps: int, emin: float, emax: float, gam
         rt = np.ascontiguousarray(np.asarray(rho_table, dtype=np.float64))
         keep.append(rt)
         p.rho_table = rt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if pair_m2 is not None:
+        pm = np.ascontiguousarray(np.asarray(pair_m2, dtype=np.float64))
+        keep.append(pm)
+        p.pair_m2 = pm.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return p, keep
 
 

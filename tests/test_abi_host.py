@@ -168,3 +168,29 @@ def test_shape_limits_match_the_header():
     assert shape(omega=np.arange(65535) % 32 / 32.0)[0] == 0
     assert shape(nky=4096, zones=(1, 15))[0] == 0
     assert shape(nkx=4096, zones=(15, 1)) == (0, (32, 32, 15 * 4096, 8))
+
+
+def test_pair_maps_validated_on_the_host():
+    """Band-pair |M(Q)|^2 maps: accepted on their own (the output shape is the
+    extended grid's), refused with pair weights, the analytic form factor,
+    RPA, a 3D grid, a grid of any size, or a negative or non-finite value."""
+    from paper_1208_3210_amd import lindhard as LH
+
+    tab = np.zeros((2, 32, 32))
+    m2 = np.ones((2, 2, 32, 3 * 32))
+    ok = dict(eps_table=tab, n_bands=2, zones=(3, 1), pair_m2=m2)
+    p, keep = LH.make_problem(**_base(**ok))
+    assert LH.problem_shape(p) == (32, 32, 96)
+    bad = [dict(pair_weight=np.ones((2, 2))), dict(ff_kind=1, ff_width=0.6), dict(want_rpa=True),
+           dict(pair_m2=-m2), dict(pair_m2=np.where(np.arange(m2.size).reshape(m2.shape) == 7, np.inf, m2))]
+    for b in bad:
+        p, keep = LH.make_problem(**_base(**dict(ok, **b)))
+        with pytest.raises(LH.LindhardError) as ei:
+            LH.problem_shape(p)
+        assert ei.value.status == -1
+    p, keep = LH.make_problem(**_base(eps_table=np.zeros((4, 32, 32)), nkz=4, pair_m2=np.ones((1, 1, 32, 32))))
+    with pytest.raises(LH.LindhardError):
+        LH.problem_shape(p)
+    p, keep = LH.make_problem(**_base(nkx=33, eps_table=np.zeros((32, 33)), pair_m2=np.ones((1, 1, 32, 33))))
+    with pytest.raises(LH.LindhardError):
+        LH.problem_shape(p)

@@ -127,3 +127,80 @@ def test_multiband_argument_errors():
     # a table of the wrong size is refused before the call
     with pytest.raises(ValueError):
         LH.Plan(precision=LH.LINDHARD_FP32C, **dict(cfg, n_bands=3))
+
+
+# ---- band-pair maps |M^{nu,mu}(Q)|^2 (Eqs. (2), (3)) ---------------------
+def pair_maps(nb, nky, nkx, zx, zy, seed, zero=()):
+    """Smooth positive maps over the extended grid, one per pair (distinct, not
+    symmetric in X and Y), with the pairs in `zero` all zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Y, X = np.meshgrid(np.arange(zy * nky) / nky, np.arange(zx * nkx) / nkx, indexing="ij")
+    m2 = np.empty((nb, nb, zy * nky, zx * nkx))
+    for nu in range(nb):
+        for mu in range(nb):
+            a, b, c = rng.uniform(0.2, 1.5, 3)
+            m2[nu, mu] = a * np.exp(-b * (X - 1.3) ** 2 - 0.5 * c * Y) * (1.0 + 0.5 * np.sin(3.0 * X + c * Y))
+    for nu, mu in zero:
+        m2[nu, mu] = 0.0
+    return m2
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_pair_maps_against_oracle(prec, symmetric):
+    """Three bands with a Q-dependent map per pair (one pair's map zero): the
+    even path over 3 x 3 zones and the general path over 3 x 1 zones, against
+    the oracle's per-pair sum."""
+    cfg = cfg_of(symmetric, nb=3, pairs=False)
+    cfg.pop("ff_kind", None)
+    cfg.pop("ff_width", None)
+    zx, zy = (3, 3) if symmetric else (3, 1)
+    cfg["zones"] = (zx, zy)
+    cfg["pair_m2"] = pair_maps(3, 32, 32, zx, zy, seed=5 + symmetric, zero=[(0, 2)])
+    eps = np.asarray(cfg["eps_table"])
+    mu = oracle.mu_solve_bands(eps, cfg["gamma"], cfg["filling"])
+    d = (cfg["emax"] - cfg["emin"]) / cfg["neps"]
+    lags = np.rint(np.asarray(cfg["omega"]) / d).astype(np.int64)
+    ref = oracle.chi_pair_maps(eps - mu, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], lags,
+                               cfg["pair_m2"], zx, zy)
+    plan = LH.Plan(precision=prec, **cfg)
+    sched = plan.info.schedule.decode()
+    assert (" even " in sched) == symmetric
+    got = plan.exec()
+    torch.cuda.synchronize()
+    err = normwise(got.double().cpu().numpy(), ref)
+    print("pair maps prec=%d sym=%d err=%.3e %s" % (prec, symmetric, err, sched))
+    assert err <= TOL[prec]
+    again = plan.exec()
+    torch.cuda.synchronize()
+    assert torch.equal(got, again)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_pair_map_of_one_band_equals_the_orbital_form_factor(prec):
+    """One band with the d-wave orbital's |M(Q)|^2 tabulated equals the
+    analytic form-factor path, and both equal the oracle."""
+    base = dict(t=0.42, tp=-0.1, tpp=0.05, filling=1.1, nkx=64, nky=64, neps=64, emin=-1.5, emax=1.5, gamma=0.06,
+                omega=np.arange(1, 30, 3) * (3.0 / 64), zones=(3, 5))
+    a = LH.Plan(precision=prec, ff_kind=1, ff_width=0.6, **base)
+    b = LH.Plan(precision=prec, pair_m2=oracle.m2_extended(64, 64, 3, 5, 1, 0.6), **base)
+    x, y = a.exec(), b.exec()
+    torch.cuda.synchronize()
+    assert normwise(y.double().cpu().numpy(), x.double().cpu().numpy()) <= TOL[prec]
+    a.close()
+    b.close()
+
+
+def test_pair_map_argument_errors():
+    cfg = cfg_of(True, nb=2, pairs=False)
+    cfg.pop("ff_kind")
+    cfg.pop("ff_width")
+    m2 = pair_maps(2, 32, 32, 3, 3, seed=1)
+    for bad in (dict(pair_weight=np.ones((2, 2))), dict(ff_kind=1, ff_width=0.6), dict(want_rpa=True),
+                dict(pair_m2=-m2), dict(pair_m2=np.where(m2 > 1.0, np.nan, m2))):
+        c = dict(cfg, pair_m2=m2)
+        c.update(bad)
+        with pytest.raises(LH.LindhardError) as ei:
+            LH.Plan(precision=LH.LINDHARD_FP32C, **c)
+        assert ei.value.status == LH.LINDHARD_EINVAL

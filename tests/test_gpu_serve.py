@@ -147,7 +147,8 @@ def test_exec_batch_equals_individual_runs():
 
 def test_served_extended_forms_equal_alone():
     """Jobs using the wider problem fields (several bands with pair weights,
-    a 3D grid, a grid that is not a power of two, omegas between lags) are
+    a 3D grid, a grid that is not a power of two, omegas between lags, band
+    pairs with a |M(Q)|^2 map each) are
     copied whole at submission: served results equal the same problems run
     alone, bit for bit."""
     d = 3.0 / 64
@@ -159,6 +160,9 @@ def test_served_extended_forms_equal_alone():
         dict(base, eps_table=np.random.Generator(np.random.PCG64(2)).uniform(-1.2, 1.5, size=(17, 33)), nkx=33,
              nky=17, omega=np.arange(1, 30, 4) * d),
         dict(base, t=0.4, tp=-0.1, tpp=0.05, nkx=32, nky=32, omega_interp=True, omega=[2.5 * d, 7.25 * d, 30.9 * d]),
+        dict(base, eps_table=W.multiband_tables(32, 2, seed=5), n_bands=2, nkx=32, nky=32, zones=(3, 1),
+             pair_m2=np.random.Generator(np.random.PCG64(6)).uniform(0.0, 1.0, size=(2, 2, 32, 96)),
+             omega=np.arange(1, 30, 4) * d),
     ]
     srv = LH.Server(hbm_budget_bytes=4 << 30, max_inflight=4, max_queue=16)
     tickets = [srv.submit(float("nan"), **j) for j in jobs]
