@@ -1543,6 +1543,17 @@ struct BatchGraph {
     hipGraphExec_t exec = nullptr;
 };
 std::vector<BatchGraph> g_graphs;
+// Batched groups of a batch: instances of the even path with equal group
+// keys run every pass as one launch over the group (descriptors in device
+// memory, kept with the batch's signature until one of its plans goes);
+// `single` lists the instances that run on their own.
+struct BatchGroups {
+    std::vector<const void *> sig;
+    std::vector<std::vector<int>> groups;
+    std::vector<int> single;
+    EvenInst *d_desc = nullptr;
+};
+std::vector<BatchGroups> g_groups;
 hipStream_t g_capture_stream = nullptr;
 
 bool batch_graphs_enabled()
@@ -1552,21 +1563,89 @@ bool batch_graphs_enabled()
 }
 }  // namespace
 
-// Fork the instances over the worker streams and join them back into `origin`.
+// The groups of a batch (made on its first call, with their descriptors).
+static hipError_t batch_groups(const std::vector<const void *> &sig, const lindhard_plan_t *plans, int n,
+                               void *const *outs, const BatchGroups **out)
+{
+    for (const BatchGroups &bg : g_groups)
+        if (bg.sig == sig) {
+            *out = &bg;
+            return hipSuccess;
+        }
+    BatchGroups bg;
+    bg.sig = sig;
+    std::map<std::string, std::vector<int>> by_key;
+    for (int i = 0; i < n; ++i) {
+        const std::string k = even_group_key(plans[i]->pl);
+        if (k.empty())
+            bg.single.push_back(i);
+        else
+            by_key[k].push_back(i);
+    }
+    std::vector<EvenInst> desc;
+    for (auto &kv : by_key) {
+        if (kv.second.size() < 2) {
+            bg.single.push_back(kv.second[0]);
+            continue;
+        }
+        bg.groups.push_back(kv.second);
+        for (int i : kv.second) {
+            desc.emplace_back();
+            even_group_fill(plans[i]->pl, outs[i], desc.back());
+        }
+    }
+    if (!desc.empty()) {
+        hipError_t e = hipMalloc((void **)&bg.d_desc, desc.size() * sizeof(EvenInst));
+        if (e == hipSuccess) e = hipMemcpy(bg.d_desc, desc.data(), desc.size() * sizeof(EvenInst), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (bg.d_desc) (void)hipFree(bg.d_desc);
+            return e;
+        }
+    }
+    g_groups.push_back(std::move(bg));
+    *out = &g_groups.back();
+    return hipSuccess;
+}
+
+// Fork the batch over the worker streams and join it back into `origin`:
+// each group of even-path instances runs its passes as one launch each, the
+// other instances on their own; largest work first, round-robin over the
+// streams.
 static hipError_t batch_launch(BatchPool *bp, const lindhard_plan_t *plans, int n, void *const *outs,
-                               hipStream_t origin)
+                               const BatchGroups &bg, hipStream_t origin)
 {
     hipError_t e = hipEventRecord(bp->fork, origin);
-    const int ns = std::min(n, kBatchStreams);
+    struct Unit {
+        int group;  // index into bg.groups, or -1 - instance
+        size_t work;
+    };
+    std::vector<Unit> units;
+    for (size_t k = 0; k < bg.groups.size(); ++k) {
+        size_t w = 0;
+        for (int i : bg.groups[k]) w += plans[i]->pl.out_elems;
+        units.push_back({(int)k, w});
+    }
+    for (int i : bg.single) units.push_back({-1 - i, plans[i]->pl.out_elems});
+    std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.work > b.work; });
+    const int ns = std::min((int)units.size(), kBatchStreams);
     for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(bp->st[i], bp->fork, 0);
-    // largest instances first, round-robin over the worker streams
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return plans[a]->pl.out_elems > plans[b]->pl.out_elems; });
-    for (int k = 0; k < n && e == hipSuccess; ++k) {
-        const int i = order[k];
-        e = launch_exec(plans[i]->pl, outs[i], bp->st[k % ns]);
+    size_t off = 0;
+    std::vector<size_t> first(bg.groups.size());
+    for (size_t k = 0; k < bg.groups.size(); ++k) {
+        first[k] = off;
+        off += bg.groups[k].size();
+    }
+    for (size_t u = 0; u < units.size() && e == hipSuccess; ++u) {
+        hipStream_t st = bp->st[u % ns];
+        if (units[u].group >= 0) {
+            const std::vector<int> &gi = bg.groups[units[u].group];
+            std::vector<const Plan *> pls;
+            for (int i : gi) pls.push_back(&plans[i]->pl);
+            e = launch_even_group(pls.data(), (int)pls.size(), bg.d_desc + first[units[u].group], st);
+        } else {
+            const int i = -1 - units[u].group;
+            e = launch_exec(plans[i]->pl, outs[i], st);
+        }
     }
     for (int i = 0; i < ns && e == hipSuccess; ++i) {
         e = hipEventRecord(bp->join[i], bp->st[i]);
@@ -1603,6 +1682,8 @@ lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, voi
         sig.push_back(plans[i]);
         sig.push_back(outs[i]);
     }
+    const BatchGroups *bg = nullptr;
+    if (e == hipSuccess) e = batch_groups(sig, plans, n, outs, &bg);
     hipGraphExec_t gexec = nullptr;
     if (e == hipSuccess && batch_graphs_enabled()) {
         for (const BatchGraph &bg : g_graphs)
@@ -1612,7 +1693,7 @@ lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, voi
             hipGraph_t graph = nullptr;
             if (e == hipSuccess) e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t el = batch_launch(bp, plans, n, outs, g_capture_stream);
+                const hipError_t el = batch_launch(bp, plans, n, outs, *bg, g_capture_stream);
                 e = hipStreamEndCapture(g_capture_stream, &graph);
                 if (e == hipSuccess) e = el;
             }
@@ -1622,7 +1703,7 @@ lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, voi
         }
         if (e == hipSuccess) e = hipGraphLaunch(gexec, caller);
     } else if (e == hipSuccess) {
-        e = batch_launch(bp, plans, n, outs, caller);
+        e = batch_launch(bp, plans, n, outs, *bg, caller);
     }
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         e = hipEventRecord(plans[i]->done, caller);
@@ -1642,6 +1723,17 @@ lindhard_status lindhard_plan_destroy(lindhard_plan_t plan)
             if (std::find(g_graphs[i].sig.begin(), g_graphs[i].sig.end(), (const void *)plan) != g_graphs[i].sig.end()) {
                 (void)hipGraphExecDestroy(g_graphs[i].exec);
                 g_graphs.erase(g_graphs.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+        for (size_t i = 0; i < g_groups.size();) {
+            if (std::find(g_groups[i].sig.begin(), g_groups[i].sig.end(), (const void *)plan) != g_groups[i].sig.end()) {
+                if (g_groups[i].d_desc) {
+                    (void)hipDeviceSynchronize();  // no launch of the batch may still read them
+                    (void)hipFree(g_groups[i].d_desc);
+                }
+                g_groups.erase(g_groups.begin() + i);
             } else {
                 ++i;
             }

@@ -163,6 +163,21 @@ struct Plan {
     std::string schedule;
 };
 
+// One instance of a batched launch on the even path: its geometry and the
+// arguments its passes take (device memory, read by the batched kernels at
+// blockIdx.z).
+struct EvenInst {
+    Geo g;
+    const double *xi;
+    const void *rho, *twx, *twy;
+    void *spec;
+    const PlaneSrc *psrc;
+    void *out;
+    const double2 *ffx, *ffy;
+    double emin, deps, gamma, scale, ffs;
+    int zx, zy, ff, onx, ony, nomega;
+};
+
 // Validate and derive everything host-side (no device work).  Fills `pl`.
 lindhard_status plan_describe(const lindhard_problem *p, Plan &pl);
 // One device buffer of a plan: where its pointer lives and its size (0: unused).
@@ -203,6 +218,15 @@ hipError_t launch_cut(const Plan &pl, const void *im, const int *xy, int npts, v
 // res: 3 + 4 * nseg doubles of device memory; im_plane: the plane to cut
 hipError_t launch_envelope(const Plan &pl, const void *im_plane, int dir, int W, int nseg, double qstep, double *res,
                            hipStream_t st);
+
+// Batched launches of the even path: plans of one group (same precision,
+// grid, momentum-density use and window schedule; one band, no pair sums,
+// maps or RPA) run each pass as one launch over all instances.  The key is
+// empty for a plan that cannot be batched.
+std::string even_group_key(const Plan &pl);
+void even_group_fill(const Plan &pl, void *out, EvenInst &d);
+hipError_t launch_even_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st);
+hipError_t launch_e3q_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st);
 
 // Setup kernels.
 hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st);

@@ -701,7 +701,7 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // kernel otherwise takes one register more than four waves allow); FP64 would
 // spill under that bound.
 template <typename T, int LOGNX, bool W>
-__global__ void __launch_bounds__(kThreads, (sizeof(T) == 4 && LOGNX < 12) ? 4 : 1) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
+__device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo &g, double emin, double deps,
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
                                                 const T *__restrict__ rho, int acc)
 {
@@ -790,11 +790,28 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 4 && LOGNX < 12) ? 4 :
     }
 }
 
+template <typename T, int LOGNX, bool W>
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 4 && LOGNX < 12) ? 4 : 1) k_e1(const double *__restrict__ xi, Geo g, double emin, double deps,
+                                                double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
+                                                const T *__restrict__ rho, int acc)
+{
+    e1_body<T, LOGNX, W>(xi, g, emin, deps, gamma, twx, spec, rho, acc);
+}
+// Batched P1: instance blockIdx.z of the descriptors (band 0, no accumulation)
+template <typename T, int LOGNX, bool W>
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 4 && LOGNX < 12) ? 4 : 1) k_e1_batch(const EvenInst *__restrict__ in)
+{
+    const EvenInst &d = in[blockIdx.z];
+    const Geo g = d.g;
+    if ((int)blockIdx.y * g.e1_jc >= g.nS) return;
+    e1_body<T, LOGNX, W>(d.xi, g, d.emin, d.deps, d.gamma, (const cx<T> *)d.twx, (T *)d.spec, (const T *)d.rho, 0);
+}
+
 // Column pass (even), forward or inverse: each line is a pair of adjacent
 // real columns of a tile (read as one complex value per row); rows above
 // nky/2 are the mirror of the stored ones.  Transformed in place.
 template <typename T, int LOGN, bool INV>
-__global__ void __launch_bounds__(col_threads(LOGN)) k_ecol(T *__restrict__ spec, Geo g,
+__device__ __forceinline__ void ecol_body(T *__restrict__ spec, const Geo &g,
                                                            const cx<T> *__restrict__ twy)
 {
     using F = RegFFT<T, LOGN, INV, ilog2_c(kEcolElems), kTwLds<T>>;
@@ -832,6 +849,22 @@ __global__ void __launch_bounds__(col_threads(LOGN)) k_ecol(T *__restrict__ spec
     }
 }
 
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(col_threads(LOGN)) k_ecol(T *__restrict__ spec, Geo g,
+                                                           const cx<T> *__restrict__ twy)
+{
+    ecol_body<T, LOGN, INV>(spec, g, twy);
+}
+// Batched column pass: instance blockIdx.z, its nS (forward) or nL (inverse) slices
+template <typename T, int LOGN, bool INV>
+__global__ void __launch_bounds__(col_threads(LOGN)) k_ecol_batch(const EvenInst *__restrict__ in)
+{
+    const EvenInst &d = in[blockIdx.z];
+    const Geo g = d.g;
+    if ((int)blockIdx.y >= (INV ? g.nL : g.nS)) return;
+    ecol_body<T, LOGN, INV>((T *)d.spec, g, (const cx<T> *)d.twy);
+}
+
 // Energy window (even, direct): S(r, m) = sum_j B(r, j) B(r, j + m), real.
 // With P'[a] = B(j0 - 1 - a) (occupied, reversed) and H'[x] = B(j0 + x)
 // (unoccupied), S(m) = sum_{a=0}^{m-1} P'[a] H'[m-1-a]: a linear convolution.
@@ -845,7 +878,7 @@ __global__ void __launch_bounds__(col_threads(LOGN)) k_ecol(T *__restrict__ spec
 // the lane partials are merged in FP64.  COMP selects nothing else today: the
 // FP64 instantiation sums in FP64 throughout.
 template <typename T, bool COMP, int TR>
-__global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
+__device__ __forceinline__ void e3_body(T *__restrict__ spec, const Geo &g)
 {
     constexpr int SU = 64 / TR;
     constexpr int HP = 16 * SU + 32;
@@ -963,6 +996,20 @@ __global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
             }
         }
     }
+}
+
+template <typename T, bool COMP, int TR>
+__global__ void __launch_bounds__(kThreads) k_e3(T *__restrict__ spec, Geo g)
+{
+    e3_body<T, COMP, TR>(spec, g);
+}
+// Batched direct window: instance blockIdx.z
+template <typename T, bool COMP, int TR>
+__global__ void __launch_bounds__(kThreads) k_e3_batch(const EvenInst *__restrict__ in)
+{
+    const EvenInst &d = in[blockIdx.z];
+    const Geo g = d.g;
+    e3_body<T, COMP, TR>((T *)d.spec, g);
 }
 
 // Energy window (even) on the matrix cores.  The same convolution
@@ -1128,7 +1175,6 @@ __device__ __forceinline__ void e3m_some(const T *hb, const T (&b)[4], int e_lo,
         e3m_some<T, E + 1>(hb, b, e_lo, e_hi, acc);
     }
 }
-
 
 // Staging geometry of one thread: P' rows a < nA, H' rows x < nHe (at row
 // PA + 32 + x), byte offset qb of its points within the tile row, slice
@@ -1375,7 +1421,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_e3m(T *__restrict__ spec, Geo g
 // MODE 0: extended, form-factor weighted output planes; MODE 1: first-zone
 // planes (natural order) for the RPA path.
 template <typename T, int LOGNX, int MODE>
-__global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
+__device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g, const cx<T> *__restrict__ twx,
                                                 const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
@@ -1504,6 +1550,26 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
             }
         }
     }
+}
+
+template <typename T, int LOGNX, int MODE>
+__global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
+                                                const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
+                                                int ff, double ffs, const double2 *__restrict__ ffx,
+                                                const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
+                                                int out_ny, const T *__restrict__ m2, int acc)
+{
+    e5_body<T, LOGNX, MODE>(spec, g, twx, psrc, scale, zx, zy, ff, ffs, ffx, ffy, out, out_nx, out_ny, m2, acc);
+}
+// Batched P5 (extended output planes): instance blockIdx.z, its omegas
+template <typename T, int LOGNX, int MODE>
+__global__ void __launch_bounds__(kThreads) k_e5_batch(const EvenInst *__restrict__ in)
+{
+    const EvenInst &d = in[blockIdx.z];
+    const Geo g = d.g;
+    if ((int)blockIdx.y >= d.nomega) return;
+    e5_body<T, LOGNX, MODE>((const T *)d.spec, g, (const cx<T> *)d.twx, d.psrc, d.scale, d.zx, d.zy, d.ff, d.ffs,
+                            d.ffx, d.ffy, (T *)d.out, d.onx, d.ony, (const T *)nullptr, 0);
 }
 
 // First-zone value at lag m (0 outside 1 <= m < neps), and the blend
@@ -2748,7 +2814,6 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
     return hipGetLastError();
 }
 
-
 // Persistent launch of the matrix-core window: as many blocks as fit on the
 // device at once (a multiple of 8, one share per XCD), each walking tiles.
 template <typename T, int TR>
@@ -2837,6 +2902,144 @@ static hipError_t window_t(const Plan &pl, hipStream_t st)
                            st, spec, g);
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batched even path
+std::string even_group_key(const Plan &pl)
+{
+    const Geo &g = pl.g;
+    if (!g.even || g.bs || g.nkz > 1 || pl.nb > 1 || pl.pairs || pl.has_m2 || pl.p.want_rpa || g.nL == 0 ||
+        g.e3_variant == 1)
+        return std::string();
+    char b[96];
+    std::snprintf(b, sizeof b, "e%d %d %d r%d w%d %d", g.fp64, g.logNx, g.logNy, pl.rho ? 1 : 0, g.e3_variant,
+                  g.e3_variant == 2 ? 16 : g.e3_TR);
+    return b;
+}
+
+void even_group_fill(const Plan &pl, void *out, EvenInst &d)
+{
+    d.g = pl.g;
+    d.xi = pl.xi;
+    d.rho = pl.rho;
+    d.twx = pl.twx;
+    d.twy = pl.twy;
+    d.spec = pl.spec;
+    d.psrc = pl.d_src;
+    d.out = out;
+    d.ffx = pl.ffx;
+    d.ffy = pl.ffy;
+    d.emin = pl.p.emin;
+    d.deps = pl.deps;
+    d.gamma = pl.p.gamma;
+    d.scale = pl.scale;
+    d.ffs = pl.ff_s;
+    d.zx = pl.zx;
+    d.zy = pl.zy;
+    d.ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+    d.onx = pl.out_nx;
+    d.ony = pl.out_ny;
+    d.nomega = pl.p.nomega;
+}
+
+// The five passes of a group of even-path instances (equal group keys), each
+// one launch over all of them: grids cover the largest instance and blocks
+// past an instance's own extent return at once.
+template <typename T>
+static hipError_t even_group_t(const Plan *const *pls, int n, const EvenInst *d, hipStream_t st)
+{
+    const Geo &g = pls[0]->g;
+    int ys1 = 0, nS = 0, nL = 0, nw = 0;
+    size_t lds3 = 0;
+    for (int i = 0; i < n; ++i) {
+        const Geo &gi = pls[i]->g;
+        ys1 = std::max(ys1, (int)cdiv(gi.nS, gi.e1_jc));
+        nS = std::max(nS, gi.nS);
+        nL = std::max(nL, gi.nL);
+        nw = std::max(nw, pls[i]->p.nomega);
+        lds3 = std::max(lds3, (size_t)(gi.e3_PL + 16 * (64 >> gi.e3_logTR) + 32 + gi.m_lo + 16 * ((gi.nL + 15) >> 4) - 1) *
+                                  gi.e3_TR * sizeof(T));
+    }
+    const unsigned nz = (unsigned)n;
+    const int np = (g.Hy + 1) / 2;
+    const bool rho = pls[0]->rho != nullptr;
+    // P1
+#define LH_E1B(LG)                                                                                                  \
+    do {                                                                                                            \
+        using F = RegFFT<T, LG, false, ilog2_c(e1_elems(LG))>;                                                     \
+        const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);                     \
+        const dim3 grid(cdiv(np, g.e1_R), ys1, nz);                                                                 \
+        if (rho)                                                                                                    \
+            hipLaunchKernelGGL((k_e1_batch<T, LG, true>), grid, dim3(g.e1_R * F::G), lds, st, d);                   \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_e1_batch<T, LG, false>), grid, dim3(g.e1_R * F::G), lds, st, d);                  \
+    } while (0)
+    LH_SWITCH_LOG12(g.logNx, LH_E1B)
+#undef LH_E1B
+    // P2 / P4
+    auto col = [&](int ns, bool inv) -> hipError_t {
+#define LH_ECB(LG)                                                                                                  \
+    do {                                                                                                            \
+        using F = RegFFT<T, LG, false, ilog2_c(kEcolElems)>;                                                       \
+        constexpr int C = sizeof(T) == 4 ? 4 : 2;                                                                   \
+        constexpr int TPB = (F::G * C >= 256) ? 1 : 256 / (F::G * C);                                               \
+        const dim3 grid(cdiv(g.NTe, TPB), ns, nz);                                                                  \
+        const size_t lds = (size_t)TPB * C * F::N * sizeof(cx<T>) + tw_lds_bytes<T>(F::N);                         \
+        if (inv)                                                                                                    \
+            hipLaunchKernelGGL((k_ecol_batch<T, LG, true>), grid, dim3(F::G * TPB * C), lds, st, d);                \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_ecol_batch<T, LG, false>), grid, dim3(F::G * TPB * C), lds, st, d);               \
+    } while (0)
+        LH_SWITCH_LOG12(g.logNy, LH_ECB)
+#undef LH_ECB
+        return hipGetLastError();
+    };
+    LH_HIP_TRY(col(nS, false));
+    // P3
+    if (g.e3_variant == 2) {
+        if constexpr (sizeof(T) == 4) {
+            LH_HIP_TRY(launch_e3q_group(pls, n, d, st));
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        const dim3 g3(cdiv(g.slice_e, g.e3_TR), 1, nz);
+#define LH_E3B(TRV)                                                                                                 \
+    do {                                                                                                            \
+        if (g.fp64)                                                                                                 \
+            hipLaunchKernelGGL((k_e3_batch<T, false, TRV>), g3, dim3(kThreads), lds3, st, d);                       \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_e3_batch<T, true, TRV>), g3, dim3(kThreads), lds3, st, d);                        \
+    } while (0)
+        switch (g.e3_TR) {
+        case 64: LH_E3B(64); break;
+        case 32: LH_E3B(32); break;
+        case 16: LH_E3B(16); break;
+        case 8: LH_E3B(8); break;
+        case 4: LH_E3B(4); break;
+        case 2: LH_E3B(2); break;
+        default: LH_E3B(1); break;
+        }
+#undef LH_E3B
+        LH_HIP_TRY(hipGetLastError());
+    }
+    LH_HIP_TRY(col(nL, true));
+    // P5
+#define LH_E5B(LG)                                                                                                  \
+    do {                                                                                                            \
+        using F = RegFFT<T, LG, true>;                                                                              \
+        const dim3 grid(cdiv(np, g.e5_R), nw, nz);                                                                  \
+        hipLaunchKernelGGL((k_e5_batch<T, LG, 0>), grid, dim3(g.e5_R * F::G),                                       \
+                           (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, d);              \
+    } while (0)
+    LH_SWITCH_LOG12(g.logNx, LH_E5B)
+#undef LH_E5B
+    return hipGetLastError();
+}
+
+hipError_t launch_even_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st)
+{
+    return pls[0]->g.fp64 ? even_group_t<double>(pls, n, d_desc, st) : even_group_t<float>(pls, n, d_desc, st);
 }
 
 hipError_t launch_window(const Plan &pl, hipStream_t st)

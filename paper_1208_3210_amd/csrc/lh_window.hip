@@ -89,7 +89,7 @@ __device__ __forceinline__ f4v buf_load4(__amdgpu_buffer_rsrc_t r, unsigned off)
 // offsets, so the block uses 64-bit addresses (flat loads and stores) instead
 // of buffer descriptors.
 template <bool BIG>
-__global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, Geo g)
+__device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int PSP = g.e3q_PSP, PSH = g.e3q_PSH, LP = g.e3q_LP, LH = g.e3q_LH;
@@ -284,6 +284,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, G
     }
 }
 
+template <bool BIG>
+__global__ void __launch_bounds__(64 * kWaves) k_e3q(float *__restrict__ spec, Geo g)
+{
+    e3q_body<BIG>(spec, g);
+}
+// Batched form: instance blockIdx.z of the descriptors
+template <bool BIG>
+__global__ void __launch_bounds__(64 * kWaves) k_e3q_batch(const EvenInst *__restrict__ in)
+{
+    const EvenInst &d = in[blockIdx.z];
+    const Geo g = d.g;
+    e3q_body<BIG>((float *)d.spec, g);
+}
+
 }  // namespace
 
 // LDS bytes of one block (16 points).
@@ -300,6 +314,24 @@ hipError_t launch_e3q(const Plan &pl, int, hipStream_t st)
         hipLaunchKernelGGL(k_e3q<true>, grid, dim3(64 * kWaves), e3q_lds_bytes(g, 1), st, (float *)pl.spec, g);
     else
         hipLaunchKernelGGL(k_e3q<false>, grid, dim3(64 * kWaves), e3q_lds_bytes(g, 1), st, (float *)pl.spec, g);
+    return hipGetLastError();
+}
+
+// The window of a batched group (all with this schedule and grid): one launch,
+// the LDS of its largest instance, 64-bit addressing if any instance needs it.
+hipError_t launch_e3q_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st)
+{
+    size_t lds = 0;
+    bool big = false;
+    for (int i = 0; i < n; ++i) {
+        lds = std::max(lds, e3q_lds_bytes(pls[i]->g, 1));
+        big = big || pls[i]->g.e3q_big;
+    }
+    const dim3 grid((unsigned)((pls[0]->g.slice_e + kPoints - 1) / kPoints), 1, (unsigned)n);
+    if (big)
+        hipLaunchKernelGGL(k_e3q_batch<true>, grid, dim3(64 * kWaves), lds, st, d_desc);
+    else
+        hipLaunchKernelGGL(k_e3q_batch<false>, grid, dim3(64 * kWaves), lds, st, d_desc);
     return hipGetLastError();
 }
 

@@ -255,3 +255,40 @@ def test_warm_problems_and_eviction():
     for pr, (t, outs) in zip(probs, tickets):
         assert torch.equal(outs["im_chi"], run_alone(float("nan"), pr)["im_chi"]), t
     srv.close()
+
+
+@pytest.mark.parametrize("window", ["mfma4", "direct"])
+def test_grouped_batch_launches_equal_alone(window, monkeypatch):
+    """Instances of one grid run each pass as one launch over the group (the
+    grid spans the largest instance; smaller ones return early): energies,
+    lag ranges, bands, fillings and broadenings differ inside a group, and
+    each result equals the instance run alone, bit for bit.  Also with a
+    group of FP64 instances and one instance that is batched on its own."""
+    monkeypatch.setenv("LINDHARD_EVEN_WINDOW", window)
+    e0, e1 = -2.0, 2.0
+    probs = []
+    for i, (nk, neps, lags, prec) in enumerate([
+            (64, 64, range(1, 33), LH.LINDHARD_FP32C), (64, 128, range(1, 50), LH.LINDHARD_FP32C),
+            (64, 128, range(5, 20), LH.LINDHARD_FP32C), (64, 256, range(1, 120, 3), LH.LINDHARD_FP32C),
+            (128, 64, range(1, 17), LH.LINDHARD_FP32C), (128, 128, range(1, 65), LH.LINDHARD_FP32C),
+            (64, 64, range(1, 33), LH.LINDHARD_FP64), (64, 128, range(2, 40, 2), LH.LINDHARD_FP64),
+            (32, 64, range(1, 9), LH.LINDHARD_FP32C)]):
+        band = W.seeded_band(np.random.Generator(np.random.PCG64(100 + i)))
+        probs.append(dict(**band, filling=1.02 + 0.02 * i, gamma=0.02 + 0.005 * i, nkx=nk, nky=nk, neps=neps,
+                          emin=e0, emax=e1, omega=W.lag_omegas(neps, e0, e1, lags), precision=prec,
+                          zones=(3, 1) if i == 1 else (1, 1)))
+    plans = [LH.Plan(**p) for p in probs]
+    alone = [p.exec() for p in plans]
+    torch.cuda.synchronize()
+    for dt in (torch.float32, torch.float64):
+        group = [(p, a) for p, a in zip(plans, alone) if p.dtype == dt]
+        outs = [p.empty() for p, _ in group]
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))
+            LH.exec_batch([p for p, _ in group], outs)
+            torch.cuda.synchronize()
+            for o, (_, a) in zip(outs, group):
+                assert torch.equal(o, a), rep
+    for p in plans:
+        p.close()
