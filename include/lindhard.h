@@ -296,12 +296,20 @@ typedef struct {
 lindhard_status lindhard_zone_envelope(lindhard_plan_t plan, const void *im, int32_t omega_index, int32_t direction,
                                        double q_scale, lindhard_envelope *out, void *stream);
 
-/* Run n independent plans as one batch ordered on `stream`: the instances
- * are forked onto a pool of worker streams (largest first, round-robin) so
- * that instances of mixed grid sizes overlap on the device, and joined back
- * into `stream` before any later work on it.  outs[i] as in lindhard_exec.
- * All plans must live on the same device; one batch runs at a time per
- * process.  Errors: EINVAL, EDEVICE. */
+/* Run n independent plans as one batch ordered on `stream` (the batched
+ * form of the hot path: many dopings, broadenings and grid sizes at once).
+ * Instances on the mirror-symmetric (even) path with the same precision,
+ * grid, momentum-density use and window schedule form a group, and each of
+ * the five passes runs as ONE launch over the whole group (per-instance
+ * descriptors in device memory; energies, omega lists, bands, fillings and
+ * broadenings may differ inside a group).  Groups and the remaining
+ * instances are forked onto a pool of worker streams (largest first) so
+ * that work of mixed grid sizes overlaps, and joined back into `stream`
+ * before any later work on it.  The sequence is captured into a HIP graph
+ * on the first call and replayed for the same plans and outputs.  Each
+ * output equals that of lindhard_exec on its plan, bit for bit.  outs[i] as
+ * in lindhard_exec; no plan twice.  All plans must live on the same device;
+ * one batch runs at a time per process.  Errors: EINVAL, EDEVICE. */
 lindhard_status lindhard_exec_batch(const lindhard_plan_t *plans, int32_t n, void *const *outs,
                                     void *stream);
 
@@ -334,6 +342,7 @@ typedef struct {
     uint64_t plan_evictions; /* idle plans freed to make room */
     int32_t cached_plans;    /* idle plans held right now */
     size_t resident_bytes;   /* device memory held by the server's plans right now */
+    uint64_t merged_jobs;    /* jobs that ran together with others of their class */
 } lindhard_serve_stats;
 
 /* Start a server.  Worker threads (max_inflight of them, each with a stream
@@ -347,8 +356,11 @@ typedef struct {
  * omegas; buffers grow when its lag range needs more), so it neither builds
  * tables nor times window schedules; only a job of a new class plans from
  * scratch.  Idle plans are freed, least recently used first, when a job
- * needs their memory.  A job's result equals that of lindhard_plan +
- * lindhard_exec (+ lindhard_rpa) on its problem, bit for bit.
+ * needs their memory.  A worker that admits a job also takes queued jobs of
+ * its class behind it (up to 8, within the budget): those on the even path
+ * with the same window schedule run every pass as one launch over all of
+ * them, as lindhard_exec_batch does.  A job's result equals that of
+ * lindhard_plan + lindhard_exec (+ lindhard_rpa) on its problem, bit for bit.
  * Errors: EINVAL, ENOMEM, EDEVICE, or the planning status of a warm problem. */
 lindhard_status lindhard_serve_create(const lindhard_serve_config *cfg, lindhard_server_t *out);
 

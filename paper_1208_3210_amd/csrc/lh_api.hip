@@ -1244,6 +1244,29 @@ lindhard_status plan_rebind(lindhard_plan_t plan, const lindhard_problem *p, hip
     return LINDHARD_OK;
 }
 
+// Run plans of one even-path group (equal even_group_key) as one launch per
+// pass on st: their descriptors are staged in host (kept by the caller until
+// the work completes) and copied to d_desc (room for n).
+hipError_t plan_exec_group(const lindhard_plan_t *plans, int n, void *const *outs, EvenInst *d_desc,
+                           std::vector<EvenInst> &host, hipStream_t st)
+{
+    host.resize(n);
+    std::vector<const Plan *> pls(n);
+    for (int i = 0; i < n; ++i) {
+        even_group_fill(plans[i]->pl, outs[i], host[i]);
+        pls[i] = &plans[i]->pl;
+    }
+    hipError_t e = hipMemcpyAsync(d_desc, host.data(), n * sizeof(EvenInst), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_even_group(pls.data(), n, d_desc, st);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipEventRecord(plans[i]->done, st);
+        plans[i]->pl.executed = true;
+    }
+    return e;
+}
+
+const Plan &plan_of(lindhard_plan_t plan) { return plan->pl; }
+
 }  // namespace lh
 
 extern "C" {

@@ -194,6 +194,7 @@ const std::string &plan_key(lindhard_plan_t plan);
 std::vector<size_t> plan_capacity(lindhard_plan_t plan);
 size_t plan_resident_bytes(lindhard_plan_t plan);
 lindhard_status plan_rebind(lindhard_plan_t plan, const lindhard_problem *p, hipStream_t st);
+const Plan &plan_of(lindhard_plan_t plan);
 // Allocate device memory, build band / mu / tables.  Synchronous on `st`.
 lindhard_status plan_build(Plan &pl, hipStream_t st);
 void plan_free(Plan &pl);
@@ -227,6 +228,8 @@ std::string even_group_key(const Plan &pl);
 void even_group_fill(const Plan &pl, void *out, EvenInst &d);
 hipError_t launch_even_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st);
 hipError_t launch_e3q_group(const Plan *const *pls, int n, const EvenInst *d_desc, hipStream_t st);
+hipError_t plan_exec_group(const lindhard_plan_t *plans, int n, void *const *outs, EvenInst *d_desc,
+                           std::vector<EvenInst> &host, hipStream_t st);
 
 // Setup kernels.
 hipError_t launch_band(const Plan &pl, const double *d_table, hipStream_t st);

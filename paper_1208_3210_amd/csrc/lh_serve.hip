@@ -61,15 +61,21 @@ struct Cached {
     uint64_t last_use = 0;
 };
 
-// What a worker took from the queue: the job, the cached plan it runs on (or
-// none: plan from scratch), the bytes accounted for it, and idle plans that
-// were evicted to make room (freed by the worker outside the lock).
-struct Admit {
+// What a worker took from the queue: jobs of one class, each with the cached
+// plan it runs on (or none: plan from scratch) and the bytes accounted for it,
+// and idle plans that were evicted to make room (freed by the worker outside
+// the lock).
+struct Taken {
     std::shared_ptr<Job> job;
     lindhard_plan_t plan = nullptr;
     size_t reserved = 0;
+};
+struct Admit {
+    std::vector<Taken> taken;
     std::vector<lindhard_plan_t> drop;
 };
+
+constexpr int kMergeMax = 8;  // jobs of one class a worker takes at once
 
 // Bytes a cached plan must grow by to hold a job.
 size_t growth(const std::vector<size_t> &cap, const std::vector<size_t> &need)
@@ -92,12 +98,13 @@ struct lindhard_server_s {
     std::unordered_map<std::string, std::vector<Cached>> idle;  // class -> idle plans
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
+    std::vector<EvenInst *> desc;  // per worker: descriptors of a grouped launch (kMergeMax)
     uint64_t next_id = 1, use_clock = 0;
     size_t resident = 0, idle_bytes = 0, high_water = 0;  // bytes of all plans held / of the idle ones
     int inflight = 0, n_idle = 0;
     bool stop = false;
     uint64_t submitted = 0, completed = 0, failed = 0, rejected = 0, canceled = 0;
-    uint64_t reuses = 0, builds = 0, evictions = 0;
+    uint64_t reuses = 0, builds = 0, evictions = 0, merged = 0;
     double points_done = 0.0;
     std::vector<double> lat_ms;  // ring of the last kLatencyWindow latencies
     size_t lat_next = 0;
@@ -128,11 +135,11 @@ static bool evict_lru(lindhard_server_s *S, std::vector<lindhard_plan_t> &drop)
     return true;
 }
 
-// Try to admit the head of the queue (caller holds the lock).
-static bool try_admit(lindhard_server_s *S, Admit &a)
+// Try to admit queued job qi (caller holds the lock); on success it leaves the
+// queue and joins a.taken.
+static bool admit_job(lindhard_server_s *S, size_t qi, Admit &a)
 {
-    if (S->queue.empty()) return false;
-    const std::shared_ptr<Job> &h = S->queue.front();
+    const std::shared_ptr<Job> h = S->queue[qi];
     const size_t budget = S->cfg.hbm_budget_bytes;
     // the idle plan of the job's class that needs the least growth (the most
     // recently used among equals)
@@ -154,6 +161,8 @@ static bool try_admit(lindhard_server_s *S, Admit &a)
         reuse = S->resident - other_idle + pick_grow <= budget;
     }
     if (!reuse && S->resident - S->idle_bytes + h->footprint > budget) return false;
+    Taken t;
+    t.job = h;
     if (reuse) {
         const Cached c = it->second[pick];
         it->second.erase(it->second.begin() + pick);
@@ -161,28 +170,45 @@ static bool try_admit(lindhard_server_s *S, Admit &a)
         S->n_idle -= 1;
         while (S->resident + pick_grow > budget && evict_lru(S, a.drop)) {
         }
-        a.plan = c.plan;
-        a.reserved = c.bytes + pick_grow;
+        t.plan = c.plan;
+        t.reserved = c.bytes + pick_grow;
         S->resident += pick_grow;
         S->reuses += 1;
     } else {
         while (S->resident + h->footprint > budget && evict_lru(S, a.drop)) {
         }
-        a.plan = nullptr;
-        a.reserved = h->footprint;
+        t.plan = nullptr;
+        t.reserved = h->footprint;
         S->resident += h->footprint;
     }
     S->high_water = std::max(S->high_water, S->resident);
-    a.job = h;
-    S->queue.pop_front();
-    a.job->state = 1;
+    S->queue.erase(S->queue.begin() + qi);
+    h->state = 1;
     S->inflight += 1;
+    a.taken.push_back(t);
     return true;
 }
 
-// Plan (or rebind) and run one job on stream st; *plan holds the plan
-// afterwards (nullptr if planning failed).
-static lindhard_status run_job(lindhard_server_s *S, Job &j, lindhard_plan_t *plan, hipStream_t st)
+// Admit the head of the queue and, behind it, further queued jobs of its
+// class that fit (up to kMergeMax in all): they run together, the passes of
+// those that can be grouped as one launch each.
+static bool try_admit(lindhard_server_s *S, Admit &a)
+{
+    if (S->queue.empty() || !admit_job(S, 0, a)) return false;
+    const std::string &key = a.taken[0].job->key;
+    for (size_t qi = 0; qi < S->queue.size() && (int)a.taken.size() < kMergeMax;) {
+        if (S->queue[qi]->key != key) {
+            ++qi;
+            continue;
+        }
+        if (!admit_job(S, qi, a)) break;
+    }
+    return true;
+}
+
+// Plan (or rebind) one job on stream st; *plan holds the plan afterwards
+// (nullptr if planning failed).
+static lindhard_status prepare_job(lindhard_server_s *S, Job &j, lindhard_plan_t *plan, hipStream_t st)
 {
     lindhard_problem p = j.p;
     p.omega = j.omega.data();
@@ -198,9 +224,6 @@ static lindhard_status run_job(lindhard_server_s *S, Job &j, lindhard_plan_t *pl
         std::lock_guard<std::mutex> lk(S->mu);
         S->builds += 1;
     }
-    if (s == LINDHARD_OK) s = lindhard_exec(*plan, j.im, st);
-    if (s == LINDHARD_OK && std::isfinite(j.U)) s = lindhard_rpa(*plan, j.U, j.re, j.imr, j.rer, st);
-    if (hipStreamSynchronize(st) != hipSuccess && s == LINDHARD_OK) s = LINDHARD_EDEVICE;
     // the inputs are no longer needed
     std::vector<double>().swap(j.omega);
     std::vector<double>().swap(j.table);
@@ -210,50 +233,105 @@ static lindhard_status run_job(lindhard_server_s *S, Job &j, lindhard_plan_t *pl
     return s;
 }
 
+// Plan and run the jobs a worker took: the even-path ones that share a group
+// key as one launch per pass, the others one by one; then the RPA epilogues.
+static void run_jobs(lindhard_server_s *S, std::vector<Taken> &tk, std::vector<lindhard_status> &st_out,
+                     EvenInst *d_desc, hipStream_t st)
+{
+    const size_t n = tk.size();
+    st_out.assign(n, LINDHARD_OK);
+    for (size_t i = 0; i < n; ++i) st_out[i] = prepare_job(S, *tk[i].job, &tk[i].plan, st);
+    std::vector<std::string> gkey(n);
+    for (size_t i = 0; i < n; ++i)
+        if (st_out[i] == LINDHARD_OK) gkey[i] = even_group_key(plan_of(tk[i].plan));
+    std::vector<bool> done(n, false);
+    std::vector<EvenInst> host;
+    for (size_t i = 0; i < n; ++i) {
+        if (st_out[i] != LINDHARD_OK || done[i] || gkey[i].empty()) continue;
+        std::vector<lindhard_plan_t> plans;
+        std::vector<void *> outs;
+        std::vector<size_t> who;
+        for (size_t k = i; k < n; ++k)
+            if (st_out[k] == LINDHARD_OK && !done[k] && gkey[k] == gkey[i]) {
+                plans.push_back(tk[k].plan);
+                outs.push_back(tk[k].job->im);
+                who.push_back(k);
+            }
+        if (plans.size() < 2) continue;
+        const hipError_t e = plan_exec_group(plans.data(), (int)plans.size(), outs.data(), d_desc, host, st);
+        for (size_t k : who) {
+            done[k] = true;
+            if (e != hipSuccess) st_out[k] = LINDHARD_EDEVICE;
+        }
+        // one group per merge: its descriptors are in use until the stream drains
+        break;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        Job &j = *tk[i].job;
+        if (st_out[i] != LINDHARD_OK) continue;
+        if (!done[i]) st_out[i] = lindhard_exec(tk[i].plan, j.im, st);
+        if (st_out[i] == LINDHARD_OK && std::isfinite(j.U)) st_out[i] = lindhard_rpa(tk[i].plan, j.U, j.re, j.imr, j.rer, st);
+    }
+    const bool ok = hipStreamSynchronize(st) == hipSuccess;
+    for (size_t i = 0; i < n; ++i)
+        if (!ok && st_out[i] == LINDHARD_OK) st_out[i] = LINDHARD_EDEVICE;
+}
+
 static void worker_loop(lindhard_server_s *S, int w)
 {
     (void)hipSetDevice(S->device);
     hipStream_t st = S->streams[w];
+    EvenInst *d_desc = S->desc[w];
+    std::vector<lindhard_status> status;
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         Admit a;
         S->cv_work.wait(lk, [&] { return (S->stop && S->queue.empty()) || try_admit(S, a); });
-        if (!a.job) return;
+        if (a.taken.empty()) return;
         lk.unlock();
         S->cv_work.notify_all();
         for (lindhard_plan_t q : a.drop) lindhard_plan_destroy(q);
 
-        lindhard_plan_t plan = a.plan;
-        const lindhard_status s = run_job(S, *a.job, &plan, st);
-        const bool keep = s == LINDHARD_OK && plan;
-        const size_t bytes = keep ? plan_resident_bytes(plan) : 0;
-        if (!keep && plan) lindhard_plan_destroy(plan);
+        run_jobs(S, a.taken, status, d_desc, st);
+        std::vector<size_t> bytes(a.taken.size(), 0);
+        for (size_t i = 0; i < a.taken.size(); ++i) {
+            lindhard_plan_t plan = a.taken[i].plan;
+            if (status[i] == LINDHARD_OK && plan)
+                bytes[i] = plan_resident_bytes(plan);
+            else if (plan)
+                lindhard_plan_destroy(plan);
+        }
 
         lk.lock();
-        Job &job = *a.job;
-        job.t_done = Clock::now();
-        job.status = s;
-        job.state = 2;
-        S->inflight -= 1;
-        S->resident = S->resident - a.reserved + bytes;
+        const Clock::time_point now = Clock::now();
+        for (size_t i = 0; i < a.taken.size(); ++i) {
+            Job &job = *a.taken[i].job;
+            const lindhard_status s = status[i];
+            job.t_done = now;
+            job.status = s;
+            job.state = 2;
+            S->inflight -= 1;
+            S->resident = S->resident - a.taken[i].reserved + bytes[i];
+            if (s == LINDHARD_OK && a.taken[i].plan) {
+                S->idle[job.key].push_back({a.taken[i].plan, bytes[i], ++S->use_clock});
+                S->idle_bytes += bytes[i];
+                S->n_idle += 1;
+            }
+            if (s == LINDHARD_OK) {
+                S->completed += 1;
+                S->points_done += (double)job.points;
+                const double ms = std::chrono::duration<double, std::milli>(job.t_done - job.t_submit).count();
+                if (S->lat_ms.size() < kLatencyWindow)
+                    S->lat_ms.push_back(ms);
+                else
+                    S->lat_ms[S->lat_next] = ms;
+                S->lat_next = (S->lat_next + 1) % kLatencyWindow;
+            } else {
+                S->failed += 1;
+            }
+        }
+        if (a.taken.size() > 1) S->merged += a.taken.size();
         S->high_water = std::max(S->high_water, S->resident);
-        if (keep) {
-            S->idle[job.key].push_back({plan, bytes, ++S->use_clock});
-            S->idle_bytes += bytes;
-            S->n_idle += 1;
-        }
-        if (s == LINDHARD_OK) {
-            S->completed += 1;
-            S->points_done += (double)job.points;
-            const double ms = std::chrono::duration<double, std::milli>(job.t_done - job.t_submit).count();
-            if (S->lat_ms.size() < kLatencyWindow)
-                S->lat_ms.push_back(ms);
-            else
-                S->lat_ms[S->lat_next] = ms;
-            S->lat_next = (S->lat_next + 1) % kLatencyWindow;
-        } else {
-            S->failed += 1;
-        }
         S->cv_done.notify_all();
         S->cv_work.notify_all();
     }
@@ -286,6 +364,8 @@ static void destroy_server(lindhard_server_s *S)
         for (const Cached &c : kv.second) lindhard_plan_destroy(c.plan);
     for (auto &st : S->streams)
         if (st) (void)hipStreamDestroy(st);
+    for (EvenInst *d : S->desc)
+        if (d) (void)hipFree(d);
     delete S;
 }
 
@@ -307,11 +387,12 @@ lindhard_status lindhard_serve_create(const lindhard_serve_config *cfg, lindhard
         return LINDHARD_EDEVICE;
     }
     S->streams.resize(cfg->max_inflight, nullptr);
-    for (auto &st : S->streams) {
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (auto &s2 : S->streams)
-                if (s2) (void)hipStreamDestroy(s2);
-            delete S;
+    S->desc.resize(cfg->max_inflight, nullptr);
+    for (int w = 0; w < cfg->max_inflight; ++w) {
+        if (hipStreamCreateWithFlags(&S->streams[w], hipStreamNonBlocking) != hipSuccess ||
+            hipMalloc((void **)&S->desc[w], kMergeMax * sizeof(EvenInst)) != hipSuccess) {
+            (void)hipGetLastError();
+            destroy_server(S);
             return LINDHARD_EDEVICE;
         }
     }
@@ -475,6 +556,7 @@ lindhard_status lindhard_serve_stats_get(lindhard_server_t S, lindhard_serve_sta
         o->plan_evictions = S->evictions;
         o->cached_plans = S->n_idle;
         o->resident_bytes = S->resident;
+        o->merged_jobs = S->merged;
         v = S->lat_ms;
     }
     if (!v.empty()) {

@@ -86,7 +86,7 @@ class ServeStats(ctypes.Structure):
         ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("points_per_s", ctypes.c_double),
         ("hbm_high_water", ctypes.c_size_t), ("queue_depth", ctypes.c_int32), ("inflight", ctypes.c_int32),
         ("plan_reuses", ctypes.c_uint64), ("plan_builds", ctypes.c_uint64), ("plan_evictions", ctypes.c_uint64),
-        ("cached_plans", ctypes.c_int32), ("resident_bytes", ctypes.c_size_t),
+        ("cached_plans", ctypes.c_int32), ("resident_bytes", ctypes.c_size_t), ("merged_jobs", ctypes.c_uint64),
     ]
 
 

@@ -200,12 +200,13 @@ def test_cached_plans_rebound_across_lag_ranges_equal_alone():
                            omega=W.lag_omegas(neps, e0, e1, range(1, 33)), precision=LH.LINDHARD_FP32C)))
     jobs.append((1.3, dict(**_tb(10), nkx=64, nky=64, neps=neps, emin=e0, emax=e1,
                            omega=W.lag_omegas(neps, e0, e1, range(2, 50, 3)), precision=LH.LINDHARD_FP32C)))
-    # one worker: the jobs run in order, each on the plan its predecessor of
-    # the class left behind
+    # one worker, one job at a time (no merging): each runs on the plan its
+    # predecessor of the class left behind
     srv = LH.Server(hbm_budget_bytes=4 << 30, max_inflight=1, max_queue=64)
-    tickets = [srv.submit(U, **prob) for U, prob in jobs]
-    for t, _ in tickets:
-        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    tickets = []
+    for U, prob in jobs:
+        tickets.append(srv.submit(U, **prob))
+        assert srv.wait(tickets[-1][0], 120.0) == LH.LINDHARD_OK
     st = srv.stats()
     assert st.plan_builds == 3 and st.plan_reuses == len(jobs) - 3, (st.plan_builds, st.plan_reuses)
     assert st.cached_plans == 3 and st.resident_bytes <= st.hbm_high_water <= 4 << 30
@@ -247,9 +248,10 @@ def test_warm_problems_and_eviction():
         p.close()
     budget = int(max(fps) * 1.3)
     srv = LH.Server(hbm_budget_bytes=budget, max_inflight=1, max_queue=16)
-    tickets = [srv.submit(float("nan"), **pr) for pr in probs]
-    for t, _ in tickets:
-        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    tickets = []
+    for pr in probs:
+        tickets.append(srv.submit(float("nan"), **pr))
+        assert srv.wait(tickets[-1][0], 120.0) == LH.LINDHARD_OK
     st = srv.stats()
     assert st.plan_evictions == 2 and st.plan_builds == 3 and st.hbm_high_water <= budget
     for pr, (t, outs) in zip(probs, tickets):
@@ -292,3 +294,26 @@ def test_grouped_batch_launches_equal_alone(window, monkeypatch):
                 assert torch.equal(o, a), rep
     for p in plans:
         p.close()
+
+
+def test_queued_jobs_of_one_class_run_merged_and_equal_alone():
+    """A burst of jobs of one class queued behind a busy worker is taken
+    together and run as grouped launches (the server counts them as merged);
+    every result equals the job run alone, bit for bit."""
+    e0, e1, neps = -2.0, 2.0, 128
+    probs = []
+    for i in range(10):
+        band = W.seeded_band(np.random.Generator(np.random.PCG64(300 + i)))
+        lags = range(1, 17 + 3 * i)
+        probs.append(dict(**band, filling=1.0 + 0.015 * i, gamma=0.03 + 0.004 * i, nkx=128, nky=128, neps=neps,
+                          emin=e0, emax=e1, omega=W.lag_omegas(neps, e0, e1, lags), precision=LH.LINDHARD_FP32C))
+    srv = LH.Server(hbm_budget_bytes=8 << 30, max_inflight=1, max_queue=64)
+    tickets = [srv.submit(float("nan"), **p) for p in probs]
+    for t, _ in tickets:
+        assert srv.wait(t, 120.0) == LH.LINDHARD_OK
+    st = srv.stats()
+    print("merged %d of %d, builds %d reuses %d" % (st.merged_jobs, len(probs), st.plan_builds, st.plan_reuses))
+    assert st.merged_jobs >= 2 and st.completed == len(probs)
+    for p, (t, outs) in zip(probs, tickets):
+        assert torch.equal(outs["im_chi"], run_alone(float("nan"), p)["im_chi"]), t
+    srv.close()
