@@ -209,7 +209,7 @@ def bench_served(LH, W, torch, n_warm=200, n_req=2000, rate_hz=200.0, n_iso=400)
             "served_over_isolated_p50": pc(ratio, 50), "served_over_isolated_p99": pc(ratio, 99),
             "points_per_s": done_points / wall, "completed": int(st.completed), "failed": int(st.failed),
             "plan_builds": int(st.plan_builds), "plan_reuses": int(st.plan_reuses),
-            "plan_evictions": int(st.plan_evictions), "warm_classes_s": t_create,
+            "plan_evictions": int(st.plan_evictions), "merged_jobs": int(st.merged_jobs), "warm_classes_s": t_create,
             "hbm_high_water_GB": st2.hbm_high_water / 1e9, "max_inflight": 8,
             "latency_note": "submit -> result ready, host clock, requests after warm-up; isolated: the same "
                             "jobs one at a time on the warm server"}
