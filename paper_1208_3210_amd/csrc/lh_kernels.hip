@@ -1629,9 +1629,10 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
 // for every needed lag, with FP64 products and sums (v_mfma_f64_16x16x4f64).
 // The weights vanish unless j - lag is odd, so the lags come in tiles of 16
 // of one parity and a tile sums over the 16 energies of the other parity in
-// each chunk of 32.  Block: four waves (one lag tile each) and 128 q; the
-// chunk of Im (32 energies x 128 q) is staged through LDS and shared by the
-// tiles, the next chunk's loads in flight while the current one is summed.
+// each chunk of 32.  Block: WV waves (one lag tile each; eight when there are
+// more than four tiles, so that Im is read once for up to 128 lags) and 128 q;
+// the chunk of Im (32 energies x 128 q) is staged through LDS and shared by
+// the tiles, the next chunk's loads in flight while the current one is summed.
 // Per step of 4 energies a wave loads its 16 x 4 weights (one double per
 // lane, contiguous) and issues eight MFMAs, one per 16 q.
 //   MFMA operands: lane l holds A[l % 16][l / 16] (lag row, energy) and
@@ -1640,16 +1641,17 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
 typedef double lh_d4 __attribute__((ext_vector_type(4)));
 constexpr int kKkQ = 128;            // q per block
 constexpr int kKkStride = kKkQ + 8;  // LDS row stride (energies two apart land 16 banks apart)
-template <typename T>
-__global__ void __launch_bounds__(256) k_kkm(const T *__restrict__ im1, int nk, int neps,
-                                            const double *__restrict__ w, const int2 *__restrict__ rows,
-                                            int ntiles, int nch, T *__restrict__ re1)
+template <typename T, int WV>
+__global__ void __launch_bounds__(64 * WV) k_kkm(const T *__restrict__ im1, int nk, int neps,
+                                                const double *__restrict__ w, const int2 *__restrict__ rows,
+                                                int ntiles, int nch, T *__restrict__ re1)
 {
     __shared__ __align__(16) T tile[32 * kKkStride];
+    constexpr int NT = 64 * WV;                     // threads
     constexpr int VEC = 16 / sizeof(T);             // values per 16-byte load
-    constexpr int NV = 32 * kKkQ / VEC / 256;       // loads per thread per chunk
+    constexpr int NV = 32 * kKkQ / VEC / NT;        // loads per thread per chunk
     const int tid = threadIdx.x, lane = tid & 63;
-    const int t = blockIdx.y * 4 + (tid >> 6);     // this wave's lag tile
+    const int t = blockIdx.y * WV + (tid >> 6);    // this wave's lag tile
     const bool active = t < ntiles;
     const long q0 = (long)blockIdx.x * kKkQ;
     const int par = active ? (rows[t * 16].x & 1) : 0;
@@ -1658,7 +1660,7 @@ __global__ void __launch_bounds__(256) k_kkm(const T *__restrict__ im1, int nk, 
     auto load = [&](int c, Vec16<T> *v) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const int idx = tid + k * 256, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
+            const int idx = tid + k * NT, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
             const int j = 32 * c + e;
             if (j < neps && q0 + qv < nk)
                 v[k] = *reinterpret_cast<const Vec16<T> *>(im1 + (size_t)j * nk + q0 + qv);
@@ -1670,7 +1672,7 @@ __global__ void __launch_bounds__(256) k_kkm(const T *__restrict__ im1, int nk, 
     auto store = [&](const Vec16<T> *v) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const int idx = tid + k * 256, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
+            const int idx = tid + k * NT, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
             *reinterpret_cast<Vec16<T> *>(&tile[e * kKkStride + qv]) = v[k];
         }
     };
@@ -3057,8 +3059,12 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
 {
     const Geo &g = pl.g;
     const int nk = g.nkx * g.nky;
-    hipLaunchKernelGGL(k_kkm<T>, dim3(cdiv(nk, kKkQ), cdiv(pl.kk_ntiles, 4)), dim3(256), 0, st, (const T *)pl.im1, nk,
-                       g.neps, pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
+    if (pl.kk_ntiles > 4)
+        hipLaunchKernelGGL((k_kkm<T, 8>), dim3(cdiv(nk, kKkQ), cdiv(pl.kk_ntiles, 8)), dim3(512), 0, st,
+                           (const T *)pl.im1, nk, g.neps, pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
+    else
+        hipLaunchKernelGGL((k_kkm<T, 4>), dim3(cdiv(nk, kKkQ), 1), dim3(256), 0, st, (const T *)pl.im1, nk, g.neps,
+                           pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
                        (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.d_kkslot,
