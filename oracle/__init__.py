@@ -286,25 +286,28 @@ def rpa(re_chi, im_chi, U: float):
     return r.imag, r.real
 
 
-def coulomb_v(hx, hy, v: float) -> np.ndarray:
+def coulomb_v(hx, hy, v: float, hz: float = 0.0) -> np.ndarray:
     """Coulomb interaction V(Q) = v / |Q|^2 on the extended grid, the form
     the paper gives for the RPA denominator (Sec. 4: V_q decays as 1/q^2),
-    with Q = 2 pi (h, l) in units of 1/a (h, l in reciprocal-lattice units,
-    see ``zone_axis``).  Shape (len(hy), len(hx)); +inf at Q = 0."""
+    with Q = 2 pi (h, l, hz) in units of 1/a (h, l in reciprocal-lattice units,
+    see ``zone_axis``; hz that of a kz plane of a three-dimensional grid, the
+    lattice constant along z taken as a).  Shape (len(hy), len(hx)); +inf at
+    Q = 0."""
     hx = np.asarray(hx, dtype=np.float64)
     hy = np.asarray(hy, dtype=np.float64)
-    q2 = (2.0 * np.pi) ** 2 * (hx[None, :] ** 2 + hy[:, None] ** 2)
+    q2 = (2.0 * np.pi) ** 2 * (hx[None, :] ** 2 + hy[:, None] ** 2 + float(hz) ** 2)
     with np.errstate(divide="ignore"):
         return np.where(q2 > 0.0, v / np.where(q2 > 0.0, q2, 1.0), np.inf)
 
 
-def rpa_coulomb(re_chi, im_chi, hx, hy, v: float):
+def rpa_coulomb(re_chi, im_chi, hx, hy, v: float, hz: float = 0.0):
     """chi_RPA = chi / (1 - V(Q) chi) with the Coulomb V of ``coulomb_v``,
     diagonal in G (no local fields), in FP64 complex arithmetic.  Arrays are
-    [..., Y, X] on the extended grid.  At Q = 0 the interaction is infinite
-    and chi_RPA takes its limit, 0.  Returns (Im chi_RPA, Re chi_RPA)."""
+    [..., Y, X] on the extended grid (one kz plane, hz, of a 3D grid).  At
+    Q = 0 the interaction is infinite and chi_RPA takes its limit, 0.
+    Returns (Im chi_RPA, Re chi_RPA)."""
     chi = np.asarray(re_chi, dtype=np.float64) + 1j * np.asarray(im_chi, dtype=np.float64)
-    V = coulomb_v(hx, hy, v)
+    V = coulomb_v(hx, hy, v, hz)
     fin = np.isfinite(V)
     Vf = np.where(fin, V, 0.0)
     r = np.where(fin, chi / (1.0 - Vf * chi), 0.0)

@@ -26,6 +26,27 @@ def test_coulomb_v_is_inverse_square_of_the_zone_momentum():
     assert np.isfinite(V).sum() == V.size - 1
 
 
+def test_coulomb_v_with_a_kz_component():
+    """A kz plane of a 3D grid: |Q|^2 gains (2 pi hz)^2, so V is finite at
+    the in-plane centre and V |Q|^2 = v everywhere; hz = 0 is the 2D map."""
+    hx, _ = oracle.zone_axis(8, 3)
+    hy, _ = oracle.zone_axis(4, 5)
+    hz = -0.25
+    V = oracle.coulomb_v(hx, hy, 2.0, hz)
+    Q2 = (2 * np.pi) ** 2 * (hx[None, :] ** 2 + hy[:, None] ** 2 + hz ** 2)
+    assert np.allclose(V * Q2, 2.0, rtol=1e-15, atol=0)
+    assert np.isfinite(V).all() and V[10, 12] == 2.0 / (2 * np.pi * hz) ** 2
+    assert np.array_equal(oracle.coulomb_v(hx, hy, 2.0, 0.0), oracle.coulomb_v(hx, hy, 2.0))
+    re, im = _chi((3, 20, 24), 11)
+    imr, rer = oracle.rpa_coulomb(re, im, hx, hy, 0.7, hz)
+    # Dyson identity in real arithmetic: chi = chi_RPA (1 - V chi) component by component
+    V = V * (0.7 / 2.0)
+    a, b = 1.0 - V * re, V * im
+    d = a * a + b * b
+    assert np.allclose(imr, im / d, rtol=1e-13, atol=1e-16)
+    assert np.allclose(rer, (re * a - V * im * im) / d, rtol=1e-13, atol=1e-16)
+
+
 def test_rpa_coulomb_identities():
     hx, _ = oracle.zone_axis(8, 3)
     hy, _ = oracle.zone_axis(8, 3)
