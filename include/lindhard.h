@@ -118,10 +118,14 @@ typedef struct {
     const double *pair_weight;
     /* Three-dimensional k-grids (the d^3p of Eq. (9)): nkz > 1 (a power of two
      * up to 256; 0 or 1 = two dimensions) adds a third periodic axis.  It
-     * needs eps_table with nkz planes [band][iz][iy][ix] (rho_table alike), one
-     * zone (zones 1 x 1, k_zones <= 1), no orbital form factor and no RPA.
-     * The output planes are [omega][Z][Y][X] with Z = (qz + nkz/2) mod nkz,
-     * reported as out_ny = nkz * nky rows of out_nx = nkx. */
+     * needs eps_table with nkz planes [band][iz][iy][ix] (rho_table alike) and
+     * a first-zone k-grid (k_zones <= 1).  Zones, the orbital form factor and
+     * the RPA apply in the plane: each kz plane is extended over zones_x x
+     * zones_y in-plane zones with the in-plane |M(Qx, Qy)|^2, and the Coulomb
+     * |Q|^2 adds (2 pi hz)^2, hz = (Z - nkz/2) / nkz (lattice constant a along
+     * z).  The output planes are [omega][Z][Y][X] with Z = (qz + nkz/2) mod
+     * nkz, reported as out_ny = nkz * zones_y * nky rows of out_nx =
+     * zones_x * nkx.  With RPA, nkz * nky <= 65535. */
     int32_t nkz;
     /* Band-pair matrix elements that vary with the momentum transfer (Eqs.
      * (2), (3)): optional host array of n_bands * n_bands maps

@@ -107,8 +107,9 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     }
     const int nkz = p->nkz < 1 ? 1 : p->nkz;
     if (p->nkz < 0 || p->nkz > 256 || !is_pow2(nkz)) return LINDHARD_EINVAL;
-    if (nkz > 1 && (!p->eps_table || p->zones_x != 1 || p->zones_y != 1 || p->k_zones > 1 ||
-                    p->ff_kind != LINDHARD_FF_NONE || p->want_rpa))
+    // three dimensions: a caller table, the first momentum zone of the k-grid,
+    // and for RPA at most 65535 rows of the first-zone map (launch grid)
+    if (nkz > 1 && (!p->eps_table || p->k_zones > 1 || (p->want_rpa && (long)nkz * p->nky > 65535)))
         return LINDHARD_EINVAL;
     const long nk = (long)p->nkx * p->nky * nkz;
     const int nbands = p->n_bands < 1 ? 1 : p->n_bands;
@@ -485,7 +486,7 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     pl.zx = p->zones_x;
     pl.zy = p->zones_y;
     pl.out_nx = p->zones_x * p->nkx;
-    pl.out_ny = p->zones_y * p->nky * nkz;  // three dimensions: nkz blocks of nky rows
+    pl.out_ny = p->zones_y * p->nky * nkz;  // three dimensions: nkz blocks of zones_y * nky rows
     pl.out_elems = (size_t)p->nomega * pl.out_nx * pl.out_ny;
     pl.elem_bytes = g.fp64 ? 8 : 4;
     pl.scale = -pl.deps / ((double)nk * (double)nk);

@@ -679,8 +679,9 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
             }
         }
     } else {
+        // first-zone rows of lag m; out_ny rows per lag (nkz planes of nky rows in 3D)
         const int m = g.m_lo + slot;
-        T *orow = out + ((size_t)m * nky + qy) * nkx;
+        T *orow = out + ((size_t)m * out_ny + qy) * nkx;
 #pragma unroll
         for (int s = 0; s < E; ++s) {
             const int u = 2 * (gg + s * G);
@@ -1544,7 +1545,7 @@ __device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g
                 }
             } else {
                 const int m = g.m_lo + slot;
-                T *orow = out + ((size_t)m * nky + qy) * nkx;
+                T *orow = out + ((size_t)m * out_ny + qy) * nkx;
 #pragma unroll
                 for (int s = 0; s < E; ++s) orow[gg + s * G] = (half ? v[s].y : v[s].x) * sc;
             }
@@ -1590,33 +1591,37 @@ __device__ __forceinline__ double lag_blend(const T *__restrict__ im1, size_t nk
 
 // Extended, form-factor weighted map from the first-zone planes (RPA path).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, int nkx, int nky, int neps,
+__global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, int nkx, int nky, int nkz, int neps,
                                                     const int *__restrict__ lags, const double *__restrict__ fracs,
                                                     int nw, int zx, int zy, int ff, double ffs,
                                                     const double2 *__restrict__ ffx, const double2 *__restrict__ ffy,
                                                     T *__restrict__ out, int out_nx, int out_ny)
 {
     // one thread per first-zone point (u, v) and group of four planes: the
-    // first-zone values are read once and written to every zone image
+    // first-zone values are read once and written to every zone image.  In
+    // three dimensions v runs over nkz planes of nky rows (natural order);
+    // plane z goes to the output block (z + nkz/2) mod nkz of zy * nky rows.
     const int u = blockIdx.x * kThreads + threadIdx.x;
     const int v = blockIdx.y;
     const int w0 = blockIdx.z * 4;
     if (u >= nkx) return;
+    const size_t nk = (size_t)nkx * nky * nkz, q = (size_t)v * nkx + u;
     T vals[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int w = min(w0 + i, nw - 1);
         const double f = fracs[w];
-        vals[i] = f > 0.0 ? (T)lag_blend(im1, (size_t)nkx * nky, (size_t)v * nkx + u, neps, lags[w], f)
-                          : lag_value(im1, (size_t)nkx * nky, (size_t)v * nkx + u, neps, lags[w]);
+        vals[i] = f > 0.0 ? (T)lag_blend(im1, nk, q, neps, lags[w], f) : lag_value(im1, nk, q, neps, lags[w]);
     }
     const size_t plane = (size_t)out_nx * out_ny;
-    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
+    const int vy = v & (nky - 1), vz = v / nky;
+    const int Yz = ((vz + nkz / 2) & (nkz - 1)) * zy * nky;  // first row of the output block
+    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (vy + (zy * nky) / 2) & (nky - 1);
     for (int zi = 0; zi < zy; ++zi) {
-        const int Y = zi * nky + yv;
+        const int Yb = zi * nky + yv, Y = Yz + Yb;
         for (int zj = 0; zj < zx; ++zj) {
             const int X = zj * nkx + xu;
-            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Y], ffs) : 1.0;
+            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Yb], ffs) : 1.0;
             const size_t o0 = (size_t)Y * out_nx + X;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -1733,15 +1738,16 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
                                                  int zy, int ff, double ffs, const double2 *__restrict__ ffx,
                                                  const double2 *__restrict__ ffy, int vkind, double V, int kzn,
                                                  T *__restrict__ re_out, T *__restrict__ imr, T *__restrict__ rer,
-                                                 int out_nx, int out_ny)
+                                                 int out_nx, int out_ny, int nkz)
 {
     // one thread per first-zone point (u, v) and group of four planes: the
-    // first-zone Im / Re are read once and every zone image is written
+    // first-zone Im / Re are read once and every zone image is written (in
+    // three dimensions as in k_extend: v over nkz planes of nky rows)
     const int u = blockIdx.x * kThreads + threadIdx.x;
     const int v = blockIdx.y;
     const int w0 = blockIdx.z * 4;
     if (u >= nkx) return;
-    const size_t q = (size_t)v * nkx + u, nk = (size_t)nkx * nky;
+    const size_t q = (size_t)v * nkx + u, nk = (size_t)nkx * nky * nkz;
     double imv[4], rev[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1755,24 +1761,29 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
         rev[i] = f > 0.0 && sb >= 0 ? (double)(T)((1.0 - f) * ra + f * (double)re1[(size_t)sb * nk + q]) : ra;
     }
     const size_t plane = (size_t)out_nx * out_ny;
-    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (v + (zy * nky) / 2) & (nky - 1);
+    const int vy = v & (nky - 1), vz = v / nky;
+    const int Zc = (vz + nkz / 2) & (nkz - 1), Yz = Zc * zy * nky;
+    // kz in reciprocal-lattice units of the third axis (0 in two dimensions)
+    const double hz = (double)(Zc - nkz / 2) / nkz;
+    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (vy + (zy * nky) / 2) & (nky - 1);
     for (int zi = 0; zi < zy; ++zi) {
-        const int Y = zi * nky + yv;
+        const int Yb = zi * nky + yv, Y = Yz + Yb;
         for (int zj = 0; zj < zx; ++zj) {
             const int X = zj * nkx + xu;
             // interaction: contact U = V, or Coulomb V / |Q|^2 with
-            // Q = 2 pi (h, l) in units of 1/a (h, l the reciprocal-lattice
+            // Q = 2 pi (h, l, hz) in units of 1/a (h, l the reciprocal-lattice
             // coordinates of X, Y: a grid spanning kzn zones has a step of
-            // kzn / n); at Q = 0 chi_RPA -> -1/V -> 0
+            // kzn / n; hz that of the kz plane, lattice constant a along z
+            // too); at Q = 0 chi_RPA -> -1/V -> 0
             double U = V;
             bool q0 = false;
             if (vkind == 1) {
-                const double h = (double)kzn * (X - (zx * nkx) / 2) / nkx, l = (double)kzn * (Y - (zy * nky) / 2) / nky;
-                const double q2 = (2.0 * kPi) * (2.0 * kPi) * (h * h + l * l);
+                const double h = (double)kzn * (X - (zx * nkx) / 2) / nkx, l = (double)kzn * (Yb - (zy * nky) / 2) / nky;
+                const double q2 = (2.0 * kPi) * (2.0 * kPi) * (h * h + l * l + hz * hz);
                 q0 = q2 == 0.0;
                 U = q0 ? 0.0 : V / q2;
             }
-            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Y], ffs) : 1.0;
+            const double m2 = ff ? form_factor_sq(ffx[X], ffy[Yb], ffs) : 1.0;
             const size_t o0 = (size_t)Y * out_nx + X;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -2713,14 +2724,20 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         } else {
             const cx<T> *spec = (const cx<T> *)buf;
             if (rpa) {
-#define LH_P5(LG) launch_p5<T, LG, 1>(pl, spec, g.nL, (T *)pl.im1, g.nkx, g.nky, st)
-                LH_SWITCH_LOG(g.logL, LH_P5)
-#undef LH_P5
-            } else {
-                // kz plane z of the spectrum -> output rows of Z = (z + nkz/2) mod nkz
+                // first-zone planes [lag][kz][ky][kx] (natural order)
                 for (int z = 0; z < g.nkz; ++z) {
                     const cx<T> *sz = spec + (size_t)z * g.plane_elems;
-                    T *oz = out + (size_t)((z + g.nkz / 2) & (g.nkz - 1)) * g.nky * pl.out_nx;
+                    T *iz = (T *)pl.im1 + (size_t)z * g.nky * g.nkx;
+#define LH_P5(LG) launch_p5<T, LG, 1>(pl, sz, g.nL, iz, g.nkx, g.nky * g.nkz, st)
+                    LH_SWITCH_LOG(g.logL, LH_P5)
+#undef LH_P5
+                }
+            } else {
+                // kz plane z of the spectrum -> output block Z = (z + nkz/2) mod nkz
+                // of zones_y * nky rows
+                for (int z = 0; z < g.nkz; ++z) {
+                    const cx<T> *sz = spec + (size_t)z * g.plane_elems;
+                    T *oz = out + (size_t)((z + g.nkz / 2) & (g.nkz - 1)) * pl.zy * g.nky * pl.out_nx;
 #define LH_P5(LG) launch_p5<T, LG, 0>(pl, sz, pl.p.nomega, oz, pl.out_nx, pl.out_ny, st, m2, acc)
                     LH_SWITCH_LOG(g.logL, LH_P5)
 #undef LH_P5
@@ -2809,9 +2826,9 @@ static hipError_t exec_t(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev)
         if (!pl.p.want_rpa) LH_HIP_TRY(p5(pl.spec));  // every plane is zero
     }
     if (pl.p.want_rpa)
-        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
-                           st, (const T *)pl.im1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx,
-                           pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
+        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky * g.nkz, cdiv(pl.p.nomega, 4)),
+                           dim3(kThreads), 0, st, (const T *)pl.im1, g.nkx, g.nky, g.nkz, g.neps, pl.d_lag, pl.d_frac,
+                           pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
     mark(5);
     return hipGetLastError();
 }
@@ -3058,7 +3075,7 @@ template <typename T>
 static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *rer, hipStream_t st)
 {
     const Geo &g = pl.g;
-    const int nk = g.nkx * g.nky;
+    const int nk = g.nkx * g.nky * g.nkz;
     if (pl.kk_ntiles > 4)
         hipLaunchKernelGGL((k_kkm<T, 8>), dim3(cdiv(nk, kKkQ), cdiv(pl.kk_ntiles, 8)), dim3(512), 0, st,
                            (const T *)pl.im1, nk, g.neps, pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
@@ -3066,10 +3083,10 @@ static hipError_t rpa_t(const Plan &pl, int vkind, double U, T *re, T *imr, T *r
         hipLaunchKernelGGL((k_kkm<T, 4>), dim3(cdiv(nk, kKkQ), 1), dim3(256), 0, st, (const T *)pl.im1, nk, g.neps,
                            pl.kkw, pl.d_kkrow, pl.kk_ntiles, pl.kk_nch, (T *)pl.re1);
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
-    hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0, st,
-                       (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac, pl.d_kkslot,
-                       pl.p.nomega, pl.zx, pl.zy, ff,
-                       pl.ff_s, pl.ffx, pl.ffy, vkind, U, pl.p.k_zones, re, imr, rer, pl.out_nx, pl.out_ny);
+    hipLaunchKernelGGL(k_rpa<T>, dim3(cdiv(g.nkx, kThreads), g.nky * g.nkz, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
+                       st, (const T *)pl.im1, (const T *)pl.re1, g.nkx, g.nky, g.neps, pl.d_lag, pl.d_frac,
+                       pl.d_kkslot, pl.p.nomega, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, vkind, U, pl.p.k_zones, re,
+                       imr, rer, pl.out_nx, pl.out_ny, g.nkz);
     return hipGetLastError();
 }
 

@@ -124,8 +124,8 @@ def test_problem_shape_is_host_only():
     dict(n_bands=2, eps_table=np.zeros((2, 32, 32)), pair_weight=-np.ones((2, 2))),
     dict(n_bands=9, eps_table=np.zeros((9, 32, 32))),
     dict(nkz=3, eps_table=np.zeros((3, 32, 32))),                      # kz count not a power of two
-    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), zones=(3, 1)),        # 3D takes one zone
-    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), want_rpa=True),
+    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), k_zones=2),           # 3D: first-zone k-grid
+    dict(nkz=4, eps_table=np.zeros((4, 32, 32)), pair_m2=np.ones((1, 1, 32, 32))),
     dict(nkx=33, eps_table=np.zeros((32, 33)), ff_kind=1, ff_width=0.6),  # any size: no form factor
     dict(nkx=2050, eps_table=np.zeros((32, 2050))),                    # FP64 any size up to 2049
     dict(omega=[1.5 / 32.0], omega_interp=False),
@@ -140,6 +140,15 @@ def test_widened_forms_validated_on_the_host(over):
     with pytest.raises(LH.LindhardError) as ei:
         LH.problem_shape(p)
     assert ei.value.status in (-1, -2)
+
+
+def test_3d_extended_shapes_on_the_host():
+    """A 3D grid with in-plane zones reports nkz blocks of zones_y * nky rows."""
+    from paper_1208_3210_amd import lindhard as LH
+
+    p, keep = LH.make_problem(**_base(nkz=4, eps_table=np.zeros((4, 32, 32)), zones=(3, 5), ff_kind=1,
+                                      ff_width=0.6, want_rpa=True))
+    assert LH.problem_shape(p) == (32, 4 * 5 * 32, 3 * 32)
 
 
 def test_offgrid_omega_accepted_with_interp_on_the_host():

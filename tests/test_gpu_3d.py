@@ -1,8 +1,9 @@
 """Three-dimensional k-grids through the C ABI against the FP64 oracle: the
 general path with a third, kz, transform pass; several shapes (flat and
 cubic-ish, two kz planes), an omega between lag-grid points, two summed bands,
-the output layout [omega][Z][Y][X], and the argument errors.  Normwise
-tolerances as for the hot path."""
+in-plane extended zones with the form factor, Kramers-Kronig with the contact
+and Coulomb RPA, the output layout [omega][Z][Y][X], and the argument errors.
+Normwise tolerances as for the hot path."""
 import numpy as np
 import pytest
 import torch
@@ -84,10 +85,81 @@ def test_3d_offgrid_omega_and_two_bands(prec):
     plan.close()
 
 
+def _oracle_full_3d(cfg):
+    eps = np.asarray(cfg["eps_table"], dtype=np.float64).reshape(cfg["nkz"], cfg["nky"], cfg["nkx"])
+    mu = oracle.mu_solve(eps.reshape(-1), cfg["gamma"], cfg["filling"])
+    full = oracle.chi_full_3d(eps - mu, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], np.arange(cfg["neps"]))
+    return mu, full  # (neps, nkz, nky, nkx), natural q order
+
+
+def _extend_3d(maps, cfg):
+    """kz planes centred, every plane extended over the in-plane zones with
+    the in-plane form factor: (n, nkz * zy * nky, zx * nkx)."""
+    zx, zy = cfg["zones"]
+    rolled = np.roll(maps, cfg["nkz"] // 2, axis=-3)
+    ext = oracle.extend(rolled, zx, zy, cfg.get("ff_kind", 0), cfg.get("ff_width", 0.0))
+    return ext.reshape(ext.shape[0], -1, ext.shape[-1])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_3d_extended_zones_and_form_factor(prec):
+    """3D grid with 3 x 5 in-plane zones and the orbital form factor: every kz
+    plane becomes a block of zones_y * nky rows (output [omega][Z][Y][X])."""
+    cfg = cfg3(16, 8, 4, zones=(3, 5), ff_kind=1, ff_width=0.6)
+    mu, full = _oracle_full_3d(cfg)
+    d = (cfg["emax"] - cfg["emin"]) / cfg["neps"]
+    lags = np.rint(np.asarray(cfg["omega"]) / d).astype(int)
+    ref = _extend_3d(full[lags], cfg)
+    plan = LH.Plan(precision=prec, **cfg)
+    assert plan.shape == (len(lags), 4 * 5 * 8, 3 * 16)
+    got = plan.exec()
+    torch.cuda.synchronize()
+    err = normwise(got.double().cpu().numpy(), ref)
+    print("3d zones+ff prec=%d err=%.3e" % (prec, err))
+    assert err <= TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_3d_rpa_contact_and_coulomb(prec):
+    """Kramers-Kronig and RPA on a 3D grid (3 x 1 zones, form factor): Re chi
+    from every lag, the contact RPA, and the Coulomb RPA whose |Q|^2 includes
+    the kz of each plane (lattice constant a along z)."""
+    cfg = cfg3(8, 8, 4, zones=(3, 1), ff_kind=1, ff_width=0.6, want_rpa=True)
+    mu, full = _oracle_full_3d(cfg)
+    d = (cfg["emax"] - cfg["emin"]) / cfg["neps"]
+    lags = np.rint(np.asarray(cfg["omega"]) / d).astype(int)
+    re1 = np.moveaxis(oracle.kk_real(np.moveaxis(full, 0, -1), lags), -1, 0)
+    im_ext = _extend_3d(full[lags], cfg)
+    re_ext = _extend_3d(re1, cfg)
+    U, v = 1.1, 0.4
+    imr_c, rer_c = oracle.rpa(re_ext, im_ext, U)
+    nkz, nky, nkx = cfg["nkz"], cfg["nky"], cfg["nkx"]
+    zx, zy = cfg["zones"]
+    hx, _ = oracle.zone_axis(nkx, zx)
+    hy, _ = oracle.zone_axis(nky, zy)
+    imr_v, rer_v = np.empty_like(im_ext), np.empty_like(im_ext)
+    for Z in range(nkz):
+        rows = slice(Z * zy * nky, (Z + 1) * zy * nky)
+        hz = (Z - nkz // 2) / nkz
+        imr_v[:, rows], rer_v[:, rows] = oracle.rpa_coulomb(re_ext[:, rows], im_ext[:, rows], hx, hy, v, hz)
+    plan = LH.Plan(precision=prec, **cfg)
+    im = plan.exec()
+    re, imr, rer = plan.rpa(U)
+    torch.cuda.synchronize()
+    errs = [normwise(x.double().cpu().numpy(), r) for x, r in ((im, im_ext), (re, re_ext), (imr, imr_c), (rer, rer_c))]
+    re2, imr2, rer2 = plan.rpa_coulomb(v)
+    torch.cuda.synchronize()
+    errs += [normwise(x.double().cpu().numpy(), r) for x, r in ((re2, re_ext), (imr2, imr_v), (rer2, rer_v))]
+    print("3d rpa prec=%d errs=%s" % (prec, ["%.2e" % e for e in errs]))
+    assert max(errs) <= TOL[prec]
+    plan.close()
+
+
 def test_3d_argument_errors():
     base = cfg3(8, 8, 4)
-    for bad in (dict(nkz=3, eps_table=np.zeros((3, 8, 8))), dict(zones=(3, 1)), dict(ff_kind=1, ff_width=0.6),
-                dict(want_rpa=True), dict(nkz=512, eps_table=np.zeros((512, 8, 8)))):
+    for bad in (dict(nkz=3, eps_table=np.zeros((3, 8, 8))), dict(k_zones=2),
+                dict(pair_m2=np.ones((1, 1, 8, 8))), dict(nkz=512, eps_table=np.zeros((512, 8, 8)))):
         with pytest.raises(LH.LindhardError) as ei:
             LH.Plan(precision=LH.LINDHARD_FP32C, **dict(base, **bad))
         assert ei.value.status == LH.LINDHARD_EINVAL
