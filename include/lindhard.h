@@ -78,8 +78,9 @@ typedef struct {
     double filling;             /* electrons per site, both spins (1 + x) */
     double gamma;               /* Lorentzian half width of Eq. (5), eV, > 0 */
     int32_t nkx, nky;           /* powers of two 4 .. 4096; other sizes >= 4 (Bluestein
-                                   transforms) up to 4097 in FP32 and 2049 in FP64 with one
-                                   zone, one band, no form factor and no RPA */
+                                   transforms) up to 4097 in FP32 and 2049 in FP64, two
+                                   dimensions and one band (zones, form factor and RPA as
+                                   for powers of two; centring (q + floor(Z n / 2)) mod n) */
     int32_t neps;               /* power of two, 4 .. 2048 */
     double emin, emax;          /* energy window, emin < 0 < emax */
     int32_t nomega;             /* number of requested omegas, 1 .. 65535 */

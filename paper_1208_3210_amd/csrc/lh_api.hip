@@ -79,16 +79,14 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
     if (!p) return LINDHARD_EINVAL;
     if (p->precision != LINDHARD_FP32C && p->precision != LINDHARD_FP64) return LINDHARD_EINVAL;
     // powers of two up to 4096; other sizes (Bluestein transforms) up to 4097
-    // in FP32 and 2049 in FP64, one zone, one band, no form factor, no RPA
+    // in FP32 and 2049 in FP64, two dimensions and one band
     const bool any_size = !is_pow2(p->nkx) || !is_pow2(p->nky);
     if (p->nkx < 4 || p->nky < 4) return LINDHARD_EINVAL;
     if (!any_size && (p->nkx > 4096 || p->nky > 4096)) return LINDHARD_EINVAL;
     if (any_size) {
         const int lim = p->precision == LINDHARD_FP64 ? 2049 : 4097;
         if (p->nkx > lim || p->nky > lim) return LINDHARD_EINVAL;
-        if (p->zones_x != 1 || p->zones_y != 1 || p->ff_kind != LINDHARD_FF_NONE || p->want_rpa || p->nkz > 1 ||
-            p->n_bands > 1 || p->pair_weight)
-            return LINDHARD_EINVAL;
+        if (p->nkz > 1 || p->n_bands > 1 || p->pair_weight) return LINDHARD_EINVAL;
     }
     if (!is_pow2(p->neps) || p->neps < 4 || p->neps > 2048) return LINDHARD_EINVAL;
     if (!std::isfinite(p->emin) || !std::isfinite(p->emax) || !(p->emin < 0.0) || !(p->emax > 0.0))

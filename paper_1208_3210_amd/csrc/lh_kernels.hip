@@ -1614,9 +1614,10 @@ __global__ void __launch_bounds__(kThreads) k_extend(const T *__restrict__ im1, 
         vals[i] = f > 0.0 ? (T)lag_blend(im1, nk, q, neps, lags[w], f) : lag_value(im1, nk, q, neps, lags[w]);
     }
     const size_t plane = (size_t)out_nx * out_ny;
-    const int vy = v & (nky - 1), vz = v / nky;
-    const int Yz = ((vz + nkz / 2) & (nkz - 1)) * zy * nky;  // first row of the output block
-    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (vy + (zy * nky) / 2) & (nky - 1);
+    // (any grid size: modulo rather than masks)
+    const int vy = v % nky, vz = v / nky;
+    const int Yz = ((vz + nkz / 2) % nkz) * zy * nky;  // first row of the output block
+    const int xu = (u + (zx * nkx) / 2) % nkx, yv = (vy + (zy * nky) / 2) % nky;
     for (int zi = 0; zi < zy; ++zi) {
         const int Yb = zi * nky + yv, Y = Yz + Yb;
         for (int zj = 0; zj < zx; ++zj) {
@@ -1662,16 +1663,21 @@ __global__ void __launch_bounds__(64 * WV) k_kkm(const T *__restrict__ im1, int 
     const int par = active ? (rows[t * 16].x & 1) : 0;
     const int J = 16 * nch;
     // staging: load v of a chunk covers energy row e = idx / (kKkQ / VEC), q group
+    // 16-byte loads while every energy row starts on a 16-byte boundary (a
+    // grid of any size may not: then element by element)
+    const bool vec = nk % VEC == 0;
     auto load = [&](int c, Vec16<T> *v) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const int idx = tid + k * NT, e = idx / (kKkQ / VEC), qv = (idx % (kKkQ / VEC)) * VEC;
             const int j = 32 * c + e;
-            if (j < neps && q0 + qv < nk)
+            if (vec && j < neps && q0 + qv < nk) {
                 v[k] = *reinterpret_cast<const Vec16<T> *>(im1 + (size_t)j * nk + q0 + qv);
-            else
+            } else {
 #pragma unroll
-                for (int u = 0; u < VEC; ++u) v[k].v[u] = (T)0;
+                for (int u = 0; u < VEC; ++u)
+                    v[k].v[u] = j < neps && q0 + qv + u < nk ? im1[(size_t)j * nk + q0 + qv + u] : (T)0;
+            }
         }
     };
     auto store = [&](const Vec16<T> *v) {
@@ -1761,11 +1767,11 @@ __global__ void __launch_bounds__(kThreads) k_rpa(const T *__restrict__ im1, con
         rev[i] = f > 0.0 && sb >= 0 ? (double)(T)((1.0 - f) * ra + f * (double)re1[(size_t)sb * nk + q]) : ra;
     }
     const size_t plane = (size_t)out_nx * out_ny;
-    const int vy = v & (nky - 1), vz = v / nky;
-    const int Zc = (vz + nkz / 2) & (nkz - 1), Yz = Zc * zy * nky;
+    const int vy = v % nky, vz = v / nky;
+    const int Zc = (vz + nkz / 2) % nkz, Yz = Zc * zy * nky;
     // kz in reciprocal-lattice units of the third axis (0 in two dimensions)
     const double hz = (double)(Zc - nkz / 2) / nkz;
-    const int xu = (u + (zx * nkx) / 2) & (nkx - 1), yv = (vy + (zy * nky) / 2) & (nky - 1);
+    const int xu = (u + (zx * nkx) / 2) % nkx, yv = (vy + (zy * nky) / 2) % nky;
     for (int zi = 0; zi < zy; ++zi) {
         const int Yb = zi * nky + yv, Y = Yz + Yb;
         for (int zj = 0; zj < zx; ++zj) {
@@ -2248,12 +2254,16 @@ __global__ void __launch_bounds__(512) k_bs_col(cx<T> *__restrict__ spec, Geo g,
 // qy = 2p, 2p + 1 packed as z = S(2p) + i S(2p + 1): both rows have real
 // transforms, so the real and imaginary parts of the result are the two
 // output rows.  Columns rx > nkx / 2 are rebuilt as conj S(nkx - rx).  The
-// rows are scaled and written Gamma-centred: out[plane][(qy + nky/2) mod
-// nky][(qx + nkx/2) mod nkx] (one zone, no form factor).
-template <typename T, int LOGM>
+// rows are scaled and written Gamma-centred into every zone image:
+// out[plane][zi nky + (qy + (zy nky)/2) mod nky][zj nkx + (qx + (zx nkx)/2)
+// mod nkx], times the orbital |M(Q)|^2 if ff (MODE 0); MODE 1 (the RPA path)
+// writes the first-zone map of window slot `plane` in natural order,
+// out[m_lo + plane][qy][qx].
+template <typename T, int LOGM, int MODE>
 __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, Geo g, BsTab tx,
                                               const PlaneSrc *__restrict__ psrc, double scale,
-                                              T *__restrict__ out)
+                                              T *__restrict__ out, int zx, int zy, int ff, double ffs,
+                                              const double2 *__restrict__ ffx, const double2 *__restrict__ ffy)
 {
     using F = RegFFT<T, LOGM, false>;
     constexpr int M = F::N, E = F::E, G = F::G;
@@ -2268,13 +2278,21 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
     const int qa = min(2 * p, g.nky - 1), qb = min(2 * p + 1, g.nky - 1);
     const bool hasa = 2 * p < g.nky, hasb = 2 * p + 1 < g.nky;
     const int nkx = g.nkx, nky = g.nky, H = nkx / 2;
-    const PlaneSrc ps = psrc[plane];
-    T *ra = out + ((size_t)plane * nky + (qa + nky / 2) % nky) * nkx;
-    T *rb = out + ((size_t)plane * nky + (qb + nky / 2) % nky) * nkx;
+    const PlaneSrc ps = MODE == 0 ? psrc[plane] : PlaneSrc{plane, -1, 1.0, 0.0};
+    const int onx = MODE == 0 ? zx * nkx : nkx, ony = MODE == 0 ? zy * nky : nky;
+    const int sx = MODE == 0 ? (zx * nkx) / 2 : 0, sy = MODE == 0 ? (zy * nky) / 2 : 0;
+    const int nzx = MODE == 0 ? zx : 1, nzy = MODE == 0 ? zy : 1;
+    const int oplane = MODE == 0 ? plane : g.m_lo + plane;
+    // output rows of zone row zi: zi nky + (q + sy) mod nky
+    const int ya = (qa + sy) % nky, yb = (qb + sy) % nky;
     if (ps.a < 0) {  // the plane is zero (block-uniform)
-        for (int k = gg; k < nkx; k += G) {
-            if (hasa) ra[k] = (T)0;
-            if (hasb) rb[k] = (T)0;
+        for (int zi = 0; zi < nzy; ++zi) {
+            T *ra = out + ((size_t)oplane * ony + zi * nky + ya) * onx;
+            T *rb = out + ((size_t)oplane * ony + zi * nky + yb) * onx;
+            for (int k = gg; k < onx; k += G) {
+                if (hasa) ra[k] = (T)0;
+                if (hasb) rb[k] = (T)0;
+            }
         }
         return;
     }
@@ -2313,13 +2331,27 @@ __global__ void __launch_bounds__(512) k_bs_p5(const cx<T> *__restrict__ spec, G
     }
     bs_line<T, LOGM, true, bs_tw_lds<T, LOGM>()>(v, lds + line * M, tl, gg, lds_xor_gfast<M, G>(line));
     const T sc = (T)scale;
+    const int xs = MODE == 0 ? sx : 0;
+    for (int zi = 0; zi < nzy; ++zi) {
+        const int Ya = zi * nky + ya, Yb = zi * nky + yb;
+        T *ra = out + ((size_t)oplane * ony + (MODE == 0 ? Ya : qa)) * onx;
+        T *rb = out + ((size_t)oplane * ony + (MODE == 0 ? Yb : qb)) * onx;
+        const double2 fya = ff ? ffy[Ya] : make_double2(1.0, 0.0), fyb = ff ? ffy[Yb] : make_double2(1.0, 0.0);
+        for (int zj = 0; zj < nzx; ++zj) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) {
-        const int k = gg + s * G;
-        if (k < nkx) {
-            const int X = (k + nkx / 2) % nkx;
-            if (hasa) ra[X] = v[s].x * sc;
-            if (hasb) rb[X] = v[s].y * sc;
+            for (int s = 0; s < E; ++s) {
+                const int k = gg + s * G;
+                if (k < nkx) {
+                    const int X = zj * nkx + (MODE == 0 ? (k + xs) % nkx : k);
+                    T a = v[s].x * sc, b = v[s].y * sc;
+                    if (MODE == 0 && ff) {
+                        a = (T)((double)a * form_factor_sq(ffx[X], fya, ffs));
+                        b = (T)((double)b * form_factor_sq(ffx[X], fyb, ffs));
+                    }
+                    if (hasa) ra[X] = a;
+                    if (hasb) rb[X] = b;
+                }
+            }
         }
     }
 }
@@ -2593,15 +2625,16 @@ static void launch_bs_col(const Plan &pl, cx<T> *spec, int nslices, hipStream_t 
                        nslices);
 }
 
-template <typename T, int LOGM>
+template <typename T, int LOGM, int MODE>
 static void launch_bs_p5(const Plan &pl, const cx<T> *spec, T *out, hipStream_t st)
 {
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGM, false>;
-    const dim3 grid(xcd_grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.bs_Rr >= 2 ? 1 : 2), pl.p.nomega);
+    const dim3 grid(xcd_grid(cdiv((g.nky + 1) / 2, g.bs_Rr), g.bs_Rr >= 2 ? 1 : 2), MODE == 0 ? pl.p.nomega : g.nL);
     const size_t lds = (size_t)(g.bs_Rr + (bs_tw_lds<T, LOGM>() ? 1 : 0)) * F::N * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_bs_p5<T, LOGM>), grid, dim3(g.bs_Rr * F::G), lds, st, spec, g, bs_tab(pl, false), pl.d_src,
-                       pl.scale, out);
+    const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+    hipLaunchKernelGGL((k_bs_p5<T, LOGM, MODE>), grid, dim3(g.bs_Rr * F::G), lds, st, spec, g, bs_tab(pl, false),
+                       pl.d_src, pl.scale, out, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy);
 }
 
 // Grids of any size: Bluestein row and column passes around the same window.
@@ -2635,9 +2668,22 @@ static hipError_t exec_bs(const Plan &pl, T *out, hipStream_t st, hipEvent_t *ev
         mark(3);
         mark(4);
     }
-#define LH_B5(LG) launch_bs_p5<T, LG>(pl, spec, out, st)
-    LH_SWITCH_LOGM(g.logMx, LH_B5)
+    if (pl.p.want_rpa) {
+        // the RPA path: first-zone maps of every lag, then the requested planes
+        if (g.nL > 0) {
+#define LH_B5(LG) launch_bs_p5<T, LG, 1>(pl, spec, (T *)pl.im1, st)
+            LH_SWITCH_LOGM(g.logMx, LH_B5)
 #undef LH_B5
+        }
+        const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
+        hipLaunchKernelGGL(k_extend<T>, dim3(cdiv(g.nkx, kThreads), g.nky, cdiv(pl.p.nomega, 4)), dim3(kThreads), 0,
+                           st, (const T *)pl.im1, g.nkx, g.nky, 1, g.neps, pl.d_lag, pl.d_frac, pl.p.nomega, pl.zx,
+                           pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, pl.out_nx, pl.out_ny);
+    } else {
+#define LH_B5(LG) launch_bs_p5<T, LG, 0>(pl, spec, out, st)
+        LH_SWITCH_LOGM(g.logMx, LH_B5)
+#undef LH_B5
+    }
     mark(5);
     return hipGetLastError();
 }

@@ -47,8 +47,8 @@ def _base(**over):
 
 
 @pytest.mark.parametrize("over,status", [
-    (dict(nkx=48, zones=(3, 1)), -1), (dict(nkx=2050), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
-    (dict(nkx=8192), -1), (dict(nky=8192), -1), (dict(nkx=48, want_rpa=True), -1), (dict(neps=100), -1),
+    (dict(nkx=48, zones=(2, 1)), -1), (dict(nkx=2050), -1), (dict(nkx=3), -1), (dict(nky=2), -1),
+    (dict(nkx=8192), -1), (dict(nky=8192), -1), (dict(nkx=48, nkz=2), -1), (dict(neps=100), -1),
     (dict(neps=2), -1), (dict(omega=np.arange(65536) / 32.0 % 1.0), -1),
     (dict(nky=4096, zones=(1, 17)), -1),
     (dict(emin=0.1), -1), (dict(emax=-0.1), -1), (dict(gamma=0.0), -1), (dict(gamma=math.nan), -1),
@@ -126,7 +126,7 @@ def test_problem_shape_is_host_only():
     dict(nkz=3, eps_table=np.zeros((3, 32, 32))),                      # kz count not a power of two
     dict(nkz=4, eps_table=np.zeros((4, 32, 32)), k_zones=2),           # 3D: first-zone k-grid
     dict(nkz=4, eps_table=np.zeros((4, 32, 32)), pair_m2=np.ones((1, 1, 32, 32))),
-    dict(nkx=33, eps_table=np.zeros((32, 33)), ff_kind=1, ff_width=0.6),  # any size: no form factor
+    dict(nkx=33, eps_table=np.zeros((2, 32, 33)), n_bands=2),            # any size: one band
     dict(nkx=2050, eps_table=np.zeros((32, 2050))),                    # FP64 any size up to 2049
     dict(omega=[1.5 / 32.0], omega_interp=False),
     dict(omega=[-1.0 / 32.0], omega_interp=True),

@@ -2,7 +2,8 @@
 through the C ABI against the FP64 oracle: Bluestein row and column passes
 around the usual window.  Full-grid comparisons on small odd and even sizes
 (caller tables and the tight-binding band, an omega between lags, momentum
-density weights over several zones), sampled comparisons on a 2049-point axis
+density weights over several zones, extended zones with the form factor and
+the RPA epilogues), sampled comparisons on a 2049-point axis
 (FP32) and a 1000-point axis (FP64), and the argument errors.  Normwise
 tolerances as for the hot path; sampled errors relative to the largest
 sampled reference value."""
@@ -118,12 +119,56 @@ def test_long_axes_sampled(prec, nkx, nky):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape,zones", [((33, 17), (3, 5)), ((12, 20), (5, 1)), ((7, 9), (3, 3))])
+def test_any_size_zones_form_factor_and_rpa(prec, shape, zones):
+    """Odd and even sizes that are not powers of two over several zones with
+    the orbital form factor: the bare map, Kramers-Kronig, the contact and the
+    Coulomb RPA against the oracle (Gamma-centred: index (q + floor(Z n/2)) mod n)."""
+    nkx, nky = shape
+    zx, zy = zones
+    rng = np.random.Generator(np.random.PCG64(nkx * 1000 + nky))
+    tab = rng.uniform(-1.2, 1.5, size=(nky, nkx))
+    cfg = dict(eps_table=tab, filling=1.1, nkx=nkx, nky=nky, neps=64, emin=-1.5, emax=1.5, gamma=0.07,
+               omega=np.arange(1, 40, 3) * (3.0 / 64), zones=zones, ff_kind=1, ff_width=0.6, want_rpa=True)
+    mu = oracle.mu_solve(tab, cfg["gamma"], cfg["filling"])
+    full = oracle.chi_full(tab - mu, cfg["neps"], cfg["emin"], cfg["emax"], cfg["gamma"], np.arange(cfg["neps"]))
+    d = (cfg["emax"] - cfg["emin"]) / cfg["neps"]
+    lags = np.rint(np.asarray(cfg["omega"]) / d).astype(int)
+    re1 = np.moveaxis(oracle.kk_real(np.moveaxis(full, 0, -1), lags), -1, 0)
+    im_ext = oracle.extend(full[lags], zx, zy, 1, 0.6)
+    re_ext = oracle.extend(re1, zx, zy, 1, 0.6)
+    U, v = 1.2, 0.5
+    imr_c, rer_c = oracle.rpa(re_ext, im_ext, U)
+    hx, _ = oracle.zone_axis(nkx, zx)
+    hy, _ = oracle.zone_axis(nky, zy)
+    imr_v, rer_v = oracle.rpa_coulomb(re_ext, im_ext, hx, hy, v)
+    plan = LH.Plan(precision=prec, **cfg)
+    assert plan.shape == (len(lags), zy * nky, zx * nkx)
+    im = plan.exec()
+    re, imr, rer = plan.rpa(U)
+    torch.cuda.synchronize()
+    errs = [normwise(x.double().cpu().numpy(), r) for x, r in ((im, im_ext), (re, re_ext), (imr, imr_c), (rer, rer_c))]
+    re2, imr2, rer2 = plan.rpa_coulomb(v)
+    torch.cuda.synchronize()
+    errs += [normwise(x.double().cpu().numpy(), r) for x, r in ((re2, re_ext), (imr2, imr_v), (rer2, rer_v))]
+    print("any size zones+rpa prec=%d shape=%s zones=%s errs=%s" % (prec, shape, zones, ["%.2e" % e for e in errs]))
+    assert max(errs) <= TOL[prec]
+    # the bare map of a plan without RPA (the extended last row pass) agrees too
+    p2 = LH.Plan(precision=prec, **dict(cfg, want_rpa=False))
+    im2 = p2.exec()
+    torch.cuda.synchronize()
+    assert normwise(im2.double().cpu().numpy(), im_ext) <= TOL[prec]
+    p2.close()
+    plan.close()
+
+
 def test_any_size_argument_errors():
     tab = np.zeros((12, 20))
     base = dict(eps_table=tab, mu=0.0, nkx=20, nky=12, neps=32, emin=-1.0, emax=1.0, gamma=0.1,
                 omega=[2 * 2.0 / 32])
-    for bad in (dict(zones=(3, 1)), dict(ff_kind=1, ff_width=0.6), dict(want_rpa=True),
-                dict(n_bands=2, eps_table=np.zeros((2, 12, 20)))):
+    for bad in (dict(n_bands=2, eps_table=np.zeros((2, 12, 20))), dict(nkz=4, eps_table=np.zeros((4, 12, 20))),
+                dict(pair_m2=np.ones((1, 1, 12, 20)))):
         with pytest.raises(LH.LindhardError) as ei:
             LH.Plan(precision=LH.LINDHARD_FP32C, **dict(base, **bad))
         assert ei.value.status == LH.LINDHARD_EINVAL
