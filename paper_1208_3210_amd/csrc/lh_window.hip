@@ -203,14 +203,22 @@ __device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
         f4v acc[kTiles];
 #pragma unroll
         for (int k = 0; k < kTiles; ++k) acc[k] = f4v{0.f, 0.f, 0.f, 0.f};
-        // tiles k < KLO are past their last chunk (their B set is u < 0): no products
+        // tiles k < KLO are past their last chunk (their B set is u < 0): no
+        // products.  The A set of the next chunk is loaded while this one is
+        // on the matrix cores (two register sets alternating with the phase).
+        float Ab[2][16];
+        auto loadA = [&](int cc, float(&dst)[16]) {
+            const int cq = min(cc, cmax);  // past the last chunk: any row in range
+#pragma unroll
+            for (int s = 0; s < 16; ++s) dst[s] = Hb[16 * cq + s];
+        };
         auto chunk = [&](auto R, int cc, auto KLO) {
             constexpr int r = decltype(R)::value % kTiles;
             constexpr int klo = decltype(KLO)::value;
+            constexpr int cur = decltype(R)::value & 1;
             loadB(t0 + U0 - cc, ring[(kTiles - r) % kTiles]);
-            float A[16];
-#pragma unroll
-            for (int s = 0; s < 16; ++s) A[s] = Hb[16 * cc + s];
+            loadA(cc + 1, Ab[cur ^ 1]);
+            const float(&A)[16] = Ab[cur];
 #pragma unroll
             for (int s = 0; s < 16; ++s)
 #pragma unroll
@@ -233,6 +241,7 @@ __device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
         // chunks after it, tile k < cc - t0 - U0 has no more terms
         const int cm = min(cl, t0 + U0);
         int c = cf, nbody = 0;
+        loadA(cf, Ab[0]);  // phase 0 of the first chunk
         for (; c + kTiles - 1 <= cm; c += kTiles) {
             chunk(I0{}, c, I0{});
             chunk(I1{}, c + 1, I0{});
