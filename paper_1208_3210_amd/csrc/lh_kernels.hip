@@ -697,6 +697,44 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // with X_a, X_b real, so the real and imaginary parts separate exactly.  Only
 // rx in [0, nkx/2] and ry in [0, nky/2] are stored (see Geo).
 
+// Row passes of the even path (P1, P5) in FP32 use the padded-layout engine
+// (padding period 32) when a line spans whole waves (at least 64 threads);
+// FP64 keeps its twiddles in global memory and the swizzled engine.
+constexpr int kRowPB = 5;
+template <typename T, int LOGN, int LOGE>
+constexpr bool row_padded()
+{
+    return sizeof(T) == 4 && LOGN - LOGE >= 6 && LOGN <= 12;
+}
+// LDS elements between the lines of a row pass
+template <typename T, int LOGN, int LOGE>
+constexpr int row_line_stride()
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::LINE;
+    else
+        return 1 << LOGN;
+}
+// LDS slot of element x of a row-pass line
+template <typename T, int LOGN, int LOGE>
+__device__ __forceinline__ int row_slot(int x)
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::pad(x);
+    else
+        return x;
+}
+// LDS bytes of a row pass with R lines: the lines, then (FP32) the twiddles
+template <typename T, int LOGN, int LOGE>
+size_t row_lds_bytes(int R)
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return (size_t)(R * row_line_stride<T, LOGN, LOGE>() + RegFFTP<T, LOGN, false, LOGE, kRowPB>::TWN) *
+               sizeof(cx<T>);
+    else
+        return (size_t)(R + (sizeof(T) == 4 ? 1 : 0)) * (1 << LOGN) * sizeof(cx<T>);
+}
+
 // P1 (even): R row pairs (ky = 2p, 2p+1, ky <= nky/2) for jc slices.
 // FP32: at least four waves per SIMD (with the momentum-density weights the
 // kernel otherwise takes one register more than four waves allow); FP64 would
@@ -706,10 +744,14 @@ __device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo
                                                 double gamma, const cx<T> *__restrict__ twx, T *__restrict__ spec,
                                                 const T *__restrict__ rho, int acc)
 {
-    using F = RegFFT<T, LOGNX, false, ilog2_c(e1_elems(LOGNX)), kTwLds<T>>;
+    constexpr int LOGE = ilog2_c(e1_elems(LOGNX));
+    using F = RegFFT<T, LOGNX, false, LOGE, kTwLds<T>>;
+    using FP = RegFFTP<T, LOGNX, false, LOGE, kRowPB>;
+    constexpr bool PADDED = row_padded<T, LOGNX, LOGE>();
     constexpr int N = F::N, E = F::E, G = F::G;
+    constexpr int LS = row_line_stride<T, LOGNX, LOGE>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N]
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][LS]
     const int R = g.e1_R;
     const int tid = threadIdx.x;
     const int line = tid / G, gg = tid % G;
@@ -717,12 +759,15 @@ __device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo
     const int kya = min(2 * (p0 + line), g.Hy - 1), kyb = min(2 * (p0 + line) + 1, g.Hy - 1);
     const int jbeg = g.jA + blockIdx.y * g.e1_jc;
     const int jend = min(g.jB, jbeg + g.e1_jc);
-    cx<T> *buf = lds + line * N;
+    cx<T> *buf = lds + line * LS;
     // FP32: the twiddle table lives in LDS after the line buffers
     const cx<T> *tw = twx;
     if (sizeof(T) == 4) {
-        cx<T> *twl = lds + R * N;
-        for (int i = tid; i < N; i += R * G) twl[tw_swz(i)] = twx[i];
+        cx<T> *twl = lds + R * LS;
+        if constexpr (PADDED)
+            FP::fill_twiddles(twl, twx, tid, R * G);
+        else
+            for (int i = tid; i < N; i += R * G) twl[tw_swz(i)] = twx[i];
         tw = twl;
         __syncthreads();
     }
@@ -753,39 +798,54 @@ __device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo
             else
                 v[s] = mk<T>(lorentz(d0, gp, g2), lorentz(d1, gp, g2));
         }
-        F::run(v, buf, tw, 0, gg, lds_xor_gfast<N, G>(line));
-        // only rx in [0, nkx/2] is stored
+        if constexpr (PADDED) {
+            FP::run(v, buf, tw, gg);
+            // only rx in [0, nkx/2] is stored (s G is a multiple of the padding period)
+            cx<T> *ob = buf + FP::pad(gg);
 #pragma unroll
-        for (int s = 0; s <= E / 2; ++s)
-            if (gg + s * G <= H) buf[gg + s * G] = v[s];
+            for (int s = 0; s <= E / 2; ++s)
+                if (gg + s * G <= H) ob[FP::pad(s * G)] = v[s];
+        } else {
+            F::run(v, buf, tw, 0, gg, lds_xor_gfast<N, G>(line));
+#pragma unroll
+            for (int s = 0; s <= E / 2; ++s)
+                if (gg + s * G <= H) buf[gg + s * G] = v[s];
+        }
         __syncthreads();
         // Each item: VEC consecutive rx of one output row (16 bytes), items
-        // ordered half-row, row, tile so that a block writes whole tiles.
-        T *dst = spec + (size_t)(j - g.jA) * g.slice_e;
+        // ordered half-row, row, tile so that a block writes whole tiles;
+        // 32-bit offsets into the slice through a buffer descriptor.
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(spec + (size_t)(j - g.jA) * g.slice_e), 0, (int)(g.slice_e * sizeof(T)), 0x00020000);
         for (int it = tid; it < nvec; it += R * G) {
             const int h = it & (HV - 1);
             const int r = (it >> logHV) & (rows - 1);
             const int tile = (it >> logHV) >> logRows;
             const int ky = 2 * p0 + r;
             if (ky >= g.Hy) continue;
-            const cx<T> *zl = lds + (r >> 1) * N;
+            const cx<T> *zl = lds + (r >> 1) * LS;
             const int rx0 = tile * Ce + h * VEC;
             Vec16<T> o;
+            if (rx0 + VEC - 1 <= H) {
+                // rx0 is a multiple of VEC: no padding slot falls between the VEC values
+                const cx<T> *zp = zl + row_slot<T, LOGNX, LOGE>(rx0);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-                const int rx = rx0 + i;
-                const cx<T> z = zl[min(rx, H)];
-                o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
+                for (int i = 0; i < VEC; ++i) o.v[i] = (r & 1) ? zp[i].y : zp[i].x;
+            } else {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    const int rx = rx0 + i;
+                    const cx<T> z = zl[row_slot<T, LOGNX, LOGE>(min(rx, H))];
+                    o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
+                }
             }
-            lh_u4 *op = reinterpret_cast<lh_u4 *>(dst + ((size_t)tile * g.HyS + ky) * Ce + h * VEC);
+            const int off = ((tile * g.HyS + ky) * Ce + h * VEC) * (int)sizeof(T);
             if (acc) {  // add this band to the earlier ones
-                const Vec16<T> old = __builtin_bit_cast(Vec16<T>, *op);
+                const Vec16<T> old = __builtin_bit_cast(Vec16<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
 #pragma unroll
                 for (int i = 0; i < VEC; ++i) o.v[i] += old.v[i];
-                *op = __builtin_bit_cast(lh_u4, o);
-            } else {
-                *op = __builtin_bit_cast(lh_u4, o);
             }
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(lh_u4, o), rs, off, 0, 0);
         }
         __syncthreads();
     }
@@ -1429,9 +1489,12 @@ __device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g
                                                 int out_ny, const T *__restrict__ m2, int acc)
 {
     using F = RegFFT<T, LOGNX, true, 4, kTwLds<T>>;
+    using FP = RegFFTP<T, LOGNX, true, 4, kRowPB>;
+    constexpr bool PADDED = row_padded<T, LOGNX, 4>();
     constexpr int N = F::N, E = F::E, G = F::G;
+    constexpr int LS = row_line_stride<T, LOGNX, 4>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][N] complex; staging [2R][N/2+1] reals
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][LS] complex; staging [2R][N/2+1] reals
     T *stage = reinterpret_cast<T *>(smem_raw);
     const int R = g.e5_R;
     const int tid = threadIdx.x, nthr = R * G;
@@ -1466,8 +1529,12 @@ __device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g
     const int nvec = g.NTe * rows * HV;
     const cx<T> *tw = twx;
     if (sizeof(T) == 4) {
-        cx<T> *twl = lds + R * N;
-        for (int i = tid; i < N; i += nthr) twl[tw_swz(i)] = twx[i];
+        // after the staging area (2R (N/2 + 1) reals < R LS complex)
+        cx<T> *twl = lds + R * LS;
+        if constexpr (PADDED)
+            FP::fill_twiddles(twl, twx, tid, nthr);
+        else
+            for (int i = tid; i < N; i += nthr) twl[tw_swz(i)] = twx[i];
         tw = twl;  // made visible by the barrier after the staging loop
     }
     // 16-byte loads (items ordered half-row, row, tile), independent in
@@ -1513,7 +1580,10 @@ __device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g
         v[s] = mk<T>(stage[(2 * line) * SW + rr], stage[(2 * line + 1) * SW + rr]);
     }
     __syncthreads();
-    F::run(v, lds + line * N, tw, 0, gg, lds_xor_gfast<N, G>(line));
+    if constexpr (PADDED)
+        FP::run(v, lds + line * LS, tw, gg);
+    else
+        F::run(v, lds + line * N, tw, 0, gg, lds_xor_gfast<N, G>(line));
 
     const T sc = (T)scale;
     for (int half = 0; half < 2; ++half) {
@@ -2489,7 +2559,7 @@ static void launch_e1(const Plan &pl, T *spec, int band, int acc, hipStream_t st
     using F = RegFFT<T, LOGNX, false, ilog2_c(e1_elems(LOGNX))>;
     const int np = (g.Hy + 1) / 2;
     const dim3 grid(cdiv(np, g.e1_R), cdiv(g.nS, g.e1_jc));
-    const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);
+    const size_t lds = row_lds_bytes<T, LOGNX, ilog2_c(e1_elems(LOGNX))>(g.e1_R);
     const size_t nk = (size_t)g.nkx * g.nky;
     const double *xi = pl.xi + band * nk;
     if (pl.rho)
@@ -2520,8 +2590,9 @@ static void launch_e5(const Plan &pl, const T *spec, int nplanes, T *out, int on
     using F = RegFFT<T, LOGNX, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
     const int np = (g.Hy + 1) / 2;
-    hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G),
-                       (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, spec, g,
+    const size_t lds = row_lds_bytes<T, LOGNX, 4>(g.e5_R);
+    hipLaunchKernelGGL((k_e5<T, LOGNX, MODE>), dim3(cdiv(np, g.e5_R), nplanes), dim3(g.e5_R * F::G), lds, st,
+                       spec, g,
                        (const cx<T> *)pl.twx, pl.d_src, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out,
                        onx, ony, m2, acc);
 }
@@ -3032,7 +3103,7 @@ static hipError_t even_group_t(const Plan *const *pls, int n, const EvenInst *d,
 #define LH_E1B(LG)                                                                                                  \
     do {                                                                                                            \
         using F = RegFFT<T, LG, false, ilog2_c(e1_elems(LG))>;                                                     \
-        const size_t lds = (size_t)(g.e1_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>);                     \
+        const size_t lds = row_lds_bytes<T, LG, ilog2_c(e1_elems(LG))>(g.e1_R);                                    \
         const dim3 grid(cdiv(np, g.e1_R), ys1, nz);                                                                 \
         if (rho)                                                                                                    \
             hipLaunchKernelGGL((k_e1_batch<T, LG, true>), grid, dim3(g.e1_R * F::G), lds, st, d);                   \
@@ -3094,8 +3165,8 @@ static hipError_t even_group_t(const Plan *const *pls, int n, const EvenInst *d,
     do {                                                                                                            \
         using F = RegFFT<T, LG, true>;                                                                              \
         const dim3 grid(cdiv(np, g.e5_R), nw, nz);                                                                  \
-        hipLaunchKernelGGL((k_e5_batch<T, LG, 0>), grid, dim3(g.e5_R * F::G),                                       \
-                           (size_t)(g.e5_R + (sizeof(T) == 4 ? 1 : 0)) * F::N * sizeof(cx<T>), st, d);              \
+        const size_t lds = row_lds_bytes<T, LG, 4>(g.e5_R);                                                         \
+        hipLaunchKernelGGL((k_e5_batch<T, LG, 0>), grid, dim3(g.e5_R * F::G), lds, st, d);                          \
     } while (0)
     LH_SWITCH_LOG12(g.logNx, LH_E5B)
 #undef LH_E5B

@@ -211,3 +211,149 @@ __device__ __forceinline__ int lds_xor_gfast(int line)
 }
 
 }  // namespace lh
+
+namespace lh {
+
+// Padded-layout variant of the same transform (FP32 passes whose lines have
+// G >= 2^PB threads).  Element x of a line sits at x + (x >> PB) of its LDS
+// buffer.  The index a thread reads or writes in a pass splits into a part
+// that depends only on its g and a part fixed at compile time (butterfly u,
+// element s) whose bits never carry across bit PB when added, so the padded
+// address is a per-thread base plus an immediate offset: the exchanges cost
+// no per-element address arithmetic.  One padding slot per 2^PB elements
+// spreads the stride-r writes of a pass over the LDS banks.
+//
+// Twiddles come from a per-pass table (fill_twiddles): pass t >= 1 (radix r,
+// sub-length p) holds exp(-+2 pi i s k / (p r)) for k < min(p, G),
+// 1 <= s < r at tw_off(t) + k (r - 1) + s - 1.  A thread's k is (g mod p)
+// plus a compile-time multiple of G, so these reads are base plus immediate
+// too, and r - 1 is odd, so lanes with different k fall into different banks.
+// Only the last pass can have p > G (then p r = N); its butterflies with
+// k = g + u G take row g times the constant exp(-+2 pi i s u / E), which keeps
+// the table near N / E + N / 8 entries.
+// a * exp(-+2 pi i m / 16) (forward: minus sign); m is a constant after
+// unrolling, so the branches fold away.
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot16(cx<T> a, int m)
+{
+    m &= 15;
+    if (m == 0) return a;
+    if (m == 4) return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+    if (m == 8) return mk<T>(-a.x, -a.y);
+    if (m == 12) return INV ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+    const T c = (T)cos16(m), s = (T)sin16(m);
+    return INV ? mk<T>(a.x * c - a.y * s, a.y * c + a.x * s) : mk<T>(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+template <typename T, int LOGN, bool INV, int LOGE_MAX, int PB>
+struct RegFFTP {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int LOGE = LOGN < LOGE_MAX ? LOGN : LOGE_MAX;
+    static constexpr int E = 1 << LOGE;
+    static constexpr int G = N / E;
+    static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
+    static_assert(G >= (1 << PB), "the padded layout needs at least 2^PB threads per line");
+    // LDS elements of one line
+    static constexpr int LINE = N + (N >> PB);
+
+    __host__ __device__ static constexpr int pad(int x) { return x + (x >> PB); }
+    __host__ __device__ static constexpr int log_radix(int t) { return LOGN - t * LOGE < LOGE ? LOGN - t * LOGE : LOGE; }
+    // table rows of pass t: k < min(p, G)
+    __host__ __device__ static constexpr int rows(int t) { return (1 << (t * LOGE)) < G ? (1 << (t * LOGE)) : G; }
+    // offset of pass t's twiddles in the table; tw_off(NPASS) is its length
+    __host__ __device__ static constexpr int tw_off(int t)
+    {
+        int off = 0;
+        for (int u = 1; u < t; ++u) off += rows(u) * ((1 << log_radix(u)) - 1);
+        return off;
+    }
+    static constexpr int TWN = tw_off(NPASS);
+
+    // Build the per-pass table at dst from tw[x] = exp(-2 pi i x / N).  Every
+    // thread of the block calls it; no barrier (the caller orders it before
+    // the first pass that reads it).
+    __device__ static void fill_twiddles(cx<T> *dst, const cx<T> *__restrict__ tw, int tid, int nthr)
+    {
+#pragma unroll
+        for (int t = 1; t < NPASS; ++t) {
+            const int lr = log_radix(t), lp = t * LOGE;
+            const int r = 1 << lr, items = rows(t) << lr;
+            const int sh = LOGN - lp - lr;
+            cx<T> *d = dst + tw_off(t);
+            for (int i = tid; i < items; i += nthr) {
+                const int s = i & (r - 1), k = i >> lr;
+                if (s) d[k * (r - 1) + s - 1] = tw[(s * k) << sh];
+            }
+        }
+    }
+
+    template <int LOGR, int LOGP>
+    __device__ static __forceinline__ void pass(cx<T> *v, cx<T> *buf, const cx<T> *tw, int g)
+    {
+        constexpr int r = 1 << LOGR;
+        constexpr int p = 1 << LOGP;
+        constexpr int q = E / r;
+        constexpr int stride = N / r;
+        constexpr bool first = LOGP == 0;
+        constexpr bool last = LOGP + LOGR == LOGN;
+        cx<T> w[E];
+        if constexpr (first) {
+#pragma unroll
+            for (int u = 0; u < q; ++u)
+#pragma unroll
+                for (int s = 0; s < r; ++s) w[u * r + s] = v[u + s * q];
+        } else {
+            const cx<T> *rb = buf + pad(g);
+#pragma unroll
+            for (int u = 0; u < q; ++u)
+#pragma unroll
+                for (int s = 0; s < r; ++s) w[u * r + s] = rb[pad(u * G + s * stride)];
+            __syncthreads();
+        }
+        const cx<T> *tb = tw + tw_off(LOGP / LOGE) + (g & (p - 1)) * (r - 1);
+        cx<T> *wb = buf + pad(((g >> LOGP) << (LOGP + LOGR)) + (g & (p - 1)));
+#pragma unroll
+        for (int u = 0; u < q; ++u) {
+            if constexpr (!first) {
+#pragma unroll
+                for (int s = 1; s < r; ++s) {
+                    cx<T> tws;
+                    if constexpr (p <= G) {
+                        tws = twid<T, INV>(tb, s - 1);
+                    } else {
+                        // k = g + u G: row g turned by exp(-+2 pi i s u G / N)
+                        static_assert(LOGP + LOGR == LOGN && E <= 16, "p > G only in the last pass");
+                        tws = rot16<T, INV>(twid<T, INV>(tb, s - 1), s * u * (16 / E));
+                    }
+                    w[u * r + s] = cmul(w[u * r + s], tws);
+                }
+            }
+            rdft<T, r, INV>(w + u * r);
+            if constexpr (last) {
+#pragma unroll
+                for (int s = 0; s < r; ++s) v[u + s * q] = w[u * r + s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < r; ++s) wb[pad((((u * G) >> LOGP) << (LOGP + LOGR)) + s * p)] = w[u * r + s];
+            }
+        }
+        if constexpr (!last) __syncthreads();
+    }
+
+    template <int T_>
+    __device__ static __forceinline__ void passes(cx<T> *v, cx<T> *buf, const cx<T> *tw, int g)
+    {
+        if constexpr (T_ < NPASS) {
+            constexpr int LOGP = T_ * LOGE;
+            constexpr int LOGR = (LOGN - LOGP) < LOGE ? (LOGN - LOGP) : LOGE;
+            pass<LOGR, LOGP>(v, buf, tw, g);
+            passes<T_ + 1>(v, buf, tw, g);
+        }
+    }
+
+    // Same entry and exit convention as RegFFT::run; buf holds LINE elements
+    // of this line, tw the per-pass table.
+    __device__ static __forceinline__ void run(cx<T> *v, cx<T> *buf, const cx<T> *tw, int g) { passes<0>(v, buf, tw, g); }
+};
+
+}  // namespace lh
