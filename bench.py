@@ -438,6 +438,36 @@ def bench_grid_2049(LH, W, torch, steps=2):
     return res
 
 
+def bench_copy_rates(torch, gib=4, reps=10):
+    """Event-timed rates of plain device streams over `gib` GiB of FP32: a fill (writes
+    only), a copy (one read and one write per byte moved; both counted) and a sum (reads
+    only, torch's reduction).  They are the rates a stream of each kind reaches on this
+    memory system, the measure beside which a pass's GB/s is read."""
+    n = (gib << 30) // 4
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("fill", lambda: x.fill_(1.0), 4 * n), ("copy", lambda: y.copy_(x), 8 * n),
+                             ("sum", lambda: x.sum(), 4 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = {"ms": ms, "bytes": nbytes, "TB/s": nbytes / ms / 1e9}
+        print("bench: %s of %d GiB: %.3f ms, %.2f TB/s" % (name, gib, ms, nbytes / ms / 1e9), file=sys.stderr,
+              flush=True)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -471,6 +501,9 @@ def main():
                     help="only time the extended-zone epilogues (for profiling them on their own)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--copy-rates", action="store_true",
+                    help="only time a plain 4 GiB device fill, copy and sum (the HBM rates plain streams "
+                         "reach, beside which the FFT passes are read)")
     args = ap.parse_args()
     if args.general:
         os.environ["LINDHARD_SYMMETRY"] = "off"
@@ -497,6 +530,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
+    if args.copy_rates:
+        print(json.dumps({"copy_rates": bench_copy_rates(torch)}), flush=True)
         return
     if args.epilogues_only:
         print(json.dumps({"epilogues": bench_epilogues(LH, W, torch)}), flush=True)
