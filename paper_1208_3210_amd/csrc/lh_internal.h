@@ -70,7 +70,7 @@ struct Geo {
     // tiles of 16, nT of them; chunk c of tile t reads the B set u = t - c + U0;
     // P' at LDS position 16 + a + offP (a0 + offP = 15), u <= umax, c <= cmax;
     // nAst / nHst values staged, rows of PSP / PSH floats (LP / LH used);
-    // e3q_W waves of 16 points per block
+    // e3q_W: the autotuner label TR / 16 (the rank-1 window block shape is fixed)
     int e3q_ok, e3q_nT, e3q_U0, e3q_a0, e3q_offP, e3q_umax, e3q_cmax, e3q_LP, e3q_LH, e3q_PSP, e3q_PSH;
     int e3q_nAst, e3q_nHst, e3q_W;
     int e3q_big;              // offsets past 4 GiB: 64-bit addressing

@@ -19,7 +19,11 @@
 // P'[a0 + 16 u + 4 j - s] with u = t - c + U0 (set B_u, per lane j), so that a
 // B set serves tile t at chunk c and tile t + 1 at chunk c + 1.  T tiles are
 // processed together: each chunk loads one A set (shared by the T tiles) and one
-// new B set into a ring of T sets, so LDS delivers half a value per matrix op.
+// new B set into a ring of T sets, so LDS delivers 2 / T values per matrix op.
+// T = 2 with four waves per block (about 120 registers: four waves per SIMD)
+// measured faster than T = 4 with two (half the LDS reads per product, but
+// about 220 registers and two waves per SIMD): 1.05 against 1.18 ms at
+// 2048^2 x 512 x 256.
 // The 4 x 4 x 1 operations share the vector unit's issue: every vector
 // instruction in the loop costs matrix-core time, so the loop holds none but
 // the folds.
@@ -49,9 +53,30 @@ __device__ __forceinline__ f4v mfma4x4(float a, float b, f4v c)
 }
 
 constexpr int kPoints = 16;   // real-space points per block (one per MFMA block)
-constexpr int kWaves = 2;     // waves per block, sharing the staged points
-constexpr int kTiles = 4;     // lag tiles processed together (T), B sets in the ring
+constexpr int kWaves = 4;     // waves per block, sharing the staged points
+constexpr int kTiles = 2;     // lag tiles processed together (T), B sets in the ring
 constexpr int kFoldChunks = 8;  // chunks (16 products each) summed in FP32 between folds (a multiple of T)
+static_assert(kTiles >= 2 && kTiles % 2 == 0 && kFoldChunks % kTiles == 0, "ring phases alternate the A sets");
+
+// f(integral_constant<I>) for I = 0 .. N-1, and for the one I equal to v
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_switch(int v, F &&f)
+{
+    if constexpr (I < N) {
+        if (v == I)
+            f(std::integral_constant<int, I>{});
+        else
+            static_switch<N, I + 1>(v, f);
+    }
+}
 
 // Launch index -> logical block: the blocks of one XCD (launch index mod 8)
 // take one contiguous range, so that neighbouring blocks (whose rows share
@@ -79,12 +104,12 @@ __device__ __forceinline__ f4v buf_load4(__amdgpu_buffer_rsrc_t r, unsigned off)
     return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
 
-// One block: 16 points staged in LDS by both waves; the tile groups are then
-// split between the waves, wave 0 taking the groups g with g mod 4 in {0, 3}
-// and wave 1 those in {1, 2} (group g has about 4 (g + 1) chunks, so the two
-// shares are equal when the group count is a multiple of four).  Two blocks'
-// waves share each SIMD, so one block's staging and operand loads overlap
-// another's products.
+// One block: 16 points staged in LDS by all its waves; the tile groups are
+// then dealt out to the W waves and back (groups g with g mod 2W = w or
+// 2W - 1 - w go to wave w): group g has about T (g + 1) chunks, so the shares
+// are equal when the group count is a multiple of 2W.  Several blocks' waves
+// share each SIMD, so one block's staging and operand loads overlap another's
+// products.
 // BIG: the staged slice ranges or the output reach past 4 GiB of byte
 // offsets, so the block uses 64-bit addresses (flat loads and stores) instead
 // of buffer descriptors.
@@ -178,8 +203,10 @@ __device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
     const unsigned ob0 = (unsigned)((p0 + b) * 4) + (unsigned)(4 * qd) * sl4;
 
     for (int gi = 0; gi < G; ++gi) {
-        const int gm = gi & 3;
-        if ((wave == 0) != (gm == 0 || gm == 3)) continue;
+        // groups dealt out and back (0, 1, .., W-1, W-1, .., 0, ...): the work of a
+        // group grows with its lags, so every wave gets a balanced share
+        const int gm = gi % (2 * kWaves);
+        if ((gm < kWaves ? gm : 2 * kWaves - 1 - gm) != wave) continue;
         const int t0 = kTiles * gi;
         float sum[kTiles][4], cmp[kTiles][4];
 #pragma unroll
@@ -226,9 +253,6 @@ __device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
                     acc[k] = mfma4x4(A[s], ring[(k - r + kTiles) % kTiles][(15 - s) >> 2][(15 - s) & 3], acc[k]);
         };
         using I0 = std::integral_constant<int, 0>;
-        using I1 = std::integral_constant<int, 1>;
-        using I2 = std::integral_constant<int, 2>;
-        using I3 = std::integral_constant<int, 3>;
         auto fold = [&]() {
 #pragma unroll
             for (int k = 0; k < kTiles; ++k) {
@@ -243,33 +267,26 @@ __device__ __forceinline__ void e3q_body(float *__restrict__ spec, const Geo &g)
         int c = cf, nbody = 0;
         loadA(cf, Ab[0]);  // phase 0 of the first chunk
         for (; c + kTiles - 1 <= cm; c += kTiles) {
-            chunk(I0{}, c, I0{});
-            chunk(I1{}, c + 1, I0{});
-            chunk(I2{}, c + 2, I0{});
-            chunk(I3{}, c + 3, I0{});
+            static_for<kTiles>([&](auto R) { chunk(R, c + decltype(R)::value, I0{}); });
             if ((++nbody & (kFoldChunks / kTiles - 1)) == 0) fold();
         }
-        // the remaining 0 .. 3 chunks of the full part (ring phase 0 after
+        // the remaining 0 .. T-1 chunks of the full part (ring phase 0 after
         // whole bodies), then the tail at the phase where they stop
         const int rem = max(0, cm - c + 1);
-        if (rem > 0) chunk(I0{}, c, I0{});
-        if (rem > 1) chunk(I1{}, c + 1, I0{});
-        if (rem > 2) chunk(I2{}, c + 2, I0{});
+        static_for<kTiles - 1>([&](auto R) {
+            if (rem > decltype(R)::value) chunk(R, c + decltype(R)::value, I0{});
+        });
         const int ct = c + rem;  // first tail chunk (t0 + U0 + 1 unless clipped)
-        auto tail = [&](auto P) {
-            constexpr int ph = decltype(P)::value;
-            if (ct <= cl) chunk(std::integral_constant<int, ph>{}, ct, I1{});
-            if (ct + 1 <= cl) chunk(std::integral_constant<int, ph + 1>{}, ct + 1, I2{});
-            if (ct + 2 <= cl) chunk(std::integral_constant<int, ph + 2>{}, ct + 2, I3{});
-        };
-        // (cf <= t0 + U0 always, so a tail, if any, starts at t0 + U0 + 1)
+        // (cf <= t0 + U0 always, so a tail, if any, starts at t0 + U0 + 1);
+        // tail chunk i leaves out the tiles k <= i, which are past their last chunk
         if (ct <= cl) {
-            switch (rem & 3) {
-            case 0: tail(I0{}); break;
-            case 1: tail(I1{}); break;
-            case 2: tail(I2{}); break;
-            default: tail(I3{}); break;
-            }
+            static_switch<kTiles>(rem, [&](auto P) {
+                constexpr int ph = decltype(P)::value;
+                static_for<kTiles - 1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if (ct + i <= cl) chunk(std::integral_constant<int, ph + i>{}, ct + i, std::integral_constant<int, i + 1>{});
+                });
+            });
         }
         fold();
         // every input of these points is in LDS, so the slices may be
