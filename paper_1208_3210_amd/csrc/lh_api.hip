@@ -384,6 +384,12 @@ lindhard_status plan_describe(const lindhard_problem *p, Plan &pl)
         };
         g.e1_R = rows_per_block(e1_elems(g.logNx));
         g.e5_R = rows_per_block(16);
+        if (!g.fp64 && g.logNx >= 10 && g.logNx <= 11) {
+            // FP32 rows of 1024 and 2048 points (padded engine): kE5MaxThreads per block
+            const int Gx = p->nkx / 16;
+            g.e5_R = std::max(1, std::min(kE5MaxThreads / Gx, 1 << ilog2(np)));
+            if ((1 << ilog2(np)) > np) g.e5_R = std::min(g.e5_R, 1 << (ilog2(np) - 1));
+        }
         {
             const long blocks = (np + g.e1_R - 1) / g.e1_R;
             long jc = (blocks * std::max(g.nS, 1)) / 4096;

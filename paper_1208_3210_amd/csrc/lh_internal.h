@@ -91,6 +91,11 @@ struct Geo {
 constexpr int kE1Elems = 8;
 // ... except on 4096-point rows, where eight would take 512 threads per line
 constexpr int e1_elems(int logn) { return logn >= 12 ? 16 : kE1Elems; }
+// Threads per block of the last even row pass: up to 512 (FP32 rows of 1024
+// and 2048 points take four lines per block: with the padded engine the
+// block's lines and twiddle table fit twice per CU, sixteen waves against the
+// twelve that blocks of two lines give)
+constexpr int kE5MaxThreads = 512;
 // Threads per block of the column passes: up to 512, 1024 for 4096-point
 // columns (one tile of C lines of 256 threads each)
 constexpr int col_threads(int logn) { return logn >= 12 ? 1024 : 512; }

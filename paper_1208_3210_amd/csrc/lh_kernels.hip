@@ -1624,7 +1624,7 @@ __device__ __forceinline__ void e5_body(const T *__restrict__ spec, const Geo &g
 }
 
 template <typename T, int LOGNX, int MODE>
-__global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
+__global__ void __launch_bounds__(kE5MaxThreads) k_e5(const T *__restrict__ spec, Geo g, const cx<T> *__restrict__ twx,
                                                 const PlaneSrc *__restrict__ psrc, double scale, int zx, int zy,
                                                 int ff, double ffs, const double2 *__restrict__ ffx,
                                                 const double2 *__restrict__ ffy, T *__restrict__ out, int out_nx,
@@ -1634,7 +1634,7 @@ __global__ void __launch_bounds__(kThreads) k_e5(const T *__restrict__ spec, Geo
 }
 // Batched P5 (extended output planes): instance blockIdx.z, its omegas
 template <typename T, int LOGNX, int MODE>
-__global__ void __launch_bounds__(kThreads) k_e5_batch(const EvenInst *__restrict__ in)
+__global__ void __launch_bounds__(kE5MaxThreads) k_e5_batch(const EvenInst *__restrict__ in)
 {
     const EvenInst &d = in[blockIdx.z];
     const Geo g = d.g;
