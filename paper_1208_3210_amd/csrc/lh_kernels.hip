@@ -787,6 +787,31 @@ __device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo
     const int rows = 2 * R, logRows = 1 + __builtin_ctz(R);
     constexpr int VEC = 16 / sizeof(T), HV = 32 / 16, logHV = 1;  // 16-byte pieces of a 32-byte tile row
     const int nvec = g.NTe * rows * HV;
+    // Output items (VEC consecutive rx of one output row, 16 bytes; items
+    // ordered half-row, row, tile so that a block writes whole tiles).  A
+    // thread's items are the same in every slice, so they are decoded once:
+    // LDS slot of the first value, byte offset in the slice, which row of the
+    // packed pair, and whether all VEC values lie in [0, nkx/2] (only the last
+    // tile's items do not).  nvec / (R G) <= 2 E / Ce + 4 E / N.
+    constexpr int MAXIT = 2 * E / (32 / (int)sizeof(T)) + 4 * E / N + 1;
+    int islot[MAXIT], ioff[MAXIT], irx[MAXIT];
+    bool iodd[MAXIT], ifull[MAXIT];
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+        const int it = tid + k * R * G;
+        const int h = it & (HV - 1);
+        const int r = (it >> logHV) & (rows - 1);
+        const int tile = (it >> logHV) >> logRows;
+        const int ky = 2 * p0 + r;
+        const int rx0 = tile * Ce + h * VEC;
+        const bool ok = it < nvec && ky < g.Hy;
+        irx[k] = rx0;
+        iodd[k] = (r & 1) != 0;
+        ifull[k] = rx0 + VEC - 1 <= H;
+        // rx0 is a multiple of VEC: no padding slot falls between the VEC values
+        islot[k] = (r >> 1) * LS + row_slot<T, LOGNX, LOGE>(min(rx0, H));
+        ioff[k] = ok ? ((tile * g.HyS + ky) * Ce + h * VEC) * (int)sizeof(T) : -1;
+    }
     for (int j = jbeg; j < jend; ++j) {
         const double ej = emin + (j + 0.5) * deps;
         cx<T> v[E];
@@ -812,34 +837,23 @@ __device__ __forceinline__ void e1_body(const double *__restrict__ xi, const Geo
                 if (gg + s * G <= H) buf[gg + s * G] = v[s];
         }
         __syncthreads();
-        // Each item: VEC consecutive rx of one output row (16 bytes), items
-        // ordered half-row, row, tile so that a block writes whole tiles;
-        // 32-bit offsets into the slice through a buffer descriptor.
+        // 32-bit offsets into the slice through a buffer descriptor
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(spec + (size_t)(j - g.jA) * g.slice_e), 0, (int)(g.slice_e * sizeof(T)), 0x00020000);
-        for (int it = tid; it < nvec; it += R * G) {
-            const int h = it & (HV - 1);
-            const int r = (it >> logHV) & (rows - 1);
-            const int tile = (it >> logHV) >> logRows;
-            const int ky = 2 * p0 + r;
-            if (ky >= g.Hy) continue;
-            const cx<T> *zl = lds + (r >> 1) * LS;
-            const int rx0 = tile * Ce + h * VEC;
+#pragma unroll
+        for (int k = 0; k < MAXIT; ++k) {
+            if (ioff[k] < 0) continue;
+            const cx<T> *zp = lds + islot[k];
             Vec16<T> o;
-            if (rx0 + VEC - 1 <= H) {
-                // rx0 is a multiple of VEC: no padding slot falls between the VEC values
-                const cx<T> *zp = zl + row_slot<T, LOGNX, LOGE>(rx0);
+            if (ifull[k]) {
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) o.v[i] = (r & 1) ? zp[i].y : zp[i].x;
+                for (int i = 0; i < VEC; ++i) o.v[i] = iodd[k] ? zp[i].y : zp[i].x;
             } else {
+                // the last tile: the values past nkx/2 are zero (zp holds rx0 <= nkx/2)
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    const int rx = rx0 + i;
-                    const cx<T> z = zl[row_slot<T, LOGNX, LOGE>(min(rx, H))];
-                    o.v[i] = rx <= H ? ((r & 1) ? z.y : z.x) : (T)0;
-                }
+                for (int i = 0; i < VEC; ++i) o.v[i] = irx[k] + i <= H ? (iodd[k] ? zp[i].y : zp[i].x) : (T)0;
             }
-            const int off = ((tile * g.HyS + ky) * Ce + h * VEC) * (int)sizeof(T);
+            const int off = ioff[k];
             if (acc) {  // add this band to the earlier ones
                 const Vec16<T> old = __builtin_bit_cast(Vec16<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
 #pragma unroll
