@@ -211,6 +211,45 @@ constexpr size_t tw_lds_bytes(int n)
     return sizeof(T) == 4 ? (size_t)n * sizeof(cx<T>) : 0;
 }
 
+// Row passes (the even path's builder and both paths' last row passes)
+// in FP32 use the padded-layout engine (padding period 32) when a line spans
+// whole waves (at least 64 threads); FP64 keeps its twiddles in global memory
+// and the swizzled engine.
+constexpr int kRowPB = 5;
+template <typename T, int LOGN, int LOGE>
+constexpr bool row_padded()
+{
+    return sizeof(T) == 4 && LOGN - LOGE >= 6 && LOGN <= 12;
+}
+// LDS elements between the lines of a row pass
+template <typename T, int LOGN, int LOGE>
+constexpr int row_line_stride()
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::LINE;
+    else
+        return 1 << LOGN;
+}
+// LDS slot of element x of a row-pass line
+template <typename T, int LOGN, int LOGE>
+__device__ __forceinline__ int row_slot(int x)
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::pad(x);
+    else
+        return x;
+}
+// LDS bytes of a row pass with R lines: the lines, then (FP32) the twiddles
+template <typename T, int LOGN, int LOGE>
+size_t row_lds_bytes(int R)
+{
+    if constexpr (row_padded<T, LOGN, LOGE>())
+        return (size_t)(R * row_line_stride<T, LOGN, LOGE>() + RegFFTP<T, LOGN, false, LOGE, kRowPB>::TWN) *
+               sizeof(cx<T>);
+    else
+        return (size_t)(R + (sizeof(T) == 4 ? 1 : 0)) * (1 << LOGN) * sizeof(cx<T>);
+}
+
 // ---------------------------------------------------------------- P1
 // One block: R rows (ky) of the spectral function for jc consecutive energy
 // slices; G = L/E threads per row.  Row kx of length nkx is packed as
@@ -574,9 +613,13 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
                                                 const T *__restrict__ m2, int acc)
 {
     using F = RegFFT<T, LOGL, true, 4, kTwLds<T>>;
+    using FP = RegFFTP<T, LOGL, true, 4, kRowPB>;
+    constexpr bool PADDED = row_padded<T, LOGL, 4>();
     constexpr int L = F::N, E = F::E, G = F::G;
+    // line stride: L + 1 staged values, then the transform's line (padded: LINE > L + 1)
+    constexpr int LS = PADDED ? row_line_stride<T, LOGL, 4>() : L + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][L + 1]
+    cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);  // [R][LS]
     const int R = g.p5_R, logR = g.p5_logR;
     const int nthr = R * G;
     const int tid = threadIdx.x;
@@ -597,7 +640,21 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         }
         return;
     }
-    const cx<T> *tw = tw_to_lds<T>(twx, lds + R * (L + 1), 2 * L, tid, nthr);
+    // the transform's twiddles (tw) and the split's exp(-2 pi i k / nkx), k < L
+    // (tws): with the padded engine the per-pass tables, then the split table
+    // in natural order (made visible by the barrier after the staging loop);
+    // otherwise one swizzled table of nkx values serving both
+    const cx<T> *tw, *tws;
+    if constexpr (PADDED) {
+        cx<T> *twp = lds + R * LS, *twsl = twp + FP::TWN;
+        FP::fill_twiddles(twp, twx, tid, nthr, 1);
+        for (int i = tid; i < L; i += nthr) twsl[i] = twx[i];
+        tw = twp;
+        tws = twsl;
+    } else {
+        tw = tw_to_lds<T>(twx, lds + R * (L + 1), 2 * L, tid, nthr);
+        tws = tw;
+    }
 
     const int C = g.C, logC = g.logC;
     const cx<T> *src = spec + (size_t)slot * g.slice_elems;
@@ -627,11 +684,11 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
             const int c = it & (C - 1);
             const int r = (it >> logC) & (R - 1);
             const int kk = (it >> (logC + logR)) * C + c;
-            if (it < nin && kk <= L) lds[r * (L + 1) + kk] = v[k];
+            if (it < nin && kk <= L) lds[r * LS + kk] = v[k];
         }
     }
     __syncthreads();
-    cx<T> *xb = lds + row * (L + 1);
+    cx<T> *xb = lds + row * LS;
     cx<T> v[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
@@ -640,11 +697,15 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
         const cx<T> XL = cconj(xb[L - k]);
         const cx<T> A = cadd(Xk, XL);
         const cx<T> D = csub(Xk, XL);
-        const cx<T> wD = cmul(cconj(tw[kTwLds<T> ? tw_swz(k) : k]), D);  // e^{+2 pi i k / nkx} D
+        const cx<T> wk = PADDED ? tws[k] : tws[kTwLds<T> ? tw_swz(k) : k];
+        const cx<T> wD = cmul(cconj(wk), D);  // e^{+2 pi i k / nkx} D
         v[s] = cadd(A, mk<T>(-wD.y, wD.x));      // A + i w D
     }
     __syncthreads();
-    F::run(v, xb, tw, 1, gg, lds_xor_gfast<L, G>(row));
+    if constexpr (PADDED)
+        FP::run(v, xb, tw, gg);
+    else
+        F::run(v, xb, tw, 1, gg, lds_xor_gfast<L, G>(row));
 
     const T sc = (T)scale;
     const int qy = qy0 + row;
@@ -696,44 +757,6 @@ __global__ void __launch_bounds__(kThreads) k_p5(const cx<T> *__restrict__ spec,
 // packed as one complex line z = a + i b; its full-length FFT is X_a + i X_b
 // with X_a, X_b real, so the real and imaginary parts separate exactly.  Only
 // rx in [0, nkx/2] and ry in [0, nky/2] are stored (see Geo).
-
-// Row passes of the even path (P1, P5) in FP32 use the padded-layout engine
-// (padding period 32) when a line spans whole waves (at least 64 threads);
-// FP64 keeps its twiddles in global memory and the swizzled engine.
-constexpr int kRowPB = 5;
-template <typename T, int LOGN, int LOGE>
-constexpr bool row_padded()
-{
-    return sizeof(T) == 4 && LOGN - LOGE >= 6 && LOGN <= 12;
-}
-// LDS elements between the lines of a row pass
-template <typename T, int LOGN, int LOGE>
-constexpr int row_line_stride()
-{
-    if constexpr (row_padded<T, LOGN, LOGE>())
-        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::LINE;
-    else
-        return 1 << LOGN;
-}
-// LDS slot of element x of a row-pass line
-template <typename T, int LOGN, int LOGE>
-__device__ __forceinline__ int row_slot(int x)
-{
-    if constexpr (row_padded<T, LOGN, LOGE>())
-        return RegFFTP<T, LOGN, false, LOGE, kRowPB>::pad(x);
-    else
-        return x;
-}
-// LDS bytes of a row pass with R lines: the lines, then (FP32) the twiddles
-template <typename T, int LOGN, int LOGE>
-size_t row_lds_bytes(int R)
-{
-    if constexpr (row_padded<T, LOGN, LOGE>())
-        return (size_t)(R * row_line_stride<T, LOGN, LOGE>() + RegFFTP<T, LOGN, false, LOGE, kRowPB>::TWN) *
-               sizeof(cx<T>);
-    else
-        return (size_t)(R + (sizeof(T) == 4 ? 1 : 0)) * (1 << LOGN) * sizeof(cx<T>);
-}
 
 // P1 (even): R row pairs (ky = 2p, 2p+1, ky <= nky/2) for jc slices.
 // FP32: at least four waves per SIMD (with the momentum-density weights the
@@ -2561,9 +2584,13 @@ static void launch_p5(const Plan &pl, const cx<T> *spec, int nplanes, T *out, in
     const Geo &g = pl.g;
     using F = RegFFT<T, LOGL, true>;
     const int ff = pl.p.ff_kind != LINDHARD_FF_NONE;
-    hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G),
-                       (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N), st, spec, g, (const cx<T> *)pl.twx, pl.d_src,
-                       pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx, ony, m2, acc);
+    // the padded engine: lines, per-pass tables and the L split twiddles
+    const size_t lds = row_padded<T, LOGL, 4>()
+                           ? row_lds_bytes<T, LOGL, 4>(g.p5_R) + F::N * sizeof(cx<T>)
+                           : (size_t)g.p5_R * (F::N + 1) * sizeof(cx<T>) + tw_lds_bytes<T>(2 * F::N);
+    hipLaunchKernelGGL((k_p5<T, LOGL, MODE>), dim3(g.nky / g.p5_R, nplanes), dim3(g.p5_R * F::G), lds, st, spec, g,
+                       (const cx<T> *)pl.twx, pl.d_src, pl.scale, pl.zx, pl.zy, ff, pl.ff_s, pl.ffx, pl.ffy, out, onx,
+                       ony, m2, acc);
 }
 
 template <typename T, int LOGNX>

@@ -269,16 +269,17 @@ struct RegFFTP {
     }
     static constexpr int TWN = tw_off(NPASS);
 
-    // Build the per-pass table at dst from tw[x] = exp(-2 pi i x / N).  Every
-    // thread of the block calls it; no barrier (the caller orders it before
-    // the first pass that reads it).
-    __device__ static void fill_twiddles(cx<T> *dst, const cx<T> *__restrict__ tw, int tid, int nthr)
+    // Build the per-pass table at dst from tw[x] = exp(-2 pi i x / (N << twsh)).
+    // Every thread of the block calls it; no barrier (the caller orders it
+    // before the first pass that reads it).
+    __device__ static void fill_twiddles(cx<T> *dst, const cx<T> *__restrict__ tw, int tid, int nthr,
+                                         int twsh = 0)
     {
 #pragma unroll
         for (int t = 1; t < NPASS; ++t) {
             const int lr = log_radix(t), lp = t * LOGE;
             const int r = 1 << lr, items = rows(t) << lr;
-            const int sh = LOGN - lp - lr;
+            const int sh = LOGN - lp - lr + twsh;
             cx<T> *d = dst + tw_off(t);
             for (int i = tid; i < items; i += nthr) {
                 const int s = i & (r - 1), k = i >> lr;
